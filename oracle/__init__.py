@@ -1,0 +1,362 @@
+"""FP64 CPU reference (oracle) for the CPR-GMRES solve.
+
+TEST INFRASTRUCTURE ONLY: imported by `tests/`, by `__graft_entry__.smoke()`
+and by the CPU-baseline leg of `bench.py`, and by nothing else.  The HIP
+library never imports, links or calls anything here, and nothing here uses
+the HIP library.
+
+The arithmetic lives in plain C (`oracle/*.c`, built with gcc, no FMA
+contraction); this module only marshals numpy arrays through ctypes.
+Every function follows a passage of Liu & Chen, arXiv 1812.03952, cited at
+its C definition.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "liboracle.so")
+_SRC = ["bsr.c", "decouple.c", "amg.c", "cpr.c"]
+
+ABF, QIMPES = 0, 1
+SM_BJ, SM_DILU = 0, 1
+
+
+def build() -> str:
+    """Compile liboracle.so with gcc (always rebuilds)."""
+    cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
+           "-shared", "-o", _SO + ".tmp"] + [os.path.join(_HERE, s) for s in _SRC] + ["-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(_SO + ".tmp", _SO)
+    return _SO
+
+
+_lib = None
+_i32p = np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")
+_f64p = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
+
+
+class AmgOpts(C.Structure):
+    _fields_ = [("theta", C.c_double), ("max_row_sum", C.c_double), ("coarse_n", C.c_int),
+                ("max_levels", C.c_int), ("lu_max", C.c_int), ("coarse_sweeps", C.c_int)]
+
+
+class Info(C.Structure):
+    _fields_ = [("iters", C.c_int), ("cycles", C.c_int), ("status", C.c_int),
+                ("relres", C.c_double)]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO):
+            build()
+        L = C.CDLL(_SO)
+        L.or_nnzb.restype = C.c_int64
+        L.or_nnzb.argtypes = [C.c_int] * 3
+        L.or_pattern.argtypes = [C.c_int] * 3 + [_i32p, _i32p]
+        L.or_assemble.argtypes = [C.c_int] * 3 + [_f64p, C.c_double, C.c_double, _f64p, _f64p, _f64p,
+                                                  C.c_double, C.c_int, _i32p, _f64p,
+                                                  _i32p, _i32p, _f64p]
+        L.or_spmv.argtypes = [C.c_int, _i32p, _i32p, _f64p, _f64p, _f64p]
+        L.or_spmv.restype = None
+        L.or_transpose.argtypes = [C.c_int, _i32p, _i32p, _f64p, _f64p]
+        L.or_decouple.argtypes = [C.c_int, _i32p, _i32p, _f64p, C.c_int, _f64p, _f64p]
+        L.or_extract_pressure.argtypes = [C.c_int64, _f64p, _f64p]
+        L.or_extract_pressure.restype = None
+        L.or_bj_setup.argtypes = [C.c_int, _i32p, _i32p, _f64p, _f64p]
+        L.or_dilu_setup.argtypes = [C.c_int, _i32p, _i32p, _f64p, _f64p]
+        L.or_bj_apply.argtypes = [C.c_int, _f64p, _f64p, _f64p]
+        L.or_bj_apply.restype = None
+        L.or_dilu_apply.argtypes = [C.c_int, _i32p, _i32p, _f64p, _f64p, _f64p, _f64p]
+        L.or_dilu_apply.restype = None
+        L.or_amg_defaults.argtypes = [C.POINTER(AmgOpts)]
+        L.or_amg_defaults.restype = None
+        L.or_amg_setup.argtypes = [C.c_int, _i32p, _i32p, _f64p, C.POINTER(AmgOpts),
+                                   C.POINTER(C.c_int)]
+        L.or_amg_setup.restype = C.c_void_p
+        L.or_amg_nlevels.argtypes = [C.c_void_p]
+        L.or_amg_level_n.argtypes = [C.c_void_p, C.c_int]
+        L.or_amg_level_nnz.argtypes = [C.c_void_p, C.c_int]
+        L.or_amg_level_nnz.restype = C.c_int64
+        L.or_amg_coarsest_is_lu.argtypes = [C.c_void_p]
+        L.or_amg_level_get.argtypes = [C.c_void_p, C.c_int] + [C.c_void_p] * 6
+        L.or_amg_level_get.restype = None
+        L.or_amg_vcycle.argtypes = [C.c_void_p, _f64p, _f64p]
+        L.or_amg_vcycle.restype = None
+        L.or_amg_free.argtypes = [C.c_void_p]
+        L.or_amg_free.restype = None
+        L.or_cpr_setup.argtypes = [C.c_int, _i32p, _i32p, _f64p, C.c_int, C.c_int,
+                                   C.POINTER(AmgOpts), C.POINTER(C.c_int)]
+        L.or_cpr_setup.restype = C.c_void_p
+        L.or_cpr_apply.argtypes = [C.c_void_p, _f64p, _f64p]
+        L.or_cpr_apply.restype = None
+        for nm in ("or_cpr_decoupled", "or_cpr_dinv", "or_cpr_dinv2", "or_cpr_pressure"):
+            getattr(L, nm).argtypes = [C.c_void_p]
+            getattr(L, nm).restype = C.POINTER(C.c_double)
+        L.or_cpr_amg.argtypes = [C.c_void_p]
+        L.or_cpr_amg.restype = C.c_void_p
+        L.or_cpr_free.argtypes = [C.c_void_p]
+        L.or_cpr_free.restype = None
+        L.or_gmres.argtypes = [C.c_int, _i32p, _i32p, _f64p, C.c_void_p, _f64p, _f64p,
+                               C.c_int, C.c_double, C.c_int, C.POINTER(Info), C.c_void_p,
+                               C.c_int]
+        L.or_grad_logk.argtypes = [C.c_int] * 3 + [_f64p, C.c_double, C.c_double, _f64p, _f64p, C.c_int,
+                                                   _i32p, _f64p, _f64p, _f64p, _f64p]
+        _lib = L
+    return _lib
+
+
+def _c(a, dt):
+    return np.ascontiguousarray(a, dtype=dt)
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+def _check(st, what):
+    if st != 0:
+        raise OracleError(f"{what} failed with status {st}")
+
+
+# ---------------------------------------------------------------------------
+class BSR:
+    """Host block-sparse matrix: rp (n+1,), ci (nnzb,), v (nnzb, 4, 4)."""
+
+    def __init__(self, nx, ny, nz, rp, ci, v):
+        self.nx, self.ny, self.nz = nx, ny, nz
+        self.n = nx * ny * nz
+        self.rp = _c(rp, np.int32)
+        self.ci = _c(ci, np.int32)
+        self.v = _c(v, np.float64).reshape(-1, 4, 4)
+
+    @property
+    def nnzb(self):
+        return self.ci.shape[0]
+
+    def with_values(self, v):
+        return BSR(self.nx, self.ny, self.nz, self.rp, self.ci, v)
+
+    def dense(self):
+        n = self.n
+        D = np.zeros((4 * n, 4 * n))
+        rows = np.repeat(np.arange(n), np.diff(self.rp))
+        for p in range(self.nnzb):
+            i, j = rows[p], self.ci[p]
+            D[4 * i:4 * i + 4, 4 * j:4 * j + 4] = self.v[p]
+        return D
+
+
+def pattern(nx, ny, nz):
+    L = lib()
+    n = nx * ny * nz
+    nnzb = L.or_nnzb(nx, ny, nz)
+    rp = np.zeros(n + 1, np.int32)
+    ci = np.zeros(nnzb, np.int32)
+    _check(L.or_pattern(nx, ny, nz, rp, ci), "or_pattern")
+    return rp, ci
+
+
+def assemble(prob, logk=None) -> BSR:
+    """Jacobian of a `synth.Problem` (optionally with another log-permeability)."""
+    L = lib()
+    rp, ci = pattern(prob.nx, prob.ny, prob.nz)
+    v = np.zeros(ci.shape[0] * 16)
+    lk = prob.logk if logk is None else logk
+    _check(L.or_assemble(prob.nx, prob.ny, prob.nz, _c(lk, np.float64), prob.kvkh, prob.tscale,
+                         _c(prob.Mf, np.float64).reshape(-1), _c(prob.Mb, np.float64).reshape(-1),
+                         _c(prob.B, np.float64).reshape(-1), prob.dt,
+                         int(prob.well_cell.shape[0]), _c(prob.well_cell, np.int32),
+                         _c(prob.well_u, np.float64), rp, ci, v), "or_assemble")
+    return BSR(prob.nx, prob.ny, prob.nz, rp, ci, v)
+
+
+def spmv(A: BSR, x):
+    y = np.zeros(4 * A.n)
+    lib().or_spmv(A.n, A.rp, A.ci, A.v.reshape(-1), _c(x, np.float64), y)
+    return y
+
+
+def transpose(A: BSR) -> BSR:
+    vt = np.zeros(A.nnzb * 16)
+    _check(lib().or_transpose(A.n, A.rp, A.ci, A.v.reshape(-1), vt), "or_transpose")
+    return A.with_values(vt)
+
+
+def decouple(A: BSR, method=ABF):
+    vt = np.zeros(A.nnzb * 16)
+    dinv = np.zeros(A.n * 16)
+    _check(lib().or_decouple(A.n, A.rp, A.ci, A.v.reshape(-1), method, vt, dinv), "or_decouple")
+    return A.with_values(vt), dinv.reshape(-1, 4, 4)
+
+
+def extract_pressure(At: BSR):
+    ap = np.zeros(At.nnzb)
+    lib().or_extract_pressure(At.nnzb, At.v.reshape(-1), ap)
+    return ap
+
+
+def bj_setup(At: BSR):
+    d = np.zeros(At.n * 16)
+    _check(lib().or_bj_setup(At.n, At.rp, At.ci, At.v.reshape(-1), d), "or_bj_setup")
+    return d.reshape(-1, 4, 4)
+
+
+def dilu_setup(At: BSR):
+    d = np.zeros(At.n * 16)
+    _check(lib().or_dilu_setup(At.n, At.rp, At.ci, At.v.reshape(-1), d), "or_dilu_setup")
+    return d.reshape(-1, 4, 4)
+
+
+def bj_apply(dinv2, r):
+    z = np.zeros_like(r, dtype=np.float64)
+    lib().or_bj_apply(dinv2.shape[0], _c(dinv2, np.float64).reshape(-1), _c(r, np.float64), z)
+    return z
+
+
+def dilu_apply(At: BSR, dinv2, r):
+    z = np.zeros(4 * At.n)
+    lib().or_dilu_apply(At.n, At.rp, At.ci, At.v.reshape(-1), _c(dinv2, np.float64).reshape(-1),
+                        _c(r, np.float64), z)
+    return z
+
+
+def amg_opts(**kw) -> AmgOpts:
+    o = AmgOpts()
+    lib().or_amg_defaults(C.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+class AMG:
+    """Aggregation AMG hierarchy on a scalar CSR matrix."""
+
+    def __init__(self, rp, ci, a, **opts):
+        L = lib()
+        self._o = amg_opts(**opts)
+        st = C.c_int(0)
+        n = rp.shape[0] - 1
+        self._h = L.or_amg_setup(n, _c(rp, np.int32), _c(ci, np.int32), _c(a, np.float64),
+                                 C.byref(self._o), C.byref(st))
+        self._own = True
+        _check(st.value, "or_amg_setup")
+
+    @classmethod
+    def _borrow(cls, h):
+        self = cls.__new__(cls)
+        self._h = h
+        self._own = False
+        return self
+
+    @property
+    def nlevels(self):
+        return lib().or_amg_nlevels(self._h)
+
+    @property
+    def coarsest_is_lu(self):
+        return bool(lib().or_amg_coarsest_is_lu(self._h))
+
+    def level(self, l):
+        L = lib()
+        n = L.or_amg_level_n(self._h, l)
+        nnz = L.or_amg_level_nnz(self._h, l)
+        rp = np.zeros(n + 1, np.int32); ci = np.zeros(max(nnz, 1), np.int32)
+        a = np.zeros(max(nnz, 1)); d = np.zeros(max(n, 1)); agg = np.zeros(max(n, 1), np.int32)
+        st = np.zeros(max(nnz, 1), np.int32)
+        L.or_amg_level_get(self._h, l, rp.ctypes.data, ci.ctypes.data, a.ctypes.data,
+                           d.ctypes.data, agg.ctypes.data, st.ctypes.data)
+        return dict(n=n, nnz=nnz, rp=rp, ci=ci[:nnz], a=a[:nnz], dl1=d[:n], agg=agg[:n],
+                    strong=st[:nnz])
+
+    def vcycle(self, b):
+        b = _c(b, np.float64)
+        x = np.zeros_like(b)
+        lib().or_amg_vcycle(self._h, b, x)
+        return x
+
+    def __del__(self):
+        if getattr(self, "_own", False) and getattr(self, "_h", None):
+            lib().or_amg_free(self._h)
+            self._h = None
+
+
+class CPR:
+    """Two-stage CPR preconditioner on a block matrix."""
+
+    def __init__(self, A: BSR, method=ABF, smoother=SM_DILU, **amg_kw):
+        L = lib()
+        self.A = A
+        self._o = amg_opts(**amg_kw)
+        st = C.c_int(0)
+        self._h = L.or_cpr_setup(A.n, A.rp, A.ci, A.v.reshape(-1), method, smoother,
+                                 C.byref(self._o), C.byref(st))
+        if st.value != 0:
+            L.or_cpr_free(self._h)
+            self._h = None
+            _check(st.value, "or_cpr_setup")
+
+    def _arr(self, fn, count):
+        p = getattr(lib(), fn)(self._h)
+        return np.ctypeslib.as_array(p, shape=(count,)).copy()
+
+    def decoupled(self) -> BSR:
+        return self.A.with_values(self._arr("or_cpr_decoupled", 16 * self.A.nnzb))
+
+    def dinv(self):
+        return self._arr("or_cpr_dinv", 16 * self.A.n).reshape(-1, 4, 4)
+
+    def dinv2(self):
+        return self._arr("or_cpr_dinv2", 16 * self.A.n).reshape(-1, 4, 4)
+
+    def pressure(self):
+        return self._arr("or_cpr_pressure", self.A.nnzb)
+
+    def amg(self) -> AMG:
+        a = AMG._borrow(lib().or_cpr_amg(self._h))
+        a._keep = self
+        return a
+
+    def apply(self, r):
+        z = np.zeros(4 * self.A.n)
+        lib().or_cpr_apply(self._h, _c(r, np.float64), z)
+        return z
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            lib().or_cpr_free(self._h)
+            self._h = None
+
+
+def gmres(A: BSR, b, M: CPR | None = None, x0=None, restart=30, rtol=1e-8, maxit=300,
+          hist=False):
+    """Flexible GMRES(restart); returns (x, info dict)."""
+    x = np.zeros(4 * A.n) if x0 is None else np.array(x0, dtype=np.float64)
+    info = Info()
+    h = np.zeros(maxit + 1) if hist else None
+    st = lib().or_gmres(A.n, A.rp, A.ci, A.v.reshape(-1), None if M is None else M._h,
+                        _c(b, np.float64), x, restart, rtol, maxit, C.byref(info),
+                        None if h is None else h.ctypes.data, 0 if h is None else h.shape[0])
+    if st < 0:
+        _check(st, "or_gmres")
+    d = dict(iters=info.iters, cycles=info.cycles, status=info.status, relres=info.relres)
+    if hist:
+        d["hist"] = h[:info.iters]
+    return x, d
+
+
+def grad_logk(prob, lam, x, logk=None):
+    g = np.zeros(prob.n)
+    lk = prob.logk if logk is None else logk
+    _check(lib().or_grad_logk(prob.nx, prob.ny, prob.nz, _c(lk, np.float64), prob.kvkh, prob.tscale,
+                              _c(prob.Mf, np.float64).reshape(-1),
+                              _c(prob.Mb, np.float64).reshape(-1),
+                              int(prob.well_cell.shape[0]), _c(prob.well_cell, np.int32),
+                              _c(prob.well_u, np.float64), _c(lam, np.float64),
+                              _c(x, np.float64), g), "or_grad_logk")
+    return g

@@ -1,0 +1,109 @@
+/* oracle.h -- plain, slow FP64 CPU reference for the CPR-GMRES linear solve
+ * of Liu & Chen, "A Scalable Thermal Reservoir Simulator for Giant Models on
+ * Parallel Computers" (arXiv 1812.03952).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library exists to check the HIP library
+ * against the paper's definitions.  It is called by the test suite, by the
+ * graft smoke check and by the CPU-baseline leg of the benchmark, and by
+ * nothing else.  It shares no code, header, table or constant generator with
+ * the HIP library and must never be linked into it.
+ *
+ * Conventions
+ *   - Grid cells are numbered c = i + nx*(j + ny*k), 0-based, i fastest
+ *     (the paper numbers unknowns grid block by grid block, Eq. mat-ja).
+ *   - A block-sparse matrix is CSR over 4x4 blocks: rp[n+1], ci[nnzb]
+ *     (columns ascending within a row), v[16*nnzb] (block k is row-major at
+ *     v + 16*k).  Vectors hold 4 unknowns per cell, unknown 0 = pressure.
+ *   - Every routine works in IEEE double, one operation at a time, in the
+ *     order written; build with -ffp-contract=off so no FMA is formed.
+ *   - Return codes: 0 ok, -1 bad argument, -4 singular block, -5 non-finite.
+ *
+ * Parity status per function is stated at its definition in the .c files.
+ */
+#ifndef RS_ORACLE_H
+#define RS_ORACLE_H
+#include <stdint.h>
+
+#define OR_OK 0
+#define OR_E_ARG (-1)
+#define OR_E_SINGULAR (-4)
+#define OR_E_NONFINITE (-5)
+
+/* ---- grid pattern and assembly (Section "Numerical Methods": transmissibility) */
+int64_t or_nnzb(int nx, int ny, int nz);
+int or_pattern(int nx, int ny, int nz, int *rp, int *ci);
+int or_assemble(int nx, int ny, int nz, const double *logk, double kvkh, double tscale,
+                const double *Mf, const double *Mb, const double *B, double dt,
+                int nw, const int *wcell, const double *wu,
+                const int *rp, const int *ci, double *v);
+
+/* ---- block matrix operations (Section "Linear System", Fig. fig-mv) */
+void or_spmv(int n, const int *rp, const int *ci, const double *v,
+             const double *x, double *y);
+int or_transpose(int n, const int *rp, const int *ci, const double *v, double *vt);
+
+/* ---- decoupling (Section "Decoupling Methods", Eqs. decoupled-eq, decoupled-abf) */
+#define OR_ABF 0
+#define OR_QIMPES 1
+int or_decouple(int n, const int *rp, const int *ci, const double *v, int method,
+                double *vt, double *dinv);
+void or_extract_pressure(int64_t nnzb, const double *vt, double *ap);
+
+/* ---- second stage: block-Jacobi (RAS with zero overlap) and block ILU(0) */
+int or_bj_setup(int n, const int *rp, const int *ci, const double *vt, double *dinv2);
+int or_dilu_setup(int n, const int *rp, const int *ci, const double *vt, double *dinv2);
+void or_bj_apply(int n, const double *dinv2, const double *r, double *z);
+void or_dilu_apply(int n, const int *rp, const int *ci, const double *vt,
+                   const double *dinv2, const double *r, double *z);
+
+/* ---- aggregation AMG on the pressure matrix (Fig. fig-ds-amg-par parameters) */
+typedef struct or_amg or_amg;
+typedef struct {
+  double theta;         /* strength threshold                         */
+  double max_row_sum;   /* rows with |row sum| > this*|a_ii| are weak  */
+  int coarse_n;         /* stop coarsening at or below this many rows  */
+  int max_levels;       /* hierarchy depth limit                       */
+  int lu_max;           /* largest coarsest level solved by dense LU   */
+  int coarse_sweeps;    /* l1-Jacobi sweeps when the coarsest is larger */
+} or_amg_opts;
+void or_amg_defaults(or_amg_opts *o);
+or_amg *or_amg_setup(int n, const int *rp, const int *ci, const double *a,
+                     const or_amg_opts *o, int *status);
+int or_amg_nlevels(const or_amg *h);
+int or_amg_level_n(const or_amg *h, int l);
+int64_t or_amg_level_nnz(const or_amg *h, int l);
+void or_amg_level_get(const or_amg *h, int l, int *rp, int *ci, double *a,
+                      double *dl1, int *agg, int *strong);
+int or_amg_coarsest_is_lu(const or_amg *h);
+void or_amg_vcycle(const or_amg *h, const double *b, double *x);
+void or_amg_free(or_amg *h);
+
+/* ---- two-stage CPR preconditioner (Section "Preconditioners") */
+#define OR_SM_BJ 0
+#define OR_SM_DILU 1
+typedef struct or_cpr or_cpr;
+or_cpr *or_cpr_setup(int n, const int *rp, const int *ci, const double *v,
+                     int method, int smoother, const or_amg_opts *ao, int *status);
+void or_cpr_apply(const or_cpr *M, const double *r, double *z);
+const double *or_cpr_decoupled(const or_cpr *M);
+const double *or_cpr_dinv(const or_cpr *M);
+const double *or_cpr_dinv2(const or_cpr *M);
+const double *or_cpr_pressure(const or_cpr *M);
+const or_amg *or_cpr_amg(const or_cpr *M);
+void or_cpr_free(or_cpr *M);
+
+/* ---- restarted flexible GMRES (Section "Linear Solver") */
+typedef struct {
+  int iters, cycles, status;
+  double relres;        /* true ||b-Ax||/||b|| at exit */
+} or_info;
+int or_gmres(int n, const int *rp, const int *ci, const double *v, const or_cpr *M,
+             const double *b, double *x, int restart, double rtol, int maxit,
+             or_info *info, double *hist, int hist_len);
+
+/* ---- adjoint gradient with respect to log-permeability */
+int or_grad_logk(int nx, int ny, int nz, const double *logk, double kvkh, double tscale,
+                 const double *Mf, const double *Mb, int nw, const int *wcell,
+                 const double *wu, const double *lam, const double *x, double *g);
+
+#endif

@@ -1,0 +1,208 @@
+/* rsolve.h -- C-ABI of librsolve.so: the linear solve inside each Newton step
+ * of a fully implicit thermal reservoir simulator (Liu & Chen, "A Scalable
+ * Thermal Reservoir Simulator for Giant Models on Parallel Computers",
+ * arXiv 1812.03952), on one AMD Instinct MI355X (gfx950).
+ *
+ * The system is A x = b with A the block Jacobian of Eq. mat-ja (Section
+ * "Linear Solver"): unknowns numbered grid block by grid block, 4x4 blocks
+ * (unknowns p, N_w, N_o, T), 7-point pattern of a 3-D Cartesian grid.  The
+ * library decouples it (Section "Decoupling Methods"), builds a two-stage
+ * CPR preconditioner from the pressure sub-matrix and an aggregation AMG
+ * (Section "Preconditioners", Fig. fig-ds-amg-par), and solves with
+ * restarted flexible GMRES.
+ *
+ * Conventions for every call
+ *   - Pointers named d_* are device pointers (any allocator: hipMalloc,
+ *     torch); h_* are host pointers.  Buffers passed in are borrowed for the
+ *     duration of the call only; the library keeps no reference to them.
+ *   - Handles (rs_bsr, rs_dcpl, rs_cpr) are opaque and owned by the library;
+ *     free them with the matching *_destroy.  A handle may be used by one
+ *     host thread at a time.
+ *   - `stream` is a hipStream_t passed as void* (0 = the null stream).  All
+ *     device work is enqueued on it.  Calls that return scalars to the host
+ *     (setup status, solve info) synchronise that stream before returning.
+ *   - Cell c = i + nx*(j + ny*k), 0-based, i fastest.  Block rows follow the
+ *     cell order; in a row the stored columns are ascending:
+ *     c-nx*ny, c-nx, c-1, c, c+1, c+nx, c+nx*ny (those inside the grid).
+ *     Block values are row-major 4x4, vals[16*p + 4*r + s].
+ *   - Vectors hold 4 doubles per cell (unknown 0 is pressure), length 4*n.
+ *   - Errors are returned, never raised or aborted on; rs_status_string()
+ *     names them.  RS_NOT_CONVERGED is not fatal: x holds the last iterate.
+ */
+#ifndef RSOLVE_H
+#define RSOLVE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rs_bsr_s *rs_bsr;
+typedef struct rs_dcpl_s *rs_dcpl;
+typedef struct rs_cpr_s *rs_cpr;
+
+typedef enum {
+  RS_OK = 0,
+  RS_NOT_CONVERGED = 1,
+  RS_E_ARG = -1,        /* invalid argument or pattern                  */
+  RS_E_HIP = -2,        /* a HIP runtime call failed                    */
+  RS_E_NOMEM = -3,      /* device allocation failed                     */
+  RS_E_SINGULAR = -4,   /* a 4x4 block or the coarsest matrix is singular */
+  RS_E_NONFINITE = -5   /* NaN/Inf in the input or during the iteration */
+} rs_status;
+
+#define RS_ABF 0        /* alternate block factorisation, Eq. decoupled-abf */
+#define RS_QIMPES 1     /* quasi-IMPES: pressure row of A_ii^{-1} only      */
+#define RS_SM_BJ 0      /* second stage: block Jacobi (RAS, overlap 0)      */
+#define RS_SM_DILU 1    /* second stage: block ILU(0), natural order        */
+
+typedef struct {
+  int smoother;        /* RS_SM_BJ or RS_SM_DILU (default DILU)                  */
+  double theta;        /* AMG strength threshold (default 0.5, Fig. fig-ds-amg-par) */
+  double max_row_sum;  /* AMG weak-row threshold (default 0.9, same figure)       */
+  int coarse_n;        /* stop coarsening at <= this many rows (default 500)     */
+  int max_levels;      /* AMG depth limit (default 20)                           */
+  int lu_max;          /* largest coarsest level inverted densely (default 2048) */
+  int coarse_sweeps;   /* l1-Jacobi sweeps if the coarsest is larger (default 4) */
+} rs_cpr_opts;
+
+typedef struct {
+  int restart;         /* Krylov dimension per cycle (default 30, max 32)        */
+  double rtol;         /* stop at ||b - A x|| <= rtol ||b|| (default 1e-8)       */
+  int maxit;           /* Arnoldi steps in total (default 300)                   */
+} rs_gmres_opts;
+
+typedef struct {
+  int iters;           /* Arnoldi steps run                                      */
+  int cycles;          /* restart cycles run                                     */
+  int status;          /* rs_status of the solve                                 */
+  double relres;       /* true FP64 ||b - A x|| / ||b|| at exit                  */
+  double est_relres;   /* last rotated-residual estimate |g_{j+1}| / ||b||        */
+  double ms;           /* wall time of the solve on the stream (hipEvents)       */
+} rs_solve_info;
+
+void rs_cpr_opts_default(rs_cpr_opts *o);
+void rs_gmres_opts_default(rs_gmres_opts *o);
+const char *rs_status_string(int status);
+
+/* ---- the five calls of the solve ---------------------------------------- */
+
+/* Ingest a 4x4-block BSR Jacobian (Eq. mat-ja).  bs must be 4 and
+ * nx*ny*nz*... must match: the pattern (d_row_ptr[n+1], d_col_idx[nnzb]) is
+ * validated against the 7-point pattern of the nx x ny x nz grid described
+ * above (RS_E_ARG otherwise).  Values (d_vals, 16*nnzb doubles) are copied
+ * into the library's own device layout; the caller may free its buffers
+ * afterwards.  Non-finite values give RS_E_NONFINITE. */
+rs_status rs_bsr_create(int nx, int ny, int nz, int bs, int64_t nnzb,
+                        const int32_t *d_row_ptr, const int32_t *d_col_idx,
+                        const double *d_vals, void *stream, rs_bsr *out);
+
+/* Replace the values of A (same pattern, caller layout), e.g. at the next
+ * Newton step.  Invalidates the cached transpose used by rs_adjoint_solve;
+ * decouplings and preconditioners built from the old values are not
+ * updated (rebuild them). */
+rs_status rs_bsr_update(rs_bsr A, const double *d_vals, void *stream);
+
+/* Decoupling (D^{-1} A) x = D^{-1} b, Eq. decoupled-eq, computed block row by
+ * block row with Gauss-Jordan elimination and row pivoting (Section
+ * "Decoupling Methods").  method: RS_ABF (D = diag(A_11..A_nn), Eq.
+ * decoupled-abf) or RS_QIMPES (only the pressure row is replaced, by row 0
+ * of A_ii^{-1} A_ij).  prec: 64 or 32, the storage and arithmetic precision
+ * of the decoupled blocks used by the preconditioner; the pressure matrix
+ * used by the AMG setup is always kept in FP64.  A singular diagonal block
+ * (pivot <= 1e-300 or <= 1e-14 max|A_ii|) gives RS_E_SINGULAR. */
+rs_status rs_decouple(rs_bsr A, int method, int prec, void *stream, rs_dcpl *out);
+
+/* Two-stage CPR setup (Section "Preconditioners"): pressure sub-matrix
+ * A_p[i][j] = A~_ij[0][0] ("getting sub-matrix (for CPR)", Section "Linear
+ * Solver"), aggregation-AMG hierarchy on A_p built on the device, and the
+ * second stage (block Jacobi or block ILU(0)) on the decoupled matrix.
+ * o == NULL takes the defaults.  The handle keeps references to A and D:
+ * destroy it before them. */
+rs_status rs_cpr_setup(rs_bsr A, rs_dcpl D, const rs_cpr_opts *o, void *stream,
+                       rs_cpr *out);
+
+/* Solve A x = b with restarted flexible GMRES right-preconditioned by M
+ * (Section "Linear Solver").  d_x holds the initial guess on entry and the
+ * iterate on exit.  o == NULL takes the defaults.  info (host, may be NULL)
+ * receives iterations, cycles and the true FP64 relative residual.  Returns
+ * RS_OK when the true residual meets rtol, RS_NOT_CONVERGED at maxit. */
+rs_status rs_gmres_solve(rs_bsr A, rs_cpr M, const double *d_b, double *d_x,
+                         const rs_gmres_opts *o, rs_solve_info *info, void *stream);
+
+/* Adjoint solve A^T lambda = w (not in the paper; gives dJ/dA = -lambda x^T
+ * for J = w^T x).  Builds on first use and caches, inside A, the block
+ * transpose, its decoupling (method, prec) and its CPR (co); the cache is
+ * dropped by rs_bsr_update.  d_lambda holds the initial guess on entry. */
+rs_status rs_adjoint_solve(rs_bsr A, int method, int prec, const rs_cpr_opts *co,
+                           const double *d_w, double *d_lambda,
+                           const rs_gmres_opts *o, rs_solve_info *info, void *stream);
+
+void rs_bsr_destroy(rs_bsr A);
+void rs_dcpl_destroy(rs_dcpl D);
+void rs_cpr_destroy(rs_cpr M);
+
+/* ---- building blocks of the path, exposed for tests and measurement ----- */
+
+/* y = A x (Fig. fig-mv).  d_x, d_y: 4n doubles, must not alias. */
+rs_status rs_spmv(rs_bsr A, const double *d_x, double *d_y, void *stream);
+
+/* One application of the CPR preconditioner, z = M^{-1} r (FP64 in/out). */
+rs_status rs_cpr_apply(rs_cpr M, const double *d_r, double *d_z, void *stream);
+
+/* Assemble the synthetic Jacobian on the device into caller-layout BSR
+ * values (16*nnzb doubles; pattern as described above), from the seeded
+ * draws: log-permeability d_logk[n], vertical ratio kvkh, transmissibility
+ * constant tscale, face blocks d_Mf, d_Mb [3][n][16], accumulation d_B
+ * [n][16], time step dt, wells d_wcell[nw] (ascending cell ids) with
+ * coefficients d_wu[nw]; d_row_ptr is the pattern's row pointer array.  Face transmissibility is tscale times the
+ * harmonic mean of the directional permeabilities (Section "Numerical
+ * Methods"); A[c][c+e_d] = -T Mf[d][c], A[c+e_d][c] = -T Mb[d][c], and each
+ * diagonal block is B/dt plus the row's T*M terms plus u*k*I at wells. */
+rs_status rs_assemble(int nx, int ny, int nz, const double *d_logk, double kvkh,
+                      double tscale, const double *d_Mf, const double *d_Mb,
+                      const double *d_B, double dt, int nw, const int32_t *d_wcell,
+                      const double *d_wu, const int32_t *d_row_ptr, double *d_vals,
+                      void *stream);
+
+/* Write the 7-point block pattern of an nx x ny x nz grid (row pointers
+ * n+1, column indices nnzb) into device buffers; *h_nnzb (host, may be NULL)
+ * receives the number of stored blocks. */
+rs_status rs_pattern(int nx, int ny, int nz, int32_t *d_row_ptr, int32_t *d_col_idx,
+                     int64_t *h_nnzb, void *stream);
+
+/* d_G[16*nnzb] (caller layout) = -lambda_i x_j^T for every stored block
+ * (i,j): the gradient of J = w^T x with respect to the values of A when
+ * A^T lambda = w. */
+rs_status rs_grad_vals(rs_bsr A, const double *d_lambda, const double *d_x,
+                       double *d_G, void *stream);
+
+/* Chain rule of rs_assemble: d_g[n] = sum over blocks of G : dA/dlogk_c
+ * given d_G = dJ/dA in caller layout (arguments as for rs_assemble). */
+rs_status rs_grad_logk(int nx, int ny, int nz, const double *d_logk, double kvkh,
+                       double tscale, const double *d_Mf, const double *d_Mb,
+                       int nw, const int32_t *d_wcell, const double *d_wu,
+                       const int32_t *d_row_ptr, const double *d_G, double *d_g,
+                       void *stream);
+
+/* ---- inspection (copies to host; synchronise the stream) --------------- */
+
+/* Decoupled blocks in caller layout (16*nnzb doubles, upcast if FP32) and
+ * D^{-1} (16*n doubles); either pointer may be NULL. */
+rs_status rs_dcpl_get(rs_dcpl D, double *h_vals, double *h_dinv);
+/* Number of AMG levels. */
+int rs_cpr_nlevels(rs_cpr M);
+/* Level l of the hierarchy: rows, stored entries, and (any may be NULL)
+ * CSR arrays, FP64 values, l1 diagonal, aggregate of each row (-1 = not
+ * aggregated; the coarsest level has none). */
+rs_status rs_cpr_level(rs_cpr M, int l, int *h_n, int64_t *h_nnz, int32_t *h_rp,
+                       int32_t *h_ci, double *h_a, double *h_dl1, int32_t *h_agg);
+/* Second-stage block inverses (16*n doubles, upcast if FP32). */
+rs_status rs_cpr_smoother_get(rs_cpr M, double *h_dinv2);
+/* One V-cycle on the pressure hierarchy, b -> x (n doubles each, device). */
+rs_status rs_cpr_vcycle(rs_cpr M, const double *d_b, double *d_x, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,746 @@
+// amg.hip -- aggregation AMG for the pressure stage of CPR, set up and
+// applied on the device.
+//
+// The paper solves the pressure sub-problem with one AMG V-cycle using the
+// defaults of Fig. fig-ds-amg-par (strength 0.5, max row sum 0.9, one cycle,
+// two relaxation sweeps per level visit).  This library keeps those
+// parameters and replaces classical coarsening by aggregation, which maps to
+// fine-grained parallel work:
+//   strength   j strongly influences i if -a_ij >= theta * max_{k!=i}(-a_ik);
+//              a row with |sum_j a_ij| > max_row_sum*|a_ii| has none;
+//              symmetrised (an edge if either direction is strong).
+//   roots      distance-2 maximal independent set with fixed priorities
+//              (fmix32 of the index, index in the low word).  Rounds: every
+//              undecided vertex that holds the largest priority among the
+//              undecided vertices within two strength edges, with no root
+//              that close, becomes a root; vertices with a root within two
+//              edges drop out.  With fixed priorities this selects exactly
+//              the set of the sequential greedy visit in priority order
+//              (Blelloch, Fineman & Shun, SPAA 2012), so the result does not
+//              depend on scheduling.
+//   aggregates roots take their strength neighbours; the rest join the
+//              neighbouring first-pass aggregate with the largest |a_ij|,
+//              ties to the lowest id; vertices with no strength edge stay
+//              unaggregated.
+//   Galerkin   A_c = P^T A P for piecewise-constant P, one thread per coarse
+//              row, summing members in increasing fine index and each
+//              member's row in column order.  Only additions are involved, so
+//              coarse matrices are bitwise reproducible.
+//   cycle      l1-Jacobi (d_i = sgn(a_ii) sum_j |a_ij|), one sweep before and
+//              one after the coarse correction; dense FP64 inverse at the
+//              coarsest level.  The pre-smoothed iterate b/d is never stored:
+//              the residual and the post-smoother recompute it on the fly.
+#include "rs_internal.h"
+#include <math.h>
+
+namespace {
+
+enum : uint8_t { ST_UND = 0, ST_ROOT = 1, ST_OUT = 2, ST_ISO = 3 };
+
+__device__ __forceinline__ uint32_t fmix32(uint32_t h) {
+  h ^= h >> 16;
+  h *= 0x85ebca6bu;
+  h ^= h >> 13;
+  h *= 0xc2b2ae35u;
+  h ^= h >> 16;
+  return h;
+}
+__device__ __forceinline__ uint64_t prio(int i, int level) {
+  uint32_t h = fmix32((uint32_t)i + 0x9e3779b9u * (uint32_t)(level + 1));
+  return ((uint64_t)h << 32) | (uint32_t)i;
+}
+
+// ---- scan ------------------------------------------------------------------
+__global__ void k_scan_block(const int32_t *__restrict__ in, int32_t *__restrict__ out,
+                             int32_t *__restrict__ bsum, int64_t n) {
+  __shared__ int32_t s[256];
+  int64_t base = (int64_t)blockIdx.x * 1024 + threadIdx.x * 4;
+  int32_t v[4], tsum = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) { v[k] = (base + k < n) ? in[base + k] : 0; tsum += v[k]; }
+  s[threadIdx.x] = tsum;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    int32_t t = threadIdx.x >= (unsigned)off ? s[threadIdx.x - off] : 0;
+    __syncthreads();
+    s[threadIdx.x] += t;
+    __syncthreads();
+  }
+  int32_t ex = s[threadIdx.x] - tsum;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (base + k < n) out[base + k] = ex;
+    ex += v[k];
+  }
+  if (threadIdx.x == 255) bsum[blockIdx.x] = s[255];
+}
+
+__global__ void k_scan_add(int32_t *__restrict__ out, const int32_t *__restrict__ boff, int64_t n) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) out[t] += boff[t / 1024];
+}
+
+// out = exclusive scan of in (n entries); *total = sum.  in may equal out.
+rs_status scan_i32(const int32_t *in, int32_t *out, int64_t n, int64_t *total, hipStream_t s) {
+  int64_t nb = (n + 1023) / 1024;
+  if (nb < 1) nb = 1;
+  dbuf bs, bo;
+  RS_TRY(bs.alloc(sizeof(int32_t) * nb));
+  k_scan_block<<<(unsigned)nb, 256, 0, s>>>(in, out, bs.as<int32_t>(), n);
+  RS_HIP(hipGetLastError());
+  if (nb == 1) {
+    int32_t t = 0;
+    RS_HIP(hipMemcpyAsync(&t, bs.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    RS_HIP(hipStreamSynchronize(s));
+    *total = t;
+    return RS_OK;
+  }
+  RS_TRY(bo.alloc(sizeof(int32_t) * nb));
+  RS_TRY(scan_i32(bs.as<int32_t>(), bo.as<int32_t>(), nb, total, s));
+  k_scan_add<<<rs_grid(n), RS_BLOCK, 0, s>>>(out, bo.as<int32_t>(), n);
+  RS_HIP(hipGetLastError());
+  return RS_OK;
+}
+
+// ---- setup kernels -----------------------------------------------------------
+__global__ void k_gather_ap(int64_t m, const int64_t *__restrict__ pos7, const double *__restrict__ ap7,
+                            double *__restrict__ a) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= m) return;
+  int64_t p = pos7[t];
+  if (p >= 0) a[p] = ap7[t];
+}
+
+__global__ void k_strength_dir(int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                               const double *__restrict__ a, double theta, double mrs,
+                               uint8_t *__restrict__ dir) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int p0 = rp[i], p1 = rp[i + 1];
+  double aii = 0.0, nm = 0.0, s = 0.0;
+  for (int p = p0; p < p1; ++p) {
+    double v = a[p];
+    s = s + v;
+    if (ci[p] == i) aii = v;
+    else if (-v > nm) nm = -v;
+  }
+  bool weak = fabs(s) > mrs * fabs(aii) || !(nm > 0.0);
+  double thr = theta * nm;
+  for (int p = p0; p < p1; ++p) dir[p] = (!weak && ci[p] != i && -a[p] >= thr) ? 1 : 0;
+}
+
+__device__ __forceinline__ int find_col(const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                                        int row, int col) {
+  int lo = rp[row], hi = rp[row + 1] - 1;
+  while (lo <= hi) {
+    int mid = (lo + hi) >> 1;
+    int v = ci[mid];
+    if (v == col) return mid;
+    if (v < col) lo = mid + 1; else hi = mid - 1;
+  }
+  return -1;
+}
+
+__global__ void k_strength_sym(int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                               const uint8_t *__restrict__ dir, uint8_t *__restrict__ strong,
+                               uint8_t *__restrict__ state) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int deg = 0;
+  for (int p = rp[i]; p < rp[i + 1]; ++p) {
+    int j = ci[p];
+    uint8_t v = 0;
+    if (j != i) {
+      int q = find_col(rp, ci, j, i);
+      v = dir[p] | (q >= 0 ? dir[q] : (uint8_t)0);
+    }
+    strong[p] = v;
+    deg += v;
+  }
+  state[i] = deg ? ST_UND : ST_ISO;
+}
+
+__device__ __forceinline__ uint64_t keyof(uint8_t st, int v, int level) {
+  return st == ST_ROOT ? ~0ull : (st == ST_UND ? prio(v, level) : 0ull);
+}
+
+__global__ void k_mis_m1(int n, int level, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                         const uint8_t *__restrict__ strong, const uint8_t *__restrict__ state,
+                         uint64_t *__restrict__ m1) {
+  int u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= n) return;
+  uint64_t m = keyof(state[u], u, level);
+  for (int p = rp[u]; p < rp[u + 1]; ++p)
+    if (strong[p]) {
+      int w = ci[p];
+      uint64_t k = keyof(state[w], w, level);
+      m = k > m ? k : m;
+    }
+  m1[u] = m;
+}
+
+__global__ void k_mis_m2(int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                         const uint8_t *__restrict__ strong, const uint64_t *__restrict__ m1,
+                         uint64_t *__restrict__ m2) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  uint64_t m = m1[v];
+  for (int p = rp[v]; p < rp[v + 1]; ++p)
+    if (strong[p]) {
+      uint64_t k = m1[ci[p]];
+      m = k > m ? k : m;
+    }
+  m2[v] = m;
+}
+
+__global__ void k_mis_decide(int n, int level, const uint64_t *__restrict__ m2, uint8_t *__restrict__ state,
+                             int *__restrict__ undecided) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  int left = 0;
+  if (v < n && state[v] == ST_UND) {
+    uint64_t m = m2[v];
+    if (m == ~0ull) state[v] = ST_OUT;
+    else if (m == prio(v, level)) state[v] = ST_ROOT;
+    else left = 1;
+  }
+  // one atomic per wave
+  unsigned long long bal = __ballot(left);
+  if ((threadIdx.x & 63) == 0 && bal) atomicAdd(undecided, __popcll(bal));
+}
+
+__global__ void k_root_flag(int n, const uint8_t *__restrict__ state, int32_t *__restrict__ f) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < n) f[v] = state[v] == ST_ROOT ? 1 : 0;
+}
+
+__global__ void k_agg1(int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                       const uint8_t *__restrict__ strong, const uint8_t *__restrict__ state,
+                       const int32_t *__restrict__ id, int32_t *__restrict__ agg1) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  int g = -1;
+  uint8_t st = state[v];
+  if (st == ST_ROOT) g = id[v];
+  else if (st != ST_ISO)
+    for (int p = rp[v]; p < rp[v + 1]; ++p)
+      if (strong[p] && state[ci[p]] == ST_ROOT) { g = id[ci[p]]; break; }
+  agg1[v] = g;
+}
+
+__global__ void k_agg2(int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                       const uint8_t *__restrict__ strong, const double *__restrict__ a,
+                       const uint8_t *__restrict__ state, const int32_t *__restrict__ agg1,
+                       int32_t *__restrict__ agg, int *__restrict__ bad) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  int g = agg1[v];
+  if (g < 0 && state[v] != ST_ISO) {
+    double bw = -1.0;
+    for (int p = rp[v]; p < rp[v + 1]; ++p) {
+      if (!strong[p]) continue;
+      int ag = agg1[ci[p]];
+      if (ag < 0) continue;
+      double w = fabs(a[p]);
+      if (w > bw || (w == bw && ag < g)) { bw = w; g = ag; }
+    }
+    if (g < 0) atomicOr(bad, 1);     // cannot happen for a maximal distance-2 set
+  }
+  agg[v] = g;
+}
+
+__global__ void k_count_members(int n, const int32_t *__restrict__ agg, int32_t *__restrict__ cnt) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < n && agg[v] >= 0) atomicAdd(&cnt[agg[v]], 1);
+}
+
+__global__ void k_fill_members(int n, const int32_t *__restrict__ agg, const int32_t *__restrict__ mptr,
+                               int32_t *__restrict__ fill, int32_t *__restrict__ mem) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < n && agg[v] >= 0) {
+    int g = agg[v];
+    int k = atomicAdd(&fill[g], 1);
+    mem[mptr[g] + k] = v;
+  }
+}
+
+// atomics fill each member list in arbitrary order: sort it (lists are short)
+__global__ void k_sort_members(int nc, const int32_t *__restrict__ mptr, int32_t *__restrict__ mem) {
+  int I = blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= nc) return;
+  int b = mptr[I], e = mptr[I + 1];
+  for (int x = b + 1; x < e; ++x) {
+    int v = mem[x], y = x - 1;
+    while (y >= b && mem[y] > v) { mem[y + 1] = mem[y]; --y; }
+    mem[y + 1] = v;
+  }
+}
+
+__global__ void k_cand(int nc, const int32_t *__restrict__ mptr, const int32_t *__restrict__ mem,
+                       const int32_t *__restrict__ rp, int32_t *__restrict__ cand) {
+  int I = blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= nc) return;
+  int s = 0;
+  for (int x = mptr[I]; x < mptr[I + 1]; ++x) s += rp[mem[x] + 1] - rp[mem[x]];
+  cand[I] = s;
+}
+
+// Coarse row I: accumulate members' rows into a first-seen list in scratch,
+// then sort the list by column (insertion sort on the short list).
+__global__ void k_galerkin(int nc, const int32_t *__restrict__ mptr, const int32_t *__restrict__ mem,
+                           const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                           const double *__restrict__ a, const int32_t *__restrict__ agg,
+                           const int32_t *__restrict__ off, int32_t *__restrict__ skey,
+                           double *__restrict__ sval, int32_t *__restrict__ cnt) {
+  int I = blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= nc) return;
+  int base = off[I], m = 0;
+  for (int x = mptr[I]; x < mptr[I + 1]; ++x) {
+    int i = mem[x];
+    for (int p = rp[i]; p < rp[i + 1]; ++p) {
+      int J = agg[ci[p]];
+      if (J < 0) continue;
+      int s = 0;
+      while (s < m && skey[base + s] != J) ++s;
+      if (s == m) { skey[base + m] = J; sval[base + m] = 0.0; ++m; }
+      sval[base + s] = sval[base + s] + a[p];
+    }
+  }
+  for (int x = 1; x < m; ++x) {
+    int k = skey[base + x];
+    double v = sval[base + x];
+    int y = x - 1;
+    while (y >= 0 && skey[base + y] > k) { skey[base + y + 1] = skey[base + y]; sval[base + y + 1] = sval[base + y]; --y; }
+    skey[base + y + 1] = k;
+    sval[base + y + 1] = v;
+  }
+  cnt[I] = m;
+}
+
+__global__ void k_galerkin_copy(int nc, const int32_t *__restrict__ off, const int32_t *__restrict__ skey,
+                                const double *__restrict__ sval, const int32_t *__restrict__ crp,
+                                int32_t *__restrict__ cci, double *__restrict__ ca) {
+  int I = blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= nc) return;
+  int b = off[I], o = crp[I], m = crp[I + 1] - crp[I];
+  for (int s = 0; s < m; ++s) { cci[o + s] = skey[b + s]; ca[o + s] = sval[b + s]; }
+}
+
+__global__ void k_set_last(int32_t *__restrict__ p, int64_t idx, int32_t v) { p[idx] = v; }
+
+template <class T>
+__global__ void k_l1diag(int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                         const double *__restrict__ a, T *__restrict__ d) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0, aii = 0.0;
+  for (int p = rp[i]; p < rp[i + 1]; ++p) {
+    s = s + fabs(a[p]);
+    if (ci[p] == i) aii = a[p];
+  }
+  if (s == 0.0) s = 1.0;
+  d[i] = (T)(aii < 0.0 ? -s : s);
+}
+
+__global__ void k_cast_f32(int64_t m, const double *__restrict__ a, float *__restrict__ b) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < m) b[t] = (float)a[t];
+}
+
+__global__ void k_densify(int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                          const double *__restrict__ a, double *__restrict__ G) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double *row = G + (int64_t)i * 2 * n;
+  for (int c = 0; c < 2 * n; ++c) row[c] = (c == n + i) ? 1.0 : 0.0;
+  for (int p = rp[i]; p < rp[i + 1]; ++p) row[ci[p]] = a[p];
+}
+
+// Gauss-Jordan with partial pivoting on [A | I] (n x 2n, row-major), one
+// pivot column per pair of launches.
+__global__ void k_gj_pivot(int n, int k, double *__restrict__ G, int *__restrict__ bad) {
+  __shared__ double sv[256];
+  __shared__ int si[256];
+  int tid = threadIdx.x;
+  double best = -1.0;
+  int bi = k;
+  for (int r = k + tid; r < n; r += blockDim.x) {
+    double v = fabs(G[(int64_t)r * 2 * n + k]);
+    if (v > best) { best = v; bi = r; }
+  }
+  sv[tid] = best; si[tid] = bi;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (tid < s) {
+      if (sv[tid + s] > sv[tid] || (sv[tid + s] == sv[tid] && si[tid + s] < si[tid])) {
+        sv[tid] = sv[tid + s]; si[tid] = si[tid + s];
+      }
+    }
+    __syncthreads();
+  }
+  int piv = si[0];
+  double *rk = G + (int64_t)k * 2 * n, *rpv = G + (int64_t)piv * 2 * n;
+  if (piv != k)
+    for (int c = tid; c < 2 * n; c += blockDim.x) { double t = rk[c]; rk[c] = rpv[c]; rpv[c] = t; }
+  __syncthreads();
+  double pv = rk[k];
+  if (tid == 0 && !(fabs(pv) > 0.0)) atomicOr(bad, 1);
+  double inv = 1.0 / pv;
+  __syncthreads();
+  for (int c = tid; c < 2 * n; c += blockDim.x)
+    if (c != k) rk[c] = rk[c] * inv;
+  __syncthreads();
+  if (tid == 0) rk[k] = 1.0;
+}
+
+__global__ void k_gj_elim(int n, int k, double *__restrict__ G) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t w = 2 * (int64_t)n - (k + 1);
+  if (t >= (int64_t)n * w) return;
+  int r = (int)(t / w);
+  int c = (int)(t - (int64_t)r * w) + k + 1;
+  if (r == k) return;
+  double f = G[(int64_t)r * 2 * n + k];
+  G[(int64_t)r * 2 * n + c] -= f * G[(int64_t)k * 2 * n + c];
+}
+
+__global__ void k_extract_inv(int n, const double *__restrict__ G, double *__restrict__ inv) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)n * n) return;
+  int r = (int)(t / n), c = (int)(t % n);
+  inv[t] = G[(int64_t)r * 2 * n + n + c];
+}
+
+// ---- cycle kernels -----------------------------------------------------------
+// r = b - A (b ./ d): residual after one l1-Jacobi sweep from zero.
+template <class T>
+__global__ __launch_bounds__(256) void k_vc_pre(int n, const int32_t *__restrict__ rp,
+                                                 const int32_t *__restrict__ ci, const T *__restrict__ a,
+                                                 const T *__restrict__ d, const T *__restrict__ b,
+                                                 T *__restrict__ r) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  T s = 0;
+  for (int p = rp[i]; p < rp[i + 1]; ++p) {
+    int j = ci[p];
+    s = fma(a[p], b[j] / d[j], s);
+  }
+  r[i] = b[i] - s;
+}
+
+template <class T>
+__global__ void k_vc_restrict(int nc, const int32_t *__restrict__ mptr, const int32_t *__restrict__ mem,
+                              const T *__restrict__ r, T *__restrict__ bc) {
+  int I = blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= nc) return;
+  T s = 0;
+  for (int x = mptr[I]; x < mptr[I + 1]; ++x) s = s + r[mem[x]];
+  bc[I] = s;
+}
+
+// x = y + (b - A y) ./ d  with  y = b ./ d + P xc  (prolongation then one
+// l1-Jacobi post-sweep).
+template <class T>
+__global__ __launch_bounds__(256) void k_vc_post(int n, const int32_t *__restrict__ rp,
+                                                  const int32_t *__restrict__ ci, const T *__restrict__ a,
+                                                  const T *__restrict__ d, const int32_t *__restrict__ agg,
+                                                  const T *__restrict__ b, const T *__restrict__ xc,
+                                                  T *__restrict__ x) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  T s = 0;
+  for (int p = rp[i]; p < rp[i + 1]; ++p) {
+    int j = ci[p];
+    T yj = b[j] / d[j];
+    int g = agg[j];
+    if (g >= 0) yj = yj + xc[g];
+    s = fma(a[p], yj, s);
+  }
+  T yi = b[i] / d[i];
+  if (agg[i] >= 0) yi = yi + xc[agg[i]];
+  x[i] = yi + (b[i] - s) / d[i];
+}
+
+template <class T>
+__global__ void k_vc_jacobi(int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                            const T *__restrict__ a, const T *__restrict__ d, const T *__restrict__ b,
+                            const T *__restrict__ xin, T *__restrict__ xout, int first) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (first) { xout[i] = b[i] / d[i]; return; }
+  T s = 0;
+  for (int p = rp[i]; p < rp[i + 1]; ++p) s = fma(a[p], xin[ci[p]], s);
+  xout[i] = xin[i] + (b[i] - s) / d[i];
+}
+
+template <class T>
+__global__ void k_to_f64(int n, const T *__restrict__ a, double *__restrict__ b) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = (double)a[i];
+}
+template <class T>
+__global__ void k_from_f64(int n, const double *__restrict__ a, T *__restrict__ b) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = (T)a[i];
+}
+
+// x = Cinv b, one wave per row.
+template <class T>
+__global__ void k_dense_mv(int n, const double *__restrict__ Ci, const T *__restrict__ b, T *__restrict__ x) {
+  int row = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
+  int lane = threadIdx.x & 63;
+  if (row >= n) return;
+  double s = 0.0;
+  for (int c = lane; c < n; c += 64) s = fma(Ci[(int64_t)row * n + c], (double)b[c], s);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  if (lane == 0) x[row] = (T)s;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+static rs_status level_alloc_work(amg_level *L, int prec) {
+  size_t es = prec == 64 ? sizeof(double) : sizeof(float);
+  RS_TRY(L->b.alloc(es * (L->n + 1)));
+  RS_TRY(L->x.alloc(es * (L->n + 1)));
+  RS_TRY(L->r.alloc(es * (L->n + 1)));
+  RS_TRY(L->dl1.alloc(es * (L->n + 1)));
+  if (prec == 32) {
+    RS_TRY(L->ap.alloc(sizeof(float) * (L->nnz + 1)));
+  }
+  return RS_OK;
+}
+
+// Build the whole hierarchy; M->lev[0] must hold n, nnz, rp, ci, a (FP64).
+rs_status rs_amg_build(rs_cpr_s *M, hipStream_t s) {
+  const rs_cpr_opts &o = M->o;
+  int prec = M->prec;
+  dbuf flag;
+  RS_TRY(flag.alloc(sizeof(int)));
+  for (int l = 0;; ++l) {
+    amg_level *L = M->lev[l];
+    int n = L->n;
+    RS_TRY(level_alloc_work(L, prec));
+    RS_TRY(L->agg.alloc(sizeof(int32_t) * (n + 1)));
+    if (prec == 64) k_l1diag<double><<<rs_grid(n), RS_BLOCK, 0, s>>>(n, L->rp.as<int32_t>(), L->ci.as<int32_t>(), L->a.as<double>(), L->dl1.as<double>());
+    else k_l1diag<float><<<rs_grid(n), RS_BLOCK, 0, s>>>(n, L->rp.as<int32_t>(), L->ci.as<int32_t>(), L->a.as<double>(), L->dl1.as<float>());
+    RS_HIP(hipGetLastError());
+    if (prec == 32) {
+      k_cast_f32<<<rs_grid(L->nnz), RS_BLOCK, 0, s>>>(L->nnz, L->a.as<double>(), L->ap.as<float>());
+      RS_HIP(hipGetLastError());
+    }
+    RS_HIP(hipMemsetAsync(L->agg.p, 0xff, sizeof(int32_t) * (n + 1), s));
+    if (n <= o.coarse_n || (int)M->lev.size() >= o.max_levels) break;
+    // strength
+    dbuf dir, strong, state, m1, m2, und;
+    RS_TRY(dir.alloc(L->nnz)); RS_TRY(strong.alloc(L->nnz)); RS_TRY(state.alloc(n));
+    RS_TRY(m1.alloc(sizeof(uint64_t) * n)); RS_TRY(m2.alloc(sizeof(uint64_t) * n));
+    RS_TRY(und.alloc(sizeof(int)));
+    const int32_t *rp = L->rp.as<int32_t>(), *ci = L->ci.as<int32_t>();
+    k_strength_dir<<<rs_grid(n), RS_BLOCK, 0, s>>>(n, rp, ci, L->a.as<double>(), o.theta, o.max_row_sum, dir.as<uint8_t>());
+    k_strength_sym<<<rs_grid(n), RS_BLOCK, 0, s>>>(n, rp, ci, dir.as<uint8_t>(), strong.as<uint8_t>(), state.as<uint8_t>());
+    RS_HIP(hipGetLastError());
+    // distance-2 MIS rounds
+    for (int round = 0;; ++round) {
+      if (round > n + 2) return RS_E_HIP;     // progress is guaranteed; guard anyway
+      RS_HIP(hipMemsetAsync(und.p, 0, sizeof(int), s));
+      k_mis_m1<<<rs_grid(n), RS_BLOCK, 0, s>>>(n, l, rp, ci, strong.as<uint8_t>(), state.as<uint8_t>(), m1.as<uint64_t>());
+      k_mis_m2<<<rs_grid(n), RS_BLOCK, 0, s>>>(n, rp, ci, strong.as<uint8_t>(), m1.as<uint64_t>(), m2.as<uint64_t>());
+      k_mis_decide<<<rs_grid(n), RS_BLOCK, 0, s>>>(n, l, m2.as<uint64_t>(), state.as<uint8_t>(), und.as<int>());
+      RS_HIP(hipGetLastError());
+      int h = 0;
+      RS_HIP(hipMemcpyAsync(&h, und.p, sizeof(int), hipMemcpyDeviceToHost, s));
+      RS_HIP(hipStreamSynchronize(s));
+      if (h == 0) break;
+    }
+    // aggregates
+    dbuf id, agg1;
+    RS_TRY(id.alloc(sizeof(int32_t) * n)); RS_TRY(agg1.alloc(sizeof(int32_t) * n));
+    k_root_flag<<<rs_grid(n), RS_BLOCK, 0, s>>>(n, state.as<uint8_t>(), id.as<int32_t>());
+    RS_HIP(hipGetLastError());
+    int64_t nc64 = 0;
+    RS_TRY(scan_i32(id.as<int32_t>(), id.as<int32_t>(), n, &nc64, s));
+    int nc = (int)nc64;
+    if (nc == 0 || nc >= n) break;   // no coarsening possible: this level is the coarsest
+    RS_HIP(hipMemsetAsync(flag.p, 0, sizeof(int), s));
+    k_agg1<<<rs_grid(n), RS_BLOCK, 0, s>>>(n, rp, ci, strong.as<uint8_t>(), state.as<uint8_t>(), id.as<int32_t>(), agg1.as<int32_t>());
+    k_agg2<<<rs_grid(n), RS_BLOCK, 0, s>>>(n, rp, ci, strong.as<uint8_t>(), L->a.as<double>(), state.as<uint8_t>(),
+                                           agg1.as<int32_t>(), L->agg.as<int32_t>(), flag.as<int>());
+    RS_HIP(hipGetLastError());
+    L->nc = nc;
+    // members of each aggregate, ascending
+    RS_TRY(L->mptr.alloc(sizeof(int32_t) * (nc + 1)));
+    dbuf cnt;
+    RS_TRY(cnt.alloc(sizeof(int32_t) * (nc + 1)));
+    RS_HIP(hipMemsetAsync(cnt.p, 0, sizeof(int32_t) * (nc + 1), s));
+    k_count_members<<<rs_grid(n), RS_BLOCK, 0, s>>>(n, L->agg.as<int32_t>(), cnt.as<int32_t>());
+    RS_HIP(hipGetLastError());
+    int64_t nmem = 0;
+    RS_TRY(scan_i32(cnt.as<int32_t>(), L->mptr.as<int32_t>(), nc + 1, &nmem, s));
+    RS_TRY(L->mem.alloc(sizeof(int32_t) * (nmem + 1)));
+    RS_HIP(hipMemsetAsync(cnt.p, 0, sizeof(int32_t) * (nc + 1), s));
+    k_fill_members<<<rs_grid(n), RS_BLOCK, 0, s>>>(n, L->agg.as<int32_t>(), L->mptr.as<int32_t>(), cnt.as<int32_t>(), L->mem.as<int32_t>());
+    k_sort_members<<<rs_grid(nc), RS_BLOCK, 0, s>>>(nc, L->mptr.as<int32_t>(), L->mem.as<int32_t>());
+    RS_HIP(hipGetLastError());
+    // Galerkin product
+    dbuf off, skey, sval;
+    RS_TRY(off.alloc(sizeof(int32_t) * (nc + 1)));
+    k_cand<<<rs_grid(nc), RS_BLOCK, 0, s>>>(nc, L->mptr.as<int32_t>(), L->mem.as<int32_t>(), rp, cnt.as<int32_t>());
+    RS_HIP(hipGetLastError());
+    int64_t ncand = 0;
+    RS_TRY(scan_i32(cnt.as<int32_t>(), off.as<int32_t>(), nc, &ncand, s));
+    RS_TRY(skey.alloc(sizeof(int32_t) * (ncand + 1)));
+    RS_TRY(sval.alloc(sizeof(double) * (ncand + 1)));
+    k_galerkin<<<rs_grid(nc), RS_BLOCK, 0, s>>>(nc, L->mptr.as<int32_t>(), L->mem.as<int32_t>(), rp, ci, L->a.as<double>(),
+                                                 L->agg.as<int32_t>(), off.as<int32_t>(), skey.as<int32_t>(),
+                                                 sval.as<double>(), cnt.as<int32_t>());
+    RS_HIP(hipGetLastError());
+    amg_level *C = new amg_level();
+    M->lev.push_back(C);
+    C->n = nc;
+    RS_TRY(C->rp.alloc(sizeof(int32_t) * (nc + 1)));
+    int64_t cnnz = 0;
+    RS_TRY(scan_i32(cnt.as<int32_t>(), C->rp.as<int32_t>(), nc, &cnnz, s));
+    k_set_last<<<1, 1, 0, s>>>(C->rp.as<int32_t>(), nc, (int32_t)cnnz);
+    C->nnz = cnnz;
+    RS_TRY(C->ci.alloc(sizeof(int32_t) * (cnnz + 1)));
+    RS_TRY(C->a.alloc(sizeof(double) * (cnnz + 1)));
+    k_galerkin_copy<<<rs_grid(nc), RS_BLOCK, 0, s>>>(nc, off.as<int32_t>(), skey.as<int32_t>(), sval.as<double>(),
+                                                      C->rp.as<int32_t>(), C->ci.as<int32_t>(), C->a.as<double>());
+    RS_HIP(hipGetLastError());
+    int h = 0;
+    RS_HIP(hipMemcpyAsync(&h, flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    RS_HIP(hipStreamSynchronize(s));
+    if (h) return RS_E_HIP;
+  }
+  M->nlev = (int)M->lev.size();
+  // coarsest level
+  amg_level *C = M->lev.back();
+  int nC = C->n;
+  M->coarse_lu = nC <= o.lu_max;
+  if (M->coarse_lu) {
+    dbuf G;
+    RS_TRY(G.alloc(sizeof(double) * 2 * (size_t)nC * nC + 8));
+    RS_TRY(M->cinv.alloc(sizeof(double) * (size_t)nC * nC + 8));
+    RS_TRY(M->cb.alloc(sizeof(double) * (nC + 1)));
+    RS_TRY(M->cx.alloc(sizeof(double) * (nC + 1)));
+    RS_HIP(hipMemsetAsync(flag.p, 0, sizeof(int), s));
+    k_densify<<<rs_grid(nC), RS_BLOCK, 0, s>>>(nC, C->rp.as<int32_t>(), C->ci.as<int32_t>(), C->a.as<double>(), G.as<double>());
+    for (int k = 0; k < nC; ++k) {
+      k_gj_pivot<<<1, 256, 0, s>>>(nC, k, G.as<double>(), flag.as<int>());
+      int64_t work = (int64_t)nC * (2 * (int64_t)nC - (k + 1));
+      if (work > 0) k_gj_elim<<<rs_grid(work), RS_BLOCK, 0, s>>>(nC, k, G.as<double>());
+    }
+    k_extract_inv<<<rs_grid((int64_t)nC * nC), RS_BLOCK, 0, s>>>(nC, G.as<double>(), M->cinv.as<double>());
+    RS_HIP(hipGetLastError());
+    int h = 0;
+    RS_HIP(hipMemcpyAsync(&h, flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    RS_HIP(hipStreamSynchronize(s));
+    if (h) return RS_E_SINGULAR;
+  }
+  RS_HIP(hipStreamSynchronize(s));
+  return RS_OK;
+}
+
+template <class T>
+static rs_status vcycle_t(rs_cpr_s *M, hipStream_t s) {
+  int nl = M->nlev;
+  // descend
+  for (int l = 0; l < nl - 1; ++l) {
+    amg_level *L = M->lev[l], *C = M->lev[l + 1];
+    const T *a = (M->prec == 64) ? (const T *)L->a.p : (const T *)L->ap.p;
+    k_vc_pre<T><<<rs_grid(L->n), RS_BLOCK, 0, s>>>(L->n, L->rp.as<int32_t>(), L->ci.as<int32_t>(), a,
+                                                  L->dl1.as<T>(), L->b.as<T>(), L->r.as<T>());
+    k_vc_restrict<T><<<rs_grid(L->nc), RS_BLOCK, 0, s>>>(L->nc, L->mptr.as<int32_t>(), L->mem.as<int32_t>(),
+                                                         L->r.as<T>(), C->b.as<T>());
+  }
+  // coarsest
+  amg_level *C = M->lev[nl - 1];
+  const T *ca = (M->prec == 64) ? (const T *)C->a.p : (const T *)C->ap.p;
+  if (M->coarse_lu) {
+    k_dense_mv<T><<<rs_grid(C->n, 4), 256, 0, s>>>(C->n, M->cinv.as<double>(), C->b.as<T>(), C->x.as<T>());
+  } else {
+    T *xa = C->x.as<T>(), *xb = C->r.as<T>();
+    for (int sw = 0; sw < M->o.coarse_sweeps; ++sw) {
+      k_vc_jacobi<T><<<rs_grid(C->n), RS_BLOCK, 0, s>>>(C->n, C->rp.as<int32_t>(), C->ci.as<int32_t>(), ca,
+                                                        C->dl1.as<T>(), C->b.as<T>(), xb, xa, sw == 0);
+      T *t = xa; xa = xb; xb = t;
+    }
+    if (xb != C->x.as<T>())
+      RS_HIP(hipMemcpyAsync(C->x.p, xb, sizeof(T) * C->n, hipMemcpyDeviceToDevice, s));
+  }
+  // ascend
+  for (int l = nl - 2; l >= 0; --l) {
+    amg_level *L = M->lev[l], *Cl = M->lev[l + 1];
+    const T *a = (M->prec == 64) ? (const T *)L->a.p : (const T *)L->ap.p;
+    k_vc_post<T><<<rs_grid(L->n), RS_BLOCK, 0, s>>>(L->n, L->rp.as<int32_t>(), L->ci.as<int32_t>(), a,
+                                                   L->dl1.as<T>(), L->agg.as<int32_t>(), L->b.as<T>(),
+                                                   Cl->x.as<T>(), L->x.as<T>());
+  }
+  RS_HIP(hipGetLastError());
+  return RS_OK;
+}
+
+rs_status rs_vcycle_run(rs_cpr_s *M, hipStream_t s) {
+  return M->prec == 64 ? vcycle_t<double>(M, s) : vcycle_t<float>(M, s);
+}
+
+extern "C" int rs_cpr_nlevels(rs_cpr M) { return M ? M->nlev : 0; }
+
+extern "C" rs_status rs_cpr_level(rs_cpr M, int l, int *h_n, int64_t *h_nnz, int32_t *h_rp,
+                                  int32_t *h_ci, double *h_a, double *h_dl1, int32_t *h_agg) {
+  if (!M || l < 0 || l >= M->nlev) return RS_E_ARG;
+  RS_HIP(hipDeviceSynchronize());
+  amg_level *L = M->lev[l];
+  if (h_n) *h_n = L->n;
+  if (h_nnz) *h_nnz = L->nnz;
+  if (h_rp) RS_HIP(hipMemcpy(h_rp, L->rp.p, sizeof(int32_t) * (L->n + 1), hipMemcpyDeviceToHost));
+  if (h_ci) RS_HIP(hipMemcpy(h_ci, L->ci.p, sizeof(int32_t) * L->nnz, hipMemcpyDeviceToHost));
+  if (h_a) RS_HIP(hipMemcpy(h_a, L->a.p, sizeof(double) * L->nnz, hipMemcpyDeviceToHost));
+  if (h_agg) RS_HIP(hipMemcpy(h_agg, L->agg.p, sizeof(int32_t) * L->n, hipMemcpyDeviceToHost));
+  if (h_dl1) {
+    if (M->prec == 64) {
+      RS_HIP(hipMemcpy(h_dl1, L->dl1.p, sizeof(double) * L->n, hipMemcpyDeviceToHost));
+    } else {
+      std::vector<float> t(L->n);
+      RS_HIP(hipMemcpy(t.data(), L->dl1.p, sizeof(float) * L->n, hipMemcpyDeviceToHost));
+      for (int i = 0; i < L->n; ++i) h_dl1[i] = t[i];
+    }
+  }
+  return RS_OK;
+}
+
+extern "C" rs_status rs_cpr_vcycle(rs_cpr M, const double *d_b, double *d_x, void *stream) {
+  if (!M || !d_b || !d_x) return RS_E_ARG;
+  hipStream_t s = rs_stream(stream);
+  amg_level *L = M->lev[0];
+  int n = L->n;
+  if (M->prec == 64) {
+    RS_HIP(hipMemcpyAsync(L->b.p, d_b, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    RS_TRY(rs_vcycle_run(M, s));
+    RS_HIP(hipMemcpyAsync(d_x, L->x.p, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+  } else {
+    k_from_f64<float><<<rs_grid(n), RS_BLOCK, 0, s>>>(n, d_b, L->b.as<float>());
+    RS_TRY(rs_vcycle_run(M, s));
+    k_to_f64<float><<<rs_grid(n), RS_BLOCK, 0, s>>>(n, L->x.as<float>(), d_x);
+    RS_HIP(hipGetLastError());
+  }
+  return RS_OK;
+}
+
+rs_status rs_amg_level0(rs_cpr_s *M, hipStream_t s) {
+  rs_bsr_s *A = M->A;
+  amg_level *L = new amg_level();
+  M->lev.push_back(L);
+  L->n = (int)A->g.n;
+  L->nnz = A->nnzb;
+  RS_TRY(L->rp.alloc(sizeof(int32_t) * (L->n + 1)));
+  RS_TRY(L->ci.alloc(sizeof(int32_t) * L->nnz));
+  RS_TRY(L->a.alloc(sizeof(double) * L->nnz));
+  RS_HIP(hipMemcpyAsync(L->rp.p, A->rp.p, sizeof(int32_t) * (L->n + 1), hipMemcpyDeviceToDevice, s));
+  RS_HIP(hipMemcpyAsync(L->ci.p, A->ci.p, sizeof(int32_t) * L->nnz, hipMemcpyDeviceToDevice, s));
+  k_gather_ap<<<rs_grid(7 * A->g.n), RS_BLOCK, 0, s>>>(7 * A->g.n, A->pos7.as<int64_t>(), M->D->ap7.as<double>(),
+                                                       L->a.as<double>());
+  RS_HIP(hipGetLastError());
+  return RS_OK;
+}

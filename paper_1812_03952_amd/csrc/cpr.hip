@@ -1,0 +1,389 @@
+// cpr.hip -- two-stage CPR preconditioner (pressure stage, then full-system
+// stage) and its second stage: block Jacobi or block ILU(0).
+//
+// Apply, for a residual r (FP64):
+//   r~  = D^{-1} r                       decoupling (Eq. decoupled-eq)
+//   x_p = Vcycle(A_p, r~[:,0])           pressure stage (Pi_r: unknown 0)
+//   r~2 = r~ - A~[:,0] x_p               residual update (column 0 of A~)
+//   z   = M2^{-1} r~2 + Pi_p x_p          second stage, then prolong x_p
+// The paper's CPR-FPF (Section "Preconditioners", Algorithm pc-fpf) wraps
+// the pressure stage between two Schwarz/ILU stages; this is the two-stage
+// pressure-then-full form.  In prec 32 every vector and stored operator of
+// the preconditioner is FP32 except the coarsest AMG solve (FP64).
+//
+// Block ILU(0) on the 7-point block pattern only modifies the diagonal
+// blocks (no fill position lies on the pattern): D_i = A~_ii - sum over the
+// lower neighbours k of A~_ik D_k^{-1} A~_ki.  Natural (cell) order makes
+// cells with equal i+j+k independent, so setup, forward and backward sweeps
+// run one hyperplane per launch, four lanes per cell (one block row each,
+// partial results exchanged by lane shuffles).  The residual update r~2 is
+// fused into the forward sweep and the prolongation Pi_p x_p into the
+// backward sweep, so r~2 and the uncorrected z are never written.
+#include "rs_internal.h"
+#include <math.h>
+
+namespace {
+#pragma clang fp contract(off)
+#include "block4.h"
+#pragma clang fp contract(fast)
+
+__device__ __forceinline__ int64_t nbr_of(int64_t c, int s, int64_t nx, int64_t nxy) {
+  switch (s) {
+    case 0: return c - nxy;
+    case 1: return c - nx;
+    case 2: return c - 1;
+    case 3: return c;
+    case 4: return c + 1;
+    case 5: return c + nx;
+    default: return c + nxy;
+  }
+}
+__device__ __forceinline__ bool in_grid(int s, int i, int j, int k, int nx, int ny, int nz) {
+  switch (s) {
+    case 0: return k > 0;
+    case 1: return j > 0;
+    case 2: return i > 0;
+    case 3: return true;
+    case 4: return i < nx - 1;
+    case 5: return j < ny - 1;
+    default: return k < nz - 1;
+  }
+}
+
+template <class T>
+__device__ __forceinline__ void ld16(const T *__restrict__ p, double (&M)[4][4]) {
+#pragma unroll
+  for (int e = 0; e < 16; ++e) M[e >> 2][e & 3] = (double)p[e];
+}
+
+// Block-Jacobi setup: invert A~_ii (FP64 arithmetic on the stored values).
+template <class T>
+__global__ void k_bj_setup(int64_t n, const T *__restrict__ t7, T *__restrict__ dinv2, int *__restrict__ flag) {
+#pragma clang fp contract(off)
+  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  double L[4][4], R[4][4];
+  ld16<T>(t7 + (3 * n + c) * 16, L);
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) R[r][q] = (r == q) ? 1.0 : 0.0;
+  int f = gje4<4>(L, R);
+  if (f) atomicOr(flag, f);
+#pragma unroll
+  for (int e = 0; e < 16; ++e) dinv2[c * 16 + e] = (T)R[e >> 2][e & 3];
+}
+
+// DILU setup for the cells of hyperplane i+j+k = lvl, one thread per cell.
+template <class T>
+__global__ void k_dilu_setup(int nx, int ny, int nz, int lvl, const T *__restrict__ t7,
+                             T *__restrict__ dinv2, int *__restrict__ flag) {
+#pragma clang fp contract(off)
+  int jk = blockIdx.x * blockDim.x + threadIdx.x;
+  if (jk >= ny * nz) return;
+  int j = jk % ny, k = jk / ny, i = lvl - j - k;
+  if (i < 0 || i >= nx) return;
+  int64_t nxy = (int64_t)nx * ny, n = nxy * nz;
+  int64_t c = i + nx * (j + (int64_t)ny * k);
+  double D[4][4];
+  ld16<T>(t7 + (3 * n + c) * 16, D);
+#pragma unroll
+  for (int s = 0; s < 3; ++s) {
+    if (!in_grid(s, i, j, k, nx, ny, nz)) continue;
+    int64_t q = nbr_of(c, s, nx, nxy);
+    double Dq[4][4], Aqc[4][4], Acq[4][4], T1[4][4];
+    ld16<T>(dinv2 + q * 16, Dq);
+    ld16<T>(t7 + ((int64_t)(6 - s) * n + q) * 16, Aqc);
+    ld16<T>(t7 + ((int64_t)s * n + c) * 16, Acq);
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int cc = 0; cc < 4; ++cc) {
+        double v = 0.0;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) v = v + Dq[r][m] * Aqc[m][cc];
+        T1[r][cc] = v;
+      }
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int cc = 0; cc < 4; ++cc) {
+        double v = 0.0;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) v = v + Acq[r][m] * T1[m][cc];
+        D[r][cc] = D[r][cc] - v;
+      }
+  }
+  double R[4][4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) R[r][q] = (r == q) ? 1.0 : 0.0;
+  int f = gje4<4>(D, R);
+  if (f) atomicOr(flag, f);
+#pragma unroll
+  for (int e = 0; e < 16; ++e) dinv2[c * 16 + e] = (T)R[e >> 2][e & 3];
+}
+
+// ---- apply -------------------------------------------------------------------
+template <class T> __device__ __forceinline__ T ldin(const double *p) { return (T)*p; }
+
+// r~ = D^{-1} r; the pressure right-hand side b_p = r~[:,0].  Four lanes per cell.
+template <class T>
+__global__ __launch_bounds__(256) void k_cpr_in(int64_t n, const T *__restrict__ dinv,
+                                                 const double *__restrict__ r, T *__restrict__ rt,
+                                                 T *__restrict__ bp) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 4 * n) return;
+  int64_t c = t >> 2;
+  int row = (int)(t & 3);
+  const T *d = dinv + c * 16 + 4 * row;
+  T s = 0;
+#pragma unroll
+  for (int m = 0; m < 4; ++m) s = fma(d[m], (T)r[4 * c + m], s);
+  rt[t] = s;
+  if (row == 0) bp[c] = s;
+}
+
+// r~2 for lane `row` of cell c: r~ - sum over the 7 slots of A~[:,0] x_p.
+template <class T>
+__device__ __forceinline__ T resid2(int64_t n, int64_t c, int row, int64_t nx, int64_t nxy,
+                                    const T *__restrict__ rt, const T *__restrict__ col0,
+                                    const T *__restrict__ xp) {
+  T v = rt[4 * c + row];
+#pragma unroll
+  for (int s = 0; s < 7; ++s) {
+    int64_t q = nbr_of(c, s, nx, nxy);
+    q = (q < 0 || q >= n) ? c : q;           // off-grid col0 entries are zero
+    v = v - col0[((int64_t)s * n + c) * 4 + row] * xp[q];
+  }
+  return v;
+}
+
+// 4x4 matvec across the four lanes of a cell: lane `row` returns (M v)[row]
+// where v[m] lives in lane m of the group.
+template <class T>
+__device__ __forceinline__ T group_mv(const T *__restrict__ Mrow, T v) {
+  int base = (threadIdx.x & 63) & ~3;
+  T out = 0;
+#pragma unroll
+  for (int m = 0; m < 4; ++m) out = fma(Mrow[m], __shfl(v, base + m, 64), out);
+  return out;
+}
+
+// Block Jacobi second stage, fused: z = D2^{-1} r~2 + Pi_p x_p.
+template <class T>
+__global__ __launch_bounds__(256) void k_bj_apply(int64_t n, int64_t nx, int64_t nxy,
+                                                   const T *__restrict__ rt, const T *__restrict__ col0,
+                                                   const T *__restrict__ xp, const T *__restrict__ dinv2,
+                                                   T *__restrict__ z) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool ok = t < 4 * n;
+  int64_t c = ok ? (t >> 2) : 0;
+  int row = (int)(t & 3);
+  T v = resid2<T>(n, c, row, nx, nxy, rt, col0, xp);
+  T o = group_mv<T>(dinv2 + c * 16 + 4 * row, v);
+  if (row == 0) o = o + xp[c];
+  if (ok) z[t] = o;
+}
+
+// DILU forward sweep on hyperplane lvl:
+//   y_c = D_c^{-1} (r~2_c - sum_{lower k} A~_ck y_k)
+template <class T>
+__global__ __launch_bounds__(256) void k_dilu_fwd(int nx, int ny, int nz, int lvl,
+                                                   const T *__restrict__ t7, const T *__restrict__ dinv2,
+                                                   const T *__restrict__ rt, const T *__restrict__ col0,
+                                                   const T *__restrict__ xp, T *__restrict__ y) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int jk = (int)(t >> 2), row = (int)(t & 3);
+  int j = jk % ny, k = jk / ny, i = lvl - j - k;
+  bool ok = jk < ny * nz && i >= 0 && i < nx;
+  int64_t nxy = (int64_t)nx * ny, n = nxy * nz;
+  int64_t c = ok ? i + nx * (j + (int64_t)ny * k) : 0;
+  T v = resid2<T>(n, c, row, nx, nxy, rt, col0, xp);
+#pragma unroll
+  for (int s = 0; s < 3; ++s) {
+    if (ok && in_grid(s, i, j, k, nx, ny, nz)) {
+      int64_t q = nbr_of(c, s, nx, nxy);
+      const T *a = t7 + ((int64_t)s * n + c) * 16 + 4 * row;
+      const T *yq = y + 4 * q;
+      T u = 0;
+#pragma unroll
+      for (int m = 0; m < 4; ++m) u = fma(a[m], yq[m], u);
+      v = v - u;
+    }
+  }
+  T o = group_mv<T>(dinv2 + c * 16 + 4 * row, v);
+  if (ok) y[4 * c + row] = o;
+}
+
+// DILU backward sweep on hyperplane lvl:
+//   z_c = y_c - D_c^{-1} sum_{upper k} A~_ck z_k;   out_c = z_c + Pi_p x_p
+template <class T>
+__global__ __launch_bounds__(256) void k_dilu_bwd(int nx, int ny, int nz, int lvl,
+                                                   const T *__restrict__ t7, const T *__restrict__ dinv2,
+                                                   const T *__restrict__ y, const T *__restrict__ xp,
+                                                   T *__restrict__ z, T *__restrict__ out) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int jk = (int)(t >> 2), row = (int)(t & 3);
+  int j = jk % ny, k = jk / ny, i = lvl - j - k;
+  bool ok = jk < ny * nz && i >= 0 && i < nx;
+  int64_t nxy = (int64_t)nx * ny, n = nxy * nz;
+  int64_t c = ok ? i + nx * (j + (int64_t)ny * k) : 0;
+  T v = 0;
+#pragma unroll
+  for (int s = 4; s < 7; ++s) {
+    if (ok && in_grid(s, i, j, k, nx, ny, nz)) {
+      int64_t q = nbr_of(c, s, nx, nxy);
+      const T *a = t7 + ((int64_t)s * n + c) * 16 + 4 * row;
+      const T *zq = z + 4 * q;
+      T u = 0;
+#pragma unroll
+      for (int m = 0; m < 4; ++m) u = fma(a[m], zq[m], u);
+      v = v + u;
+    }
+  }
+  T w = group_mv<T>(dinv2 + c * 16 + 4 * row, v);
+  if (ok) {
+    T zc = y[4 * c + row] - w;
+    z[4 * c + row] = zc;
+    out[4 * c + row] = row == 0 ? zc + xp[c] : zc;
+  }
+}
+
+template <class T>
+__global__ void k_vec_to_f64(int64_t m, const T *__restrict__ a, double *__restrict__ b) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < m) b[t] = (double)a[t];
+}
+
+}  // namespace
+
+rs_status rs_amg_level0(rs_cpr_s *M, hipStream_t s);
+rs_status rs_amg_build(rs_cpr_s *M, hipStream_t s);
+
+extern "C" void rs_cpr_opts_default(rs_cpr_opts *o) {
+  if (!o) return;
+  o->smoother = RS_SM_DILU;
+  o->theta = 0.5;
+  o->max_row_sum = 0.9;
+  o->coarse_n = 500;
+  o->max_levels = 20;
+  o->lu_max = 2048;
+  o->coarse_sweeps = 4;
+}
+
+rs_cpr_s::~rs_cpr_s() {
+  for (amg_level *L : lev) delete L;
+  if (hpin) (void)hipHostFree(hpin);
+}
+
+extern "C" void rs_cpr_destroy(rs_cpr M) { delete M; }
+
+extern "C" rs_status rs_cpr_setup(rs_bsr A, rs_dcpl D, const rs_cpr_opts *o, void *stream, rs_cpr *out) {
+  if (!A || !D || !out || D->A != A) return RS_E_ARG;
+  *out = nullptr;
+  rs_cpr_opts opts;
+  if (o) opts = *o; else rs_cpr_opts_default(&opts);
+  if ((opts.smoother != RS_SM_BJ && opts.smoother != RS_SM_DILU) || opts.coarse_n < 1 ||
+      opts.max_levels < 1 || opts.lu_max < 1 || opts.lu_max > 8192 || opts.coarse_sweeps < 1)
+    return RS_E_ARG;
+  hipStream_t s = rs_stream(stream);
+  rs_cpr_s *M = new rs_cpr_s();
+  M->A = A; M->D = D; M->o = opts; M->prec = D->prec;
+  int64_t n = A->g.n;
+  size_t es = M->prec == 64 ? sizeof(double) : sizeof(float);
+  rs_status st = RS_OK;
+  do {
+    if ((st = rs_amg_level0(M, s)) != RS_OK) break;
+    if ((st = rs_amg_build(M, s)) != RS_OK) break;
+    if ((st = M->dinv2.alloc(es * 16 * n)) != RS_OK) break;
+    if ((st = M->rt.alloc(es * 4 * n)) != RS_OK) break;
+    if ((st = M->yv.alloc(es * 4 * n)) != RS_OK) break;
+    if ((st = M->zt.alloc(es * 4 * n)) != RS_OK) break;
+    dbuf flag;
+    if ((st = flag.alloc(sizeof(int))) != RS_OK) break;
+    if (hipMemsetAsync(flag.p, 0, sizeof(int), s) != hipSuccess) { st = RS_E_HIP; break; }
+    const grid3 &g = A->g;
+    if (opts.smoother == RS_SM_BJ) {
+      if (M->prec == 64) k_bj_setup<double><<<rs_grid(n), RS_BLOCK, 0, s>>>(n, D->t7.as<double>(), M->dinv2.as<double>(), flag.as<int>());
+      else k_bj_setup<float><<<rs_grid(n), RS_BLOCK, 0, s>>>(n, D->t7.as<float>(), M->dinv2.as<float>(), flag.as<int>());
+    } else {
+      int nlv = g.nx + g.ny + g.nz - 2;
+      unsigned grid = rs_grid((int64_t)g.ny * g.nz);
+      for (int l = 0; l < nlv; ++l) {
+        if (M->prec == 64) k_dilu_setup<double><<<grid, RS_BLOCK, 0, s>>>(g.nx, g.ny, g.nz, l, D->t7.as<double>(), M->dinv2.as<double>(), flag.as<int>());
+        else k_dilu_setup<float><<<grid, RS_BLOCK, 0, s>>>(g.nx, g.ny, g.nz, l, D->t7.as<float>(), M->dinv2.as<float>(), flag.as<int>());
+      }
+    }
+    int h = 0;
+    if (hipGetLastError() != hipSuccess ||
+        hipMemcpyAsync(&h, flag.p, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) { st = RS_E_HIP; break; }
+    if (h & RSF_NONFINITE) st = RS_E_NONFINITE;
+    else if (h & RSF_SINGULAR) st = RS_E_SINGULAR;
+  } while (0);
+  if (st != RS_OK) { delete M; return st; }
+  *out = M;
+  return RS_OK;
+}
+
+template <class T>
+static rs_status cpr_apply_t(rs_cpr_s *M, const double *r, T *z, hipStream_t s) {
+  const rs_bsr_s *A = M->A;
+  const grid3 &g = A->g;
+  int64_t n = g.n;
+  amg_level *L0 = M->lev[0];
+  k_cpr_in<T><<<rs_grid(4 * n), RS_BLOCK, 0, s>>>(n, M->D->dinv.as<T>(), r, M->rt.as<T>(), L0->b.as<T>());
+  RS_HIP(hipGetLastError());
+  RS_TRY(rs_vcycle_run(M, s));
+  const T *xp = L0->x.as<T>();
+  if (M->o.smoother == RS_SM_BJ) {
+    k_bj_apply<T><<<rs_grid(4 * n), RS_BLOCK, 0, s>>>(n, g.nx, g.nxy, M->rt.as<T>(), M->D->col0.as<T>(), xp,
+                                                     M->dinv2.as<T>(), z);
+  } else {
+    int nlv = g.nx + g.ny + g.nz - 2;
+    unsigned grid = rs_grid(4 * (int64_t)g.ny * g.nz);
+    for (int l = 0; l < nlv; ++l)
+      k_dilu_fwd<T><<<grid, RS_BLOCK, 0, s>>>(g.nx, g.ny, g.nz, l, M->D->t7.as<T>(), M->dinv2.as<T>(), M->rt.as<T>(),
+                                              M->D->col0.as<T>(), xp, M->yv.as<T>());
+    for (int l = nlv - 1; l >= 0; --l)
+      k_dilu_bwd<T><<<grid, RS_BLOCK, 0, s>>>(g.nx, g.ny, g.nz, l, M->D->t7.as<T>(), M->dinv2.as<T>(), M->yv.as<T>(),
+                                              xp, M->zt.as<T>(), z);
+  }
+  RS_HIP(hipGetLastError());
+  return RS_OK;
+}
+
+rs_status rs_cpr_apply_any(rs_cpr_s *M, const double *r, void *z, int zprec, hipStream_t s) {
+  if (zprec != M->prec) return RS_E_ARG;
+  return M->prec == 64 ? cpr_apply_t<double>(M, r, (double *)z, s) : cpr_apply_t<float>(M, r, (float *)z, s);
+}
+
+extern "C" rs_status rs_cpr_apply(rs_cpr M, const double *d_r, double *d_z, void *stream) {
+  if (!M || !d_r || !d_z || d_r == d_z) return RS_E_ARG;
+  hipStream_t s = rs_stream(stream);
+  if (M->prec == 64) return cpr_apply_t<double>(M, d_r, d_z, s);
+  int64_t m = 4 * M->A->g.n;
+  dbuf tmp;
+  RS_TRY(tmp.alloc(sizeof(float) * m));
+  RS_TRY(cpr_apply_t<float>(M, d_r, tmp.as<float>(), s));
+  k_vec_to_f64<float><<<rs_grid(m), RS_BLOCK, 0, s>>>(m, tmp.as<float>(), d_z);
+  RS_HIP(hipGetLastError());
+  RS_HIP(hipStreamSynchronize(s));   // tmp is freed on return
+  return RS_OK;
+}
+
+extern "C" rs_status rs_cpr_smoother_get(rs_cpr M, double *h_dinv2) {
+  if (!M || !h_dinv2) return RS_E_ARG;
+  RS_HIP(hipDeviceSynchronize());
+  int64_t m = 16 * M->A->g.n;
+  if (M->prec == 64) {
+    RS_HIP(hipMemcpy(h_dinv2, M->dinv2.p, sizeof(double) * m, hipMemcpyDeviceToHost));
+  } else {
+    std::vector<float> t(m);
+    RS_HIP(hipMemcpy(t.data(), M->dinv2.p, sizeof(float) * m, hipMemcpyDeviceToHost));
+    for (int64_t e = 0; e < m; ++e) h_dinv2[e] = t[e];
+  }
+  return RS_OK;
+}

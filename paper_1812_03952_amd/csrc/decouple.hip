@@ -1,0 +1,190 @@
+// decouple.hip -- ABF / quasi-IMPES decoupling and pressure-matrix extraction.
+//
+// Decoupling is a left scaling (D^{-1} A) x = D^{-1} b (Eq. decoupled-eq)
+// applied block row by block row with Gauss-Jordan elimination and row
+// pivoting only (Section "Decoupling Methods").  Eight lanes work on one
+// block row: lane s < 7 carries block column s of [A_ii | A_i,s] through the
+// elimination, lane 7 carries the identity and so produces D_i^{-1}.  Every
+// lane repeats the (cheap) pivot sequence on A_ii itself, which keeps all
+// lanes independent and the per-lane state at 32 doubles.  Row exchanges
+// are written as selects over compile-time indices so nothing spills.
+//
+// FMA contraction is off in this file: each update is one multiply and one
+// subtract, in the same order as the FP64 reference, so the FP64 pressure
+// matrix used by the AMG setup does not depend on the compiler's choices.
+#pragma clang fp contract(off)
+#include "rs_internal.h"
+#include <math.h>
+
+namespace {
+#include "block4.h"
+
+template <class T>
+__device__ __forceinline__ void store_block(T *__restrict__ t7, T *__restrict__ col0, double *__restrict__ ap7,
+                                            int s, int64_t n, int64_t c, const double (&R)[4][4]) {
+  T *o = t7 + ((int64_t)s * n + c) * 16;
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) o[4 * r + q] = (T)R[r][q];
+  T *o0 = col0 + ((int64_t)s * n + c) * 4;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) o0[r] = (T)R[r][0];
+  ap7[(int64_t)s * n + c] = R[0][0];
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_decouple_abf(int64_t n, const double *__restrict__ a7,
+                                                       T *__restrict__ t7, T *__restrict__ dinv,
+                                                       double *__restrict__ ap7, T *__restrict__ col0,
+                                                       int *__restrict__ flag) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 8 * n) return;
+  int64_t c = t >> 3;
+  int lane = (int)(t & 7);
+  double L[4][4], R[4][4];
+  load16(a7 + (3 * n + c) * 16, L);
+  if (lane < 7) {
+    load16(a7 + ((int64_t)lane * n + c) * 16, R);
+  } else {
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) R[r][q] = (r == q) ? 1.0 : 0.0;
+  }
+  int f = gje4<4>(L, R);
+  if (lane == 0 && f) atomicOr(flag, f);
+  if (lane == 7) {
+    T *o = dinv + c * 16;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) o[4 * r + q] = (T)R[r][q];
+    return;
+  }
+  if (lane == 3) {      // A~_ii = I exactly
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) R[r][q] = (r == q) ? 1.0 : 0.0;
+  }
+  store_block<T>(t7, col0, ap7, lane, n, c, R);
+}
+
+// Quasi-IMPES: w_i solves A_ii^T w_i = e_0; row 0 of each block in row i
+// becomes w_i^T A_ij; rows 1-3 stay; D_i^{-1} = [w_i^T; e_1^T; e_2^T; e_3^T].
+template <class T>
+__global__ __launch_bounds__(256) void k_decouple_qi(int64_t n, const double *__restrict__ a7,
+                                                      T *__restrict__ t7, T *__restrict__ dinv,
+                                                      double *__restrict__ ap7, T *__restrict__ col0,
+                                                      int *__restrict__ flag) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 8 * n) return;
+  int64_t c = t >> 3;
+  int lane = (int)(t & 7);
+  double L[4][4], w[4][1];
+  {
+    double Aii[4][4];
+    load16(a7 + (3 * n + c) * 16, Aii);
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) L[r][q] = Aii[q][r];
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) w[r][0] = (r == 0) ? 1.0 : 0.0;
+  int f = gje4<1>(L, w);
+  if (lane == 0 && f) atomicOr(flag, f);
+  if (lane == 7) {
+    T *o = dinv + c * 16;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) o[e] = (T)0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) o[q] = (T)w[q][0];
+    o[5] = o[10] = o[15] = (T)1.0;
+    return;
+  }
+  double A[4][4], R[4][4];
+  load16(a7 + ((int64_t)lane * n + c) * 16, A);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    double s = 0.0;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) s = s + w[m][0] * A[m][q];
+    R[0][q] = s;
+  }
+#pragma unroll
+  for (int r = 1; r < 4; ++r)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) R[r][q] = A[r][q];
+  store_block<T>(t7, col0, ap7, lane, n, c, R);
+}
+
+}  // namespace
+
+extern "C" rs_status rs_decouple(rs_bsr A, int method, int prec, void *stream, rs_dcpl *out) {
+  if (!A || !out || (method != RS_ABF && method != RS_QIMPES) || (prec != 32 && prec != 64))
+    return RS_E_ARG;
+  *out = nullptr;
+  hipStream_t s = rs_stream(stream);
+  int64_t n = A->g.n;
+  size_t es = prec == 64 ? sizeof(double) : sizeof(float);
+  rs_dcpl_s *D = new rs_dcpl_s();
+  D->A = A; D->method = method; D->prec = prec;
+  rs_status st = RS_OK;
+  int h = 0;
+  do {
+    if ((st = D->t7.alloc(es * 7 * n * 16)) != RS_OK) break;
+    if ((st = D->dinv.alloc(es * n * 16)) != RS_OK) break;
+    if ((st = D->ap7.alloc(sizeof(double) * 7 * n)) != RS_OK) break;
+    if ((st = D->col0.alloc(es * 7 * n * 4)) != RS_OK) break;
+    dbuf flag;
+    if ((st = flag.alloc(sizeof(int))) != RS_OK) break;
+    if (hipMemsetAsync(flag.p, 0, sizeof(int), s) != hipSuccess) { st = RS_E_HIP; break; }
+    unsigned grid = rs_grid(8 * n);
+    if (method == RS_ABF) {
+      if (prec == 64)
+        k_decouple_abf<double><<<grid, RS_BLOCK, 0, s>>>(n, A->a7.as<double>(), D->t7.as<double>(), D->dinv.as<double>(),
+                                                         D->ap7.as<double>(), D->col0.as<double>(), flag.as<int>());
+      else
+        k_decouple_abf<float><<<grid, RS_BLOCK, 0, s>>>(n, A->a7.as<double>(), D->t7.as<float>(), D->dinv.as<float>(),
+                                                        D->ap7.as<double>(), D->col0.as<float>(), flag.as<int>());
+    } else {
+      if (prec == 64)
+        k_decouple_qi<double><<<grid, RS_BLOCK, 0, s>>>(n, A->a7.as<double>(), D->t7.as<double>(), D->dinv.as<double>(),
+                                                        D->ap7.as<double>(), D->col0.as<double>(), flag.as<int>());
+      else
+        k_decouple_qi<float><<<grid, RS_BLOCK, 0, s>>>(n, A->a7.as<double>(), D->t7.as<float>(), D->dinv.as<float>(),
+                                                       D->ap7.as<double>(), D->col0.as<float>(), flag.as<int>());
+    }
+    if (hipGetLastError() != hipSuccess ||
+        hipMemcpyAsync(&h, flag.p, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) { st = RS_E_HIP; break; }
+    if (h & RSF_NONFINITE) st = RS_E_NONFINITE;
+    else if (h & RSF_SINGULAR) st = RS_E_SINGULAR;
+  } while (0);
+  if (st != RS_OK) { delete D; return st; }
+  *out = D;
+  return RS_OK;
+}
+
+extern "C" void rs_dcpl_destroy(rs_dcpl D) { delete D; }
+
+rs_status rs_from7_host(const rs_bsr_s *A, const void *a7, int prec, double *h_vals);
+
+extern "C" rs_status rs_dcpl_get(rs_dcpl D, double *h_vals, double *h_dinv) {
+  if (!D) return RS_E_ARG;
+  RS_HIP(hipDeviceSynchronize());
+  if (h_vals) RS_TRY(rs_from7_host(D->A, D->t7.p, D->prec, h_vals));
+  if (h_dinv) {
+    int64_t n = D->A->g.n;
+    if (D->prec == 64) {
+      RS_HIP(hipMemcpy(h_dinv, D->dinv.p, sizeof(double) * 16 * n, hipMemcpyDeviceToHost));
+    } else {
+      std::vector<float> tmp(16 * n);
+      RS_HIP(hipMemcpy(tmp.data(), D->dinv.p, sizeof(float) * 16 * n, hipMemcpyDeviceToHost));
+      for (int64_t e = 0; e < 16 * n; ++e) h_dinv[e] = tmp[e];
+    }
+  }
+  return RS_OK;
+}

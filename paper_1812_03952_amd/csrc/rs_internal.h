@@ -1,0 +1,121 @@
+// rs_internal.h -- shared declarations of librsolve (HIP, gfx950).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <vector>
+#include "../../include/rsolve.h"
+
+#define RS_BLOCK 256
+
+// ---- error handling: every HIP call is checked and mapped to rs_status ----
+#define RS_HIP(call)                                                   \
+  do {                                                                 \
+    hipError_t e_ = (call);                                            \
+    if (e_ != hipSuccess) return (e_ == hipErrorOutOfMemory) ? RS_E_NOMEM : RS_E_HIP; \
+  } while (0)
+#define RS_TRY(expr)                        \
+  do {                                      \
+    rs_status s_ = (expr);                  \
+    if (s_ != RS_OK) return s_;             \
+  } while (0)
+
+static inline hipStream_t rs_stream(void *s) { return (hipStream_t)s; }
+
+// A device allocation owned by a handle.
+struct dbuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+  ~dbuf() { if (p) (void)hipFree(p); }
+  dbuf() = default;
+  dbuf(const dbuf &) = delete;
+  dbuf &operator=(const dbuf &) = delete;
+  rs_status alloc(size_t b) {
+    if (p && bytes >= b) return RS_OK;
+    if (p) { (void)hipFree(p); p = nullptr; bytes = 0; }
+    if (b == 0) b = 16;
+    hipError_t e = hipMalloc(&p, b);
+    if (e != hipSuccess) { p = nullptr; return RS_E_NOMEM; }
+    bytes = b;
+    return RS_OK;
+  }
+  void release() { if (p) (void)hipFree(p); p = nullptr; bytes = 0; }
+  template <class T> T *as() const { return (T *)p; }
+};
+
+static inline unsigned rs_grid(int64_t work, int block = RS_BLOCK) {
+  int64_t g = (work + block - 1) / block;
+  if (g < 1) g = 1;
+  return (unsigned)g;
+}
+
+// ---- grid geometry --------------------------------------------------------
+// The 7 stencil slots in ascending column order: -z -y -x self +x +y +z.
+struct grid3 {
+  int nx, ny, nz;
+  int64_t n, nxy;
+};
+
+// ---- handles --------------------------------------------------------------
+struct rs_bsr_s {
+  grid3 g;
+  int64_t nnzb;
+  dbuf rp, ci;       // caller pattern (copy), int32
+  dbuf pos7;         // int64 per (slot, cell): caller block index or -1
+  dbuf a7;           // double [7][n][16]: blocks by stencil slot (zeros off-grid)
+  // adjoint cache
+  rs_bsr_s *at = nullptr;
+  rs_dcpl_s *at_d = nullptr;
+  rs_cpr_s *at_m = nullptr;
+  int at_method = -1, at_prec = -1;
+  rs_cpr_opts at_opts;
+  ~rs_bsr_s();
+};
+
+struct rs_dcpl_s {
+  rs_bsr_s *A;
+  int method, prec;
+  dbuf t7;      // decoupled blocks [7][n][16], prec
+  dbuf dinv;    // D^{-1} [n][16], prec
+  dbuf ap7;     // pressure entries [7][n], double
+  dbuf col0;    // column 0 of the decoupled blocks [7][n][4], prec
+};
+
+struct amg_level {
+  int n = 0, nc = 0;
+  int64_t nnz = 0;
+  dbuf rp, ci;        // int32 CSR
+  dbuf a;             // double values (setup precision)
+  dbuf ap;            // values in apply precision (alias of a when prec 64)
+  dbuf dl1;           // l1 diagonal, apply precision
+  dbuf agg;           // int32 aggregate per row (-1 none)
+  dbuf mptr, mem;     // members of each aggregate (ascending), for restriction
+  dbuf b, x, r;       // cycle work vectors, apply precision
+};
+
+struct rs_cpr_s {
+  rs_bsr_s *A;
+  rs_dcpl_s *D;
+  rs_cpr_opts o;
+  int prec;
+  int nlev = 0;
+  std::vector<amg_level *> lev;
+  int coarse_lu = 0;
+  dbuf cinv;          // dense inverse of the coarsest level (double)
+  dbuf cb, cx;        // coarsest rhs / solution in double
+  dbuf dinv2;         // second-stage block inverses [n][16], prec
+  // CPR work
+  dbuf rt, bp, xp, yv, zt;   // prec vectors
+  // GMRES work (allocated on first solve)
+  int m = 0;
+  dbuf V, Z, w, part, scal;
+  double *hpin = nullptr;     // pinned host status word
+  ~rs_cpr_s();
+};
+
+// ---- internal entry points shared between translation units ---------------
+rs_status rs_spmv_any(const rs_bsr_s *A, const void *x, int xprec, double *y,
+                      const double *b_minus, hipStream_t s);
+rs_status rs_cpr_apply_any(rs_cpr_s *M, const double *r, void *z, int zprec,
+                           hipStream_t s);
+rs_status rs_vcycle_run(rs_cpr_s *M, hipStream_t s);
+rs_status rs_transpose7(const rs_bsr_s *A, rs_bsr_s *At, hipStream_t s);

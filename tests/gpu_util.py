@@ -1,0 +1,23 @@
+"""Helpers for the GPU parity tests: move an oracle-assembled problem to the
+device and build the library's handles on it."""
+import numpy as np
+import torch
+
+import oracle
+from paper_1812_03952_amd import rsolve as rs
+
+
+def dev(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+def upload(A: "oracle.BSR"):
+    rp = dev(A.rp, torch.int32)
+    ci = dev(A.ci, torch.int32)
+    v = dev(A.v.reshape(-1))
+    return rs.bsr_create(A.nx, A.ny, A.nz, rp, ci, v)
+
+
+def relerr(a, b):
+    a = np.asarray(a); b = np.asarray(b)
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)

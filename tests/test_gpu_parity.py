@@ -1,0 +1,205 @@
+"""HIP path against the FP64 oracle, element by element, through the C-ABI.
+
+Inputs are seeded synthetic problems; both sides get the same assembled
+matrix (from the oracle), so every difference is the kernels'.  Where the
+library keeps the oracle's operation order (pattern, decoupling, AMG
+setup) the results are compared bitwise; elsewhere FMA contraction and
+reduction order differ and the tolerance is stated per test."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from paper_1812_03952_amd import rsolve as rs
+from gpu_util import dev, relerr, upload
+
+pytestmark = pytest.mark.gpu
+
+GRIDS = [(1, 1, 1), (1, 1, 7), (6, 1, 1), (1, 5, 1), (5, 3, 4), (20, 20, 10), (33, 17, 9)]
+
+
+def _prob(dims, seed=3, **kw):
+    nx, ny, nz = dims
+    w = synth.wells_vertical_pair(nx, ny, nz, (0, 0), (nx - 1, ny - 1)) if nx * ny > 1 else None
+    return synth.make(nx, ny, nz, seed=seed, wells=w, **kw)
+
+
+@pytest.mark.parametrize("dims", GRIDS)
+def test_pattern_and_assembly(dims):
+    p = _prob(dims, sigma=1.5)
+    rp, ci = oracle.pattern(*dims)
+    drp, dci = rs.pattern(*dims)
+    assert np.array_equal(drp.cpu().numpy(), rp) and np.array_equal(dci.cpu().numpy(), ci)
+    A = oracle.assemble(p)
+    dp = rs.DeviceProblem(p)
+    torch.cuda.synchronize()
+    got = dp.vals.cpu().numpy().reshape(-1, 4, 4)
+    scale = np.abs(A.v).max(axis=(1, 2), keepdims=True)
+    assert np.all(np.abs(got - A.v) <= 4e-16 * 8 * scale)     # exp() may differ by an ulp
+
+
+@pytest.mark.parametrize("dims", GRIDS)
+def test_spmv(dims):
+    p = _prob(dims, sigma=2.0, shale=0.1)
+    A = oracle.assemble(p)
+    M = upload(A)
+    x = np.random.default_rng(1).standard_normal(4 * A.n)
+    y = torch.empty(4 * A.n, dtype=torch.float64, device="cuda")
+    rs.spmv(M, dev(x), y)
+    ref = oracle.spmv(A, x)
+    bound = 1e-15 * 8 * np.abs(A.v).sum(axis=2).max() * np.abs(x).max() * 7
+    assert np.abs(y.cpu().numpy() - ref).max() <= bound
+
+
+@pytest.mark.parametrize("method", [rs.ABF, rs.QIMPES])
+@pytest.mark.parametrize("dims", [(5, 3, 4), (20, 20, 10), (1, 1, 7)])
+def test_decouple_fp64_bitwise(method, dims):
+    p = _prob(dims, sigma=1.5)
+    A = oracle.assemble(p)
+    At, dinv = oracle.decouple(A, method)
+    D = rs.decouple(upload(A), method, 64)
+    vals, dd = rs.dcpl_get(D)
+    assert np.array_equal(vals, At.v)
+    assert np.array_equal(dd, dinv)
+
+
+def test_decouple_fp32():
+    p = _prob((20, 20, 10), sigma=1.5)
+    A = oracle.assemble(p)
+    At, dinv = oracle.decouple(A)
+    D = rs.decouple(upload(A), rs.ABF, 32)
+    vals, dd = rs.dcpl_get(D)
+    assert np.array_equal(vals, At.v.astype(np.float32).astype(np.float64))
+    assert np.array_equal(dd, dinv.astype(np.float32).astype(np.float64))
+
+
+def test_decouple_errors():
+    p = _prob((2, 2, 1))
+    A = oracle.assemble(p)
+    v = A.v.copy()
+    v[A.rp[1] + 1] = 0.0
+    with pytest.raises(rs.RsError) as e:
+        rs.decouple(upload(A.with_values(v)), rs.ABF, 64)
+    assert e.value.status == -4
+    rp = dev(A.rp, torch.int32); ci = dev(A.ci, torch.int32)
+    bad = ci.clone(); bad[0] = 3
+    with pytest.raises(rs.RsError) as e:
+        rs.bsr_create(2, 2, 1, rp, bad, dev(A.v.reshape(-1)))
+    assert e.value.status == -1
+    v = A.v.copy(); v[0, 0, 0] = np.nan
+    with pytest.raises(rs.RsError) as e:
+        rs.bsr_create(2, 2, 1, rp, ci, dev(v.reshape(-1)))
+    assert e.value.status == -5
+
+
+@pytest.mark.parametrize("dims,sigma", [((20, 20, 10), 1.0), ((33, 17, 9), 2.0), ((40, 40, 20), 2.0)])
+def test_amg_hierarchy_bitwise(dims, sigma):
+    p = _prob(dims, sigma=sigma, shale=0.1 if sigma > 1.5 else 0.0)
+    A = oracle.assemble(p)
+    Mo = oracle.CPR(A, coarse_n=50)
+    B = upload(A)
+    D = rs.decouple(B, rs.ABF, 64)
+    Mg = rs.cpr_setup(B, D, rs.cpr_opts(coarse_n=50))
+    ho = Mo.amg()
+    assert rs.cpr_nlevels(Mg) == ho.nlevels
+    for l in range(ho.nlevels):
+        Lo, Lg = ho.level(l), rs.cpr_level(Mg, l)
+        assert Lo["n"] == Lg["n"] and Lo["nnz"] == Lg["nnz"]
+        assert np.array_equal(Lo["rp"], Lg["rp"]) and np.array_equal(Lo["ci"], Lg["ci"])
+        assert np.array_equal(Lo["a"], Lg["a"])
+        assert np.array_equal(Lo["dl1"], Lg["dl1"])
+        if l < ho.nlevels - 1:
+            assert np.array_equal(Lo["agg"], Lg["agg"])
+
+
+@pytest.mark.parametrize("smoother", [rs.SM_BJ, rs.SM_DILU])
+@pytest.mark.parametrize("method", [rs.ABF, rs.QIMPES])
+def test_smoother_factors(method, smoother):
+    p = _prob((20, 20, 10), sigma=1.5)
+    A = oracle.assemble(p)
+    Mo = oracle.CPR(A, method=method, smoother=smoother)
+    B = upload(A)
+    Mg = rs.cpr_setup(B, rs.decouple(B, method, 64), rs.cpr_opts(smoother=smoother))
+    assert np.array_equal(rs.cpr_smoother_get(Mg), Mo.dinv2())
+
+
+def test_vcycle():
+    p = _prob((33, 17, 9), sigma=2.0, shale=0.1)
+    A = oracle.assemble(p)
+    Mo = oracle.CPR(A, coarse_n=50)
+    B = upload(A)
+    Mg = rs.cpr_setup(B, rs.decouple(B, rs.ABF, 64), rs.cpr_opts(coarse_n=50))
+    b = np.random.default_rng(5).standard_normal(A.n)
+    x = torch.empty(A.n, dtype=torch.float64, device="cuda")
+    rs.cpr_vcycle(Mg, dev(b), x)
+    ref = Mo.amg().vcycle(b)
+    assert relerr(x.cpu().numpy(), ref) <= 1e-11
+
+
+@pytest.mark.parametrize("smoother", [rs.SM_BJ, rs.SM_DILU])
+@pytest.mark.parametrize("method", [rs.ABF, rs.QIMPES])
+@pytest.mark.parametrize("dims", [(20, 20, 10), (7, 1, 5), (1, 1, 1)])
+def test_cpr_apply(method, smoother, dims):
+    p = _prob(dims, sigma=1.5)
+    A = oracle.assemble(p)
+    Mo = oracle.CPR(A, method=method, smoother=smoother)
+    B = upload(A)
+    Mg = rs.cpr_setup(B, rs.decouple(B, method, 64), rs.cpr_opts(smoother=smoother))
+    r = np.random.default_rng(7).standard_normal(4 * A.n)
+    z = torch.empty(4 * A.n, dtype=torch.float64, device="cuda")
+    rs.cpr_apply(Mg, dev(r), z)
+    assert relerr(z.cpu().numpy(), Mo.apply(r)) <= 1e-10
+
+
+def test_cpr_apply_fp32_close_to_fp64():
+    p = _prob((20, 20, 10), sigma=1.5)
+    A = oracle.assemble(p)
+    Mo = oracle.CPR(A)
+    B = upload(A)
+    Mg = rs.cpr_setup(B, rs.decouple(B, rs.ABF, 32))
+    r = np.random.default_rng(7).standard_normal(4 * A.n)
+    z = torch.empty(4 * A.n, dtype=torch.float64, device="cuda")
+    rs.cpr_apply(Mg, dev(r), z)
+    assert relerr(z.cpu().numpy(), Mo.apply(r)) <= 1e-4
+
+
+@pytest.mark.parametrize("cfg", [0])
+@pytest.mark.parametrize("prec", [64, 32])
+def test_gmres_solution(cfg, prec):
+    p = synth.config(cfg)
+    A = oracle.assemble(p)
+    xo, io = oracle.gmres(A, p.b, oracle.CPR(A), rtol=1e-13, maxit=300)
+    B = upload(A)
+    M = rs.cpr_setup(B, rs.decouple(B, rs.ABF, prec))
+    x = torch.zeros(4 * A.n, dtype=torch.float64, device="cuda")
+    info = rs.gmres_solve(B, M, dev(p.b), x, rs.gmres_opts(rtol=1e-8))
+    xg = x.cpu().numpy()
+    true = np.linalg.norm(p.b - oracle.spmv(A, xg)) / np.linalg.norm(p.b)
+    assert info["return"] == 0 and true <= 1e-8 and abs(true - info["relres"]) <= 1e-12
+    assert relerr(xg, xo) <= 1e-5
+    if prec == 64:
+        xo8, io8 = oracle.gmres(A, p.b, oracle.CPR(A), rtol=1e-8)
+        assert info["iters"] == io8["iters"]
+
+
+def test_gmres_deterministic_and_status():
+    p = synth.config(0)
+    A = oracle.assemble(p)
+    B = upload(A)
+    M = rs.cpr_setup(B, rs.decouple(B, rs.ABF, 64))
+    b = dev(p.b)
+    xs = []
+    for _ in range(2):
+        x = torch.zeros_like(b)
+        rs.gmres_solve(B, M, b, x)
+        xs.append(x.cpu().numpy())
+    assert np.array_equal(xs[0], xs[1])
+    x = torch.zeros_like(b)
+    info = rs.gmres_solve(B, M, b, x, rs.gmres_opts(maxit=1, rtol=1e-14))
+    assert info["return"] == 1 and info["iters"] == 1
+    bb = b.clone(); bb[5] = float("nan")
+    info = rs.gmres_solve(B, M, bb, torch.zeros_like(b), check=False)
+    assert info["return"] == -5
+    info = rs.gmres_solve(B, M, torch.zeros_like(b), x)
+    assert info["return"] == 0 and info["iters"] == 0 and not x.any()

@@ -203,9 +203,8 @@ __global__ void k_mis_decide(int n, int level, const uint64_t *__restrict__ m2, 
     else if (m == prio(v, level)) state[v] = ST_ROOT;
     else left = 1;
   }
-  // one atomic per wave
-  unsigned long long bal = __ballot(left);
-  if ((threadIdx.x & 63) == 0 && bal) atomicAdd(undecided, __popcll(bal));
+  // one plain store per block that still has undecided vertices
+  if (__syncthreads_or(left) && threadIdx.x == 0) *undecided = 1;
 }
 
 __global__ void k_root_flag(int n, const uint8_t *__restrict__ state, int32_t *__restrict__ f) {
@@ -499,10 +498,14 @@ __global__ void k_dense_mv(int n, const double *__restrict__ Ci, const T *__rest
 }  // namespace
 
 // ---------------------------------------------------------------------------
-static rs_status level_alloc_work(amg_level *L, int prec) {
+static rs_status level_alloc_work(amg_level *L, int prec, int64_t guard, hipStream_t s) {
   size_t es = prec == 64 ? sizeof(double) : sizeof(float);
   RS_TRY(L->b.alloc(es * (L->n + 1)));
-  RS_TRY(L->x.alloc(es * (L->n + 1)));
+  // the fine level's iterate is read at every stencil neighbour of every cell
+  // by the second stage; zero guard planes make those reads in-bounds
+  RS_TRY(L->x.alloc(es * (L->n + 1 + 2 * guard)));
+  L->xoff = guard;
+  if (guard) RS_HIP(hipMemsetAsync(L->x.p, 0, es * (L->n + 1 + 2 * guard), s));
   RS_TRY(L->r.alloc(es * (L->n + 1)));
   RS_TRY(L->dl1.alloc(es * (L->n + 1)));
   if (prec == 32) {
@@ -520,7 +523,7 @@ rs_status rs_amg_build(rs_cpr_s *M, hipStream_t s) {
   for (int l = 0;; ++l) {
     amg_level *L = M->lev[l];
     int n = L->n;
-    RS_TRY(level_alloc_work(L, prec));
+    RS_TRY(level_alloc_work(L, prec, l == 0 ? M->A->g.nxy : 0, s));
     RS_TRY(L->agg.alloc(sizeof(int32_t) * (n + 1)));
     if (prec == 64) k_l1diag<double><<<rs_grid(n), RS_BLOCK, 0, s>>>(n, L->rp.as<int32_t>(), L->ci.as<int32_t>(), L->a.as<double>(), L->dl1.as<double>());
     else k_l1diag<float><<<rs_grid(n), RS_BLOCK, 0, s>>>(n, L->rp.as<int32_t>(), L->ci.as<int32_t>(), L->a.as<double>(), L->dl1.as<float>());
@@ -658,16 +661,16 @@ static rs_status vcycle_t(rs_cpr_s *M, hipStream_t s) {
   amg_level *C = M->lev[nl - 1];
   const T *ca = (M->prec == 64) ? (const T *)C->a.p : (const T *)C->ap.p;
   if (M->coarse_lu) {
-    k_dense_mv<T><<<rs_grid(C->n, 4), 256, 0, s>>>(C->n, M->cinv.as<double>(), C->b.as<T>(), C->x.as<T>());
+    k_dense_mv<T><<<rs_grid(C->n, 4), 256, 0, s>>>(C->n, M->cinv.as<double>(), C->b.as<T>(), C->xp<T>());
   } else {
-    T *xa = C->x.as<T>(), *xb = C->r.as<T>();
+    T *xa = C->xp<T>(), *xb = C->r.as<T>();
     for (int sw = 0; sw < M->o.coarse_sweeps; ++sw) {
       k_vc_jacobi<T><<<rs_grid(C->n), RS_BLOCK, 0, s>>>(C->n, C->rp.as<int32_t>(), C->ci.as<int32_t>(), ca,
                                                         C->dl1.as<T>(), C->b.as<T>(), xb, xa, sw == 0);
       T *t = xa; xa = xb; xb = t;
     }
-    if (xb != C->x.as<T>())
-      RS_HIP(hipMemcpyAsync(C->x.p, xb, sizeof(T) * C->n, hipMemcpyDeviceToDevice, s));
+    if (xb != C->xp<T>())
+      RS_HIP(hipMemcpyAsync(C->xp<T>(), xb, sizeof(T) * C->n, hipMemcpyDeviceToDevice, s));
   }
   // ascend
   for (int l = nl - 2; l >= 0; --l) {
@@ -675,7 +678,7 @@ static rs_status vcycle_t(rs_cpr_s *M, hipStream_t s) {
     const T *a = (M->prec == 64) ? (const T *)L->a.p : (const T *)L->ap.p;
     k_vc_post<T><<<rs_grid(L->n), RS_BLOCK, 0, s>>>(L->n, L->rp.as<int32_t>(), L->ci.as<int32_t>(), a,
                                                    L->dl1.as<T>(), L->agg.as<int32_t>(), L->b.as<T>(),
-                                                   Cl->x.as<T>(), L->x.as<T>());
+                                                   Cl->xp<T>(), L->xp<T>());
   }
   RS_HIP(hipGetLastError());
   return RS_OK;
@@ -718,11 +721,11 @@ extern "C" rs_status rs_cpr_vcycle(rs_cpr M, const double *d_b, double *d_x, voi
   if (M->prec == 64) {
     RS_HIP(hipMemcpyAsync(L->b.p, d_b, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
     RS_TRY(rs_vcycle_run(M, s));
-    RS_HIP(hipMemcpyAsync(d_x, L->x.p, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    RS_HIP(hipMemcpyAsync(d_x, L->xp<double>(), sizeof(double) * n, hipMemcpyDeviceToDevice, s));
   } else {
     k_from_f64<float><<<rs_grid(n), RS_BLOCK, 0, s>>>(n, d_b, L->b.as<float>());
     RS_TRY(rs_vcycle_run(M, s));
-    k_to_f64<float><<<rs_grid(n), RS_BLOCK, 0, s>>>(n, L->x.as<float>(), d_x);
+    k_to_f64<float><<<rs_grid(n), RS_BLOCK, 0, s>>>(n, L->xp<float>(), d_x);
     RS_HIP(hipGetLastError());
   }
   return RS_OK;

@@ -13,12 +13,10 @@
 //
 // Block ILU(0) on the 7-point block pattern only modifies the diagonal
 // blocks (no fill position lies on the pattern): D_i = A~_ii - sum over the
-// lower neighbours k of A~_ik D_k^{-1} A~_ki.  Natural (cell) order makes
-// cells with equal i+j+k independent, so setup, forward and backward sweeps
-// run one hyperplane per launch, four lanes per cell (one block row each,
-// partial results exchanged by lane shuffles).  The residual update r~2 is
-// fused into the forward sweep and the prolongation Pi_p x_p into the
-// backward sweep, so r~2 and the uncorrected z are never written.
+// lower neighbours k of A~_ik D_k^{-1} A~_ki.  Its factorisation and sweeps
+// are the pipelined kernels of dilu.hip; the residual update r~2 is fused
+// into the forward sweep and the prolongation Pi_p x_p into the backward
+// sweep, so r~2 and the corrected z are never stored separately.
 #include "rs_internal.h"
 #include <math.h>
 
@@ -74,57 +72,6 @@ __global__ void k_bj_setup(int64_t n, const T *__restrict__ t7, T *__restrict__ 
   for (int e = 0; e < 16; ++e) dinv2[c * 16 + e] = (T)R[e >> 2][e & 3];
 }
 
-// DILU setup for the cells of hyperplane i+j+k = lvl, one thread per cell.
-template <class T>
-__global__ void k_dilu_setup(int nx, int ny, int nz, int lvl, const T *__restrict__ t7,
-                             T *__restrict__ dinv2, int *__restrict__ flag) {
-#pragma clang fp contract(off)
-  int jk = blockIdx.x * blockDim.x + threadIdx.x;
-  if (jk >= ny * nz) return;
-  int j = jk % ny, k = jk / ny, i = lvl - j - k;
-  if (i < 0 || i >= nx) return;
-  int64_t nxy = (int64_t)nx * ny, n = nxy * nz;
-  int64_t c = i + nx * (j + (int64_t)ny * k);
-  double D[4][4];
-  ld16<T>(t7 + (3 * n + c) * 16, D);
-#pragma unroll
-  for (int s = 0; s < 3; ++s) {
-    if (!in_grid(s, i, j, k, nx, ny, nz)) continue;
-    int64_t q = nbr_of(c, s, nx, nxy);
-    double Dq[4][4], Aqc[4][4], Acq[4][4], T1[4][4];
-    ld16<T>(dinv2 + q * 16, Dq);
-    ld16<T>(t7 + ((int64_t)(6 - s) * n + q) * 16, Aqc);
-    ld16<T>(t7 + ((int64_t)s * n + c) * 16, Acq);
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-#pragma unroll
-      for (int cc = 0; cc < 4; ++cc) {
-        double v = 0.0;
-#pragma unroll
-        for (int m = 0; m < 4; ++m) v = v + Dq[r][m] * Aqc[m][cc];
-        T1[r][cc] = v;
-      }
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-#pragma unroll
-      for (int cc = 0; cc < 4; ++cc) {
-        double v = 0.0;
-#pragma unroll
-        for (int m = 0; m < 4; ++m) v = v + Acq[r][m] * T1[m][cc];
-        D[r][cc] = D[r][cc] - v;
-      }
-  }
-  double R[4][4];
-#pragma unroll
-  for (int r = 0; r < 4; ++r)
-#pragma unroll
-    for (int q = 0; q < 4; ++q) R[r][q] = (r == q) ? 1.0 : 0.0;
-  int f = gje4<4>(D, R);
-  if (f) atomicOr(flag, f);
-#pragma unroll
-  for (int e = 0; e < 16; ++e) dinv2[c * 16 + e] = (T)R[e >> 2][e & 3];
-}
-
 // ---- apply -------------------------------------------------------------------
 template <class T> __device__ __forceinline__ T ldin(const double *p) { return (T)*p; }
 
@@ -155,7 +102,7 @@ __device__ __forceinline__ T resid2(int64_t n, int64_t c, int row, int64_t nx, i
   for (int s = 0; s < 7; ++s) {
     int64_t q = nbr_of(c, s, nx, nxy);
     q = (q < 0 || q >= n) ? c : q;           // off-grid col0 entries are zero
-    v = v - col0[((int64_t)s * n + c) * 4 + row] * xp[q];
+    v = v - col0[c * 32 + 8 * row + s] * xp[q];
   }
   return v;
 }
@@ -185,70 +132,6 @@ __global__ __launch_bounds__(256) void k_bj_apply(int64_t n, int64_t nx, int64_t
   T o = group_mv<T>(dinv2 + c * 16 + 4 * row, v);
   if (row == 0) o = o + xp[c];
   if (ok) z[t] = o;
-}
-
-// DILU forward sweep on hyperplane lvl:
-//   y_c = D_c^{-1} (r~2_c - sum_{lower k} A~_ck y_k)
-template <class T>
-__global__ __launch_bounds__(256) void k_dilu_fwd(int nx, int ny, int nz, int lvl,
-                                                   const T *__restrict__ t7, const T *__restrict__ dinv2,
-                                                   const T *__restrict__ rt, const T *__restrict__ col0,
-                                                   const T *__restrict__ xp, T *__restrict__ y) {
-  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int jk = (int)(t >> 2), row = (int)(t & 3);
-  int j = jk % ny, k = jk / ny, i = lvl - j - k;
-  bool ok = jk < ny * nz && i >= 0 && i < nx;
-  int64_t nxy = (int64_t)nx * ny, n = nxy * nz;
-  int64_t c = ok ? i + nx * (j + (int64_t)ny * k) : 0;
-  T v = resid2<T>(n, c, row, nx, nxy, rt, col0, xp);
-#pragma unroll
-  for (int s = 0; s < 3; ++s) {
-    if (ok && in_grid(s, i, j, k, nx, ny, nz)) {
-      int64_t q = nbr_of(c, s, nx, nxy);
-      const T *a = t7 + ((int64_t)s * n + c) * 16 + 4 * row;
-      const T *yq = y + 4 * q;
-      T u = 0;
-#pragma unroll
-      for (int m = 0; m < 4; ++m) u = fma(a[m], yq[m], u);
-      v = v - u;
-    }
-  }
-  T o = group_mv<T>(dinv2 + c * 16 + 4 * row, v);
-  if (ok) y[4 * c + row] = o;
-}
-
-// DILU backward sweep on hyperplane lvl:
-//   z_c = y_c - D_c^{-1} sum_{upper k} A~_ck z_k;   out_c = z_c + Pi_p x_p
-template <class T>
-__global__ __launch_bounds__(256) void k_dilu_bwd(int nx, int ny, int nz, int lvl,
-                                                   const T *__restrict__ t7, const T *__restrict__ dinv2,
-                                                   const T *__restrict__ y, const T *__restrict__ xp,
-                                                   T *__restrict__ z, T *__restrict__ out) {
-  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int jk = (int)(t >> 2), row = (int)(t & 3);
-  int j = jk % ny, k = jk / ny, i = lvl - j - k;
-  bool ok = jk < ny * nz && i >= 0 && i < nx;
-  int64_t nxy = (int64_t)nx * ny, n = nxy * nz;
-  int64_t c = ok ? i + nx * (j + (int64_t)ny * k) : 0;
-  T v = 0;
-#pragma unroll
-  for (int s = 4; s < 7; ++s) {
-    if (ok && in_grid(s, i, j, k, nx, ny, nz)) {
-      int64_t q = nbr_of(c, s, nx, nxy);
-      const T *a = t7 + ((int64_t)s * n + c) * 16 + 4 * row;
-      const T *zq = z + 4 * q;
-      T u = 0;
-#pragma unroll
-      for (int m = 0; m < 4; ++m) u = fma(a[m], zq[m], u);
-      v = v + u;
-    }
-  }
-  T w = group_mv<T>(dinv2 + c * 16 + 4 * row, v);
-  if (ok) {
-    T zc = y[4 * c + row] - w;
-    z[4 * c + row] = zc;
-    out[4 * c + row] = row == 0 ? zc + xp[c] : zc;
-  }
 }
 
 template <class T>
@@ -309,12 +192,8 @@ extern "C" rs_status rs_cpr_setup(rs_bsr A, rs_dcpl D, const rs_cpr_opts *o, voi
       if (M->prec == 64) k_bj_setup<double><<<rs_grid(n), RS_BLOCK, 0, s>>>(n, D->t7.as<double>(), M->dinv2.as<double>(), flag.as<int>());
       else k_bj_setup<float><<<rs_grid(n), RS_BLOCK, 0, s>>>(n, D->t7.as<float>(), M->dinv2.as<float>(), flag.as<int>());
     } else {
-      int nlv = g.nx + g.ny + g.nz - 2;
-      unsigned grid = rs_grid((int64_t)g.ny * g.nz);
-      for (int l = 0; l < nlv; ++l) {
-        if (M->prec == 64) k_dilu_setup<double><<<grid, RS_BLOCK, 0, s>>>(g.nx, g.ny, g.nz, l, D->t7.as<double>(), M->dinv2.as<double>(), flag.as<int>());
-        else k_dilu_setup<float><<<grid, RS_BLOCK, 0, s>>>(g.nx, g.ny, g.nz, l, D->t7.as<float>(), M->dinv2.as<float>(), flag.as<int>());
-      }
+      if ((st = rs_dilu_prepare(M)) != RS_OK) break;
+      if ((st = rs_dilu_setup_run(M, flag.as<int>(), s)) != RS_OK) break;
     }
     int h = 0;
     if (hipGetLastError() != hipSuccess ||
@@ -322,6 +201,7 @@ extern "C" rs_status rs_cpr_setup(rs_bsr A, rs_dcpl D, const rs_cpr_opts *o, voi
         hipStreamSynchronize(s) != hipSuccess) { st = RS_E_HIP; break; }
     if (h & RSF_NONFINITE) st = RS_E_NONFINITE;
     else if (h & RSF_SINGULAR) st = RS_E_SINGULAR;
+    else st = rs_dilu_check(M, s);
   } while (0);
   if (st != RS_OK) { delete M; return st; }
   *out = M;
@@ -337,19 +217,12 @@ static rs_status cpr_apply_t(rs_cpr_s *M, const double *r, T *z, hipStream_t s) 
   k_cpr_in<T><<<rs_grid(4 * n), RS_BLOCK, 0, s>>>(n, M->D->dinv.as<T>(), r, M->rt.as<T>(), L0->b.as<T>());
   RS_HIP(hipGetLastError());
   RS_TRY(rs_vcycle_run(M, s));
-  const T *xp = L0->x.as<T>();
+  const T *xp = L0->xp<T>();
   if (M->o.smoother == RS_SM_BJ) {
     k_bj_apply<T><<<rs_grid(4 * n), RS_BLOCK, 0, s>>>(n, g.nx, g.nxy, M->rt.as<T>(), M->D->col0.as<T>(), xp,
                                                      M->dinv2.as<T>(), z);
   } else {
-    int nlv = g.nx + g.ny + g.nz - 2;
-    unsigned grid = rs_grid(4 * (int64_t)g.ny * g.nz);
-    for (int l = 0; l < nlv; ++l)
-      k_dilu_fwd<T><<<grid, RS_BLOCK, 0, s>>>(g.nx, g.ny, g.nz, l, M->D->t7.as<T>(), M->dinv2.as<T>(), M->rt.as<T>(),
-                                              M->D->col0.as<T>(), xp, M->yv.as<T>());
-    for (int l = nlv - 1; l >= 0; --l)
-      k_dilu_bwd<T><<<grid, RS_BLOCK, 0, s>>>(g.nx, g.ny, g.nz, l, M->D->t7.as<T>(), M->dinv2.as<T>(), M->yv.as<T>(),
-                                              xp, M->zt.as<T>(), z);
+    RS_TRY(rs_dilu_apply_run<T>(M, xp, z, s));
   }
   RS_HIP(hipGetLastError());
   return RS_OK;
@@ -363,7 +236,10 @@ rs_status rs_cpr_apply_any(rs_cpr_s *M, const double *r, void *z, int zprec, hip
 extern "C" rs_status rs_cpr_apply(rs_cpr M, const double *d_r, double *d_z, void *stream) {
   if (!M || !d_r || !d_z || d_r == d_z) return RS_E_ARG;
   hipStream_t s = rs_stream(stream);
-  if (M->prec == 64) return cpr_apply_t<double>(M, d_r, d_z, s);
+  if (M->prec == 64) {
+    RS_TRY(cpr_apply_t<double>(M, d_r, d_z, s));
+    return rs_dilu_check(M, s);
+  }
   int64_t m = 4 * M->A->g.n;
   dbuf tmp;
   RS_TRY(tmp.alloc(sizeof(float) * m));
@@ -371,7 +247,7 @@ extern "C" rs_status rs_cpr_apply(rs_cpr M, const double *d_r, double *d_z, void
   k_vec_to_f64<float><<<rs_grid(m), RS_BLOCK, 0, s>>>(m, tmp.as<float>(), d_z);
   RS_HIP(hipGetLastError());
   RS_HIP(hipStreamSynchronize(s));   // tmp is freed on return
-  return RS_OK;
+  return rs_dilu_check(M, s);
 }
 
 extern "C" rs_status rs_cpr_smoother_get(rs_cpr M, double *h_dinv2) {

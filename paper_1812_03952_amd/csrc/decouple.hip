@@ -27,9 +27,14 @@ __device__ __forceinline__ void store_block(T *__restrict__ t7, T *__restrict__ 
   for (int r = 0; r < 4; ++r)
 #pragma unroll
     for (int q = 0; q < 4; ++q) o[4 * r + q] = (T)R[r][q];
-  T *o0 = col0 + ((int64_t)s * n + c) * 4;
+  // column 0 of every block of the row, per block row: [c][row][slot], 8 wide
+  T *o0 = col0 + c * 32 + s;
 #pragma unroll
-  for (int r = 0; r < 4; ++r) o0[r] = (T)R[r][0];
+  for (int r = 0; r < 4; ++r) o0[8 * r] = (T)R[r][0];
+  if (s == 6) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) o0[8 * r + 1] = (T)0;
+  }
   ap7[(int64_t)s * n + c] = R[0][0];
 }
 
@@ -137,7 +142,7 @@ extern "C" rs_status rs_decouple(rs_bsr A, int method, int prec, void *stream, r
     if ((st = D->t7.alloc(es * 7 * n * 16)) != RS_OK) break;
     if ((st = D->dinv.alloc(es * n * 16)) != RS_OK) break;
     if ((st = D->ap7.alloc(sizeof(double) * 7 * n)) != RS_OK) break;
-    if ((st = D->col0.alloc(es * 7 * n * 4)) != RS_OK) break;
+    if ((st = D->col0.alloc(es * 32 * n)) != RS_OK) break;
     dbuf flag;
     if ((st = flag.alloc(sizeof(int))) != RS_OK) break;
     if (hipMemsetAsync(flag.p, 0, sizeof(int), s) != hipSuccess) { st = RS_E_HIP; break; }

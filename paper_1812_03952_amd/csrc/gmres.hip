@@ -312,6 +312,10 @@ static rs_status gmres_t(rs_bsr_s *A, rs_cpr_s *M, const double *b, double *x, c
     }
     est = (bnorm > 0.0) ? est / bnorm : 0.0;
   } while (0);
+  if (st == RS_OK || st == RS_NOT_CONVERGED) {
+    rs_status e = rs_dilu_check(M, s);
+    if (e != RS_OK) st = e;
+  }
   float ms = 0.f;
   (void)hipEventRecord(e1, s);
   (void)hipEventSynchronize(e1);

@@ -77,7 +77,7 @@ struct rs_dcpl_s {
   dbuf t7;      // decoupled blocks [7][n][16], prec
   dbuf dinv;    // D^{-1} [n][16], prec
   dbuf ap7;     // pressure entries [7][n], double
-  dbuf col0;    // column 0 of the decoupled blocks [7][n][4], prec
+  dbuf col0;    // column 0 of the decoupled blocks, [n][4 rows][8] (slots 0-6, pad), prec
 };
 
 struct amg_level {
@@ -90,6 +90,8 @@ struct amg_level {
   dbuf agg;           // int32 aggregate per row (-1 none)
   dbuf mptr, mem;     // members of each aggregate (ascending), for restriction
   dbuf b, x, r;       // cycle work vectors, apply precision
+  int64_t xoff = 0;   // x starts xoff elements into its buffer (zero guard planes at level 0)
+  template <class T> T *xp() const { return x.as<T>() + xoff; }
 };
 
 struct rs_cpr_s {
@@ -103,6 +105,10 @@ struct rs_cpr_s {
   dbuf cinv;          // dense inverse of the coarsest level (double)
   dbuf cb, cx;        // coarsest rhs / solution in double
   dbuf dinv2;         // second-stage block inverses [n][16], prec
+  // pipelined DILU sweeps: brick size, brick grid, ticket order, progress
+  int pb = 0, pnj = 0, pnk = 0;
+  uint32_t pepoch = 0;       // tag of the last pipelined sweep
+  dbuf pord, pdone, pctl, pxch;
   // CPR work
   dbuf rt, bp, xp, yv, zt;   // prec vectors
   // GMRES work (allocated on first solve)
@@ -119,3 +125,7 @@ rs_status rs_cpr_apply_any(rs_cpr_s *M, const double *r, void *z, int zprec,
                            hipStream_t s);
 rs_status rs_vcycle_run(rs_cpr_s *M, hipStream_t s);
 rs_status rs_transpose7(const rs_bsr_s *A, rs_bsr_s *At, hipStream_t s);
+rs_status rs_dilu_prepare(rs_cpr_s *M);
+rs_status rs_dilu_setup_run(rs_cpr_s *M, int *flag, hipStream_t s);
+template <class T> rs_status rs_dilu_apply_run(rs_cpr_s *M, const T *xp, T *out, hipStream_t s);
+rs_status rs_dilu_check(rs_cpr_s *M, hipStream_t s);

@@ -23,7 +23,7 @@ _SO = os.path.join(_HERE, "liboracle.so")
 _SRC = ["bsr.c", "decouple.c", "amg.c", "cpr.c"]
 
 ABF, QIMPES = 0, 1
-SM_BJ, SM_DILU = 0, 1
+SM_BJ, SM_DILU, SM_RAS = 0, 1, 2
 
 
 def build() -> str:
@@ -90,8 +90,11 @@ def lib():
         L.or_amg_vcycle.restype = None
         L.or_amg_free.argtypes = [C.c_void_p]
         L.or_amg_free.restype = None
-        L.or_cpr_setup.argtypes = [C.c_int, _i32p, _i32p, _f64p, C.c_int, C.c_int,
+        L.or_cpr_setup.argtypes = [C.c_int, _i32p, _i32p, _f64p, C.c_int, C.c_int, C.c_int64,
                                    C.POINTER(AmgOpts), C.POINTER(C.c_int)]
+        L.or_ras_restrict.argtypes = [C.c_int, C.c_int64, _i32p, _i32p, _f64p] + [C.c_void_p] * 3
+        L.or_free.argtypes = [C.c_void_p]
+        L.or_free.restype = None
         L.or_cpr_setup.restype = C.c_void_p
         L.or_cpr_apply.argtypes = [C.c_void_p, _f64p, _f64p]
         L.or_cpr_apply.restype = None
@@ -213,6 +216,25 @@ def dilu_setup(At: BSR):
     return d.reshape(-1, 4, 4)
 
 
+def ras_restrict(At: BSR, sub=None) -> BSR:
+    """The block-diagonal restriction of At to subdomains of `sub` consecutive
+    cells (default nx*ny: the xy-layers); zero-overlap RAS is DILU of it."""
+    L = lib()
+    sub = At.nx * At.ny if sub is None else int(sub)
+    prp, pci, pv = C.c_void_p(), C.c_void_p(), C.c_void_p()
+    _check(L.or_ras_restrict(At.n, sub, At.rp, At.ci, At.v.reshape(-1), C.byref(prp), C.byref(pci),
+                             C.byref(pv)), "or_ras_restrict")
+    try:
+        rp = np.ctypeslib.as_array(C.cast(prp, C.POINTER(C.c_int)), shape=(At.n + 1,)).copy()
+        nk = int(rp[-1])
+        ci = np.ctypeslib.as_array(C.cast(pci, C.POINTER(C.c_int)), shape=(max(nk, 1),))[:nk].copy()
+        v = np.ctypeslib.as_array(C.cast(pv, C.POINTER(C.c_double)), shape=(max(nk, 1) * 16,))[:16 * nk].copy()
+    finally:
+        for q in (prp, pci, pv):
+            L.or_free(q)
+    return BSR(At.nx, At.ny, At.nz, rp, ci, v)
+
+
 def bj_apply(dinv2, r):
     z = np.zeros_like(r, dtype=np.float64)
     lib().or_bj_apply(dinv2.shape[0], _c(dinv2, np.float64).reshape(-1), _c(r, np.float64), z)
@@ -289,12 +311,14 @@ class AMG:
 class CPR:
     """Two-stage CPR preconditioner on a block matrix."""
 
-    def __init__(self, A: BSR, method=ABF, smoother=SM_DILU, **amg_kw):
+    def __init__(self, A: BSR, method=ABF, smoother=SM_DILU, sub=None, **amg_kw):
+        """sub: cells per RAS subdomain (SM_RAS only); default nx*ny, the xy-layers."""
         L = lib()
         self.A = A
         self._o = amg_opts(**amg_kw)
         st = C.c_int(0)
-        self._h = L.or_cpr_setup(A.n, A.rp, A.ci, A.v.reshape(-1), method, smoother,
+        sub = A.nx * A.ny if sub is None else int(sub)
+        self._h = L.or_cpr_setup(A.n, A.rp, A.ci, A.v.reshape(-1), method, smoother, sub,
                                  C.byref(self._o), C.byref(st))
         if st.value != 0:
             L.or_cpr_free(self._h)

@@ -16,6 +16,8 @@ struct or_cpr {
   double *dinv;            /* decoupling D_i^{-1} */
   double *ap;              /* pressure matrix values */
   double *dinv2;           /* second-stage block inverses */
+  int *rp2, *ci2;          /* RAS: pattern restricted to the subdomains */
+  double *vt2;             /* RAS: decoupled blocks on that pattern */
   or_amg *amg;
 };
 
@@ -28,11 +30,14 @@ struct or_cpr {
  *    r~  = D^{-1} r                          (decoupling, Eq. decoupled-eq)
  *    x_p = Vcycle(A_p, Pi_r r~)              (Pi_r: unknown 0 of each cell)
  *    r~2 = r~ - A~ Pi_p x_p                  (Pi_p: inject into unknown 0)
- *    z   = M2^{-1} r~2 + Pi_p x_p            (M2: block-Jacobi or DILU on A~)
+ *    z   = M2^{-1} r~2 + Pi_p x_p            (M2: block-Jacobi, DILU, or
+ *                                             zero-overlap RAS with DILU in
+ *                                             each subdomain, on A~)
  * Pinned by the dense composition [C + M2^{-1}(I - A~ C)] D^{-1} with
  * C = Pi_p A_p^{-1} Pi_r when the AMG is a single exact level. */
 or_cpr *or_cpr_setup(int n, const int *rp, const int *ci, const double *v,
-                     int method, int smoother, const or_amg_opts *ao, int *status) {
+                     int method, int smoother, int64_t sub, const or_amg_opts *ao,
+                     int *status) {
   or_cpr *M = (or_cpr *)calloc(1, sizeof(or_cpr));
   int64_t nnzb = rp[n];
   M->n = n; M->smoother = smoother; M->nnzb = nnzb;
@@ -48,8 +53,13 @@ or_cpr *or_cpr_setup(int n, const int *rp, const int *ci, const double *v,
   *status = or_decouple(n, rp, ci, v, method, M->vt, M->dinv);
   if (*status != OR_OK) return M;
   or_extract_pressure(nnzb, M->vt, M->ap);
-  *status = (smoother == OR_SM_DILU) ? or_dilu_setup(n, rp, ci, M->vt, M->dinv2)
-                                     : or_bj_setup(n, rp, ci, M->vt, M->dinv2);
+  if (smoother == OR_SM_RAS) {
+    *status = or_ras_restrict(n, sub, rp, ci, M->vt, &M->rp2, &M->ci2, &M->vt2);
+    if (*status == OR_OK) *status = or_dilu_setup(n, M->rp2, M->ci2, M->vt2, M->dinv2);
+  } else {
+    *status = (smoother == OR_SM_DILU) ? or_dilu_setup(n, rp, ci, M->vt, M->dinv2)
+                                       : or_bj_setup(n, rp, ci, M->vt, M->dinv2);
+  }
   if (*status != OR_OK) return M;
   M->amg = or_amg_setup(n, rp, ci, M->ap, ao, status);
   return M;
@@ -74,6 +84,7 @@ void or_cpr_apply(const or_cpr *M, const double *r, double *z) {
       for (int a = 0; a < 4; ++a) rt[4 * i + a] = rt[4 * i + a] - M->vt[16 * p + 4 * a] * xj;
     }
   if (M->smoother == OR_SM_DILU) or_dilu_apply(n, M->rp, M->ci, M->vt, M->dinv2, rt, z);
+  else if (M->smoother == OR_SM_RAS) or_dilu_apply(n, M->rp2, M->ci2, M->vt2, M->dinv2, rt, z);
   else or_bj_apply(n, M->dinv2, rt, z);
   for (int64_t i = 0; i < n; ++i) z[4 * i] = z[4 * i] + xp[i];
   free(rt); free(bp); free(xp);
@@ -88,6 +99,7 @@ const or_amg *or_cpr_amg(const or_cpr *M) { return M->amg; }
 void or_cpr_free(or_cpr *M) {
   if (!M) return;
   free(M->rpc); free(M->cic); free(M->vt); free(M->dinv); free(M->ap); free(M->dinv2);
+  free(M->rp2); free(M->ci2); free(M->vt2);
   or_amg_free(M->amg);
   free(M);
 }

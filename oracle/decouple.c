@@ -239,3 +239,40 @@ void or_dilu_apply(int n, const int *rp, const int *ci, const double *vt,
     for (int c = 0; c < 4; ++c) z[4 * i + c] = y[4 * i + c] - u[c];
   }
 }
+
+/* Restricted additive Schwarz with zero overlap (Section "Preconditioners":
+ * with overlap 0 RAS is block Jacobi over the subdomains) and block ILU(0)
+ * as the subdomain solver (BILU(k), k = 0, named in the same section).
+ * Subdomain of cell i is floor(i / sub); with cells numbered i fastest and
+ * sub = nx*ny the subdomains are the xy-layers of the grid.  Block Jacobi over
+ * subdomains means every block that couples two subdomains is left out, so
+ * the preconditioner is the DILU of the restricted matrix built here.
+ * Returns a new CSR pattern and values (caller frees *rp2, *ci2, *vt2).
+ * Pinned by: sub >= n gives the global DILU; each subdomain solved on its
+ * own extracted matrix gives the same result; the dense product
+ * (D+L)D^{-1}(D+U) equals the restricted matrix on its pattern. */
+int or_ras_restrict(int n, int64_t sub, const int *rp, const int *ci, const double *vt,
+                    int **rp2, int **ci2, double **vt2) {
+  if (sub < 1) return OR_E_ARG;
+  int64_t keep = 0;
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t p = rp[i]; p < rp[i + 1]; ++p)
+      if (ci[p] / sub == i / sub) ++keep;
+  *rp2 = (int *)malloc(sizeof(int) * ((size_t)n + 1));
+  *ci2 = (int *)malloc(sizeof(int) * (size_t)(keep > 0 ? keep : 1));
+  *vt2 = (double *)malloc(sizeof(double) * 16 * (size_t)(keep > 0 ? keep : 1));
+  int64_t q = 0;
+  (*rp2)[0] = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    for (int64_t p = rp[i]; p < rp[i + 1]; ++p) {
+      if (ci[p] / sub != i / sub) continue;
+      (*ci2)[q] = ci[p];
+      memcpy(&(*vt2)[16 * q], &vt[16 * p], 16 * sizeof(double));
+      ++q;
+    }
+    (*rp2)[i + 1] = (int)q;
+  }
+  return OR_OK;
+}
+
+void or_free(void *p) { free(p); }

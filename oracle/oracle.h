@@ -55,6 +55,9 @@ int or_dilu_setup(int n, const int *rp, const int *ci, const double *vt, double 
 void or_bj_apply(int n, const double *dinv2, const double *r, double *z);
 void or_dilu_apply(int n, const int *rp, const int *ci, const double *vt,
                    const double *dinv2, const double *r, double *z);
+int or_ras_restrict(int n, int64_t sub, const int *rp, const int *ci, const double *vt,
+                    int **rp2, int **ci2, double **vt2);
+void or_free(void *p);
 
 /* ---- aggregation AMG on the pressure matrix (Fig. fig-ds-amg-par parameters) */
 typedef struct or_amg or_amg;
@@ -81,9 +84,11 @@ void or_amg_free(or_amg *h);
 /* ---- two-stage CPR preconditioner (Section "Preconditioners") */
 #define OR_SM_BJ 0
 #define OR_SM_DILU 1
+#define OR_SM_RAS 2     /* zero-overlap RAS, DILU in each subdomain of sub cells */
 typedef struct or_cpr or_cpr;
 or_cpr *or_cpr_setup(int n, const int *rp, const int *ci, const double *v,
-                     int method, int smoother, const or_amg_opts *ao, int *status);
+                     int method, int smoother, int64_t sub, const or_amg_opts *ao,
+                     int *status);
 void or_cpr_apply(const or_cpr *M, const double *r, double *z);
 const double *or_cpr_decoupled(const or_cpr *M);
 const double *or_cpr_dinv(const or_cpr *M);

@@ -17,7 +17,7 @@ def _blockdiag(blocks):
     return D
 
 
-@pytest.mark.parametrize("smoother", [oracle.SM_BJ, oracle.SM_DILU])
+@pytest.mark.parametrize("smoother", [oracle.SM_BJ, oracle.SM_DILU, oracle.SM_RAS])
 @pytest.mark.parametrize("method", [oracle.ABF, oracle.QIMPES])
 def test_cpr_dense_composition(method, smoother):
     """With a single-level (exact) pressure solve:
@@ -39,8 +39,11 @@ def test_cpr_dense_composition(method, smoother):
     else:
         d2 = M.dinv2()
         lower = np.tril(Dt, -1) * 0; upper = lower.copy()
+        nxy = p.nx * p.ny
         for i in range(n):
             for j in range(n):
+                if smoother == oracle.SM_RAS and i // nxy != j // nxy:
+                    continue        # zero-overlap RAS: no coupling between layers
                 if j < i: lower[4*i:4*i+4, 4*j:4*j+4] = Dt[4*i:4*i+4, 4*j:4*j+4]
                 if j > i: upper[4*i:4*i+4, 4*j:4*j+4] = Dt[4*i:4*i+4, 4*j:4*j+4]
         Dblk = _blockdiag(np.linalg.inv(d2))
@@ -65,8 +68,9 @@ def test_cpr_gmres_vs_dense_lu(dims, sigma):
                    wells=synth.wells_vertical_pair(*dims, (0, 0), (dims[0] - 1, dims[1] - 1)))
     A = oracle.assemble(p)
     xref = np.linalg.solve(A.dense(), p.b)
-    for method in (oracle.ABF, oracle.QIMPES):
-        M = oracle.CPR(A, method=method, coarse_n=20)
+    for method, smoother in ((oracle.ABF, oracle.SM_DILU), (oracle.QIMPES, oracle.SM_DILU),
+                             (oracle.ABF, oracle.SM_RAS)):
+        M = oracle.CPR(A, method=method, smoother=smoother, coarse_n=20)
         x, info = oracle.gmres(A, p.b, M, rtol=1e-12, maxit=200)
         assert info["status"] == 0 and info["relres"] <= 1e-12
         r = p.b - A.dense() @ x

@@ -21,6 +21,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# second stage: zero-overlap RAS over xy-layers with DILU inside (default),
+# DILU of the whole matrix, or block Jacobi
+SMOOTHERS = {"bj": 0, "dilu": 1, "ras": 2}
+SMOOTHER_NAMES = {"bj": "block Jacobi", "dilu": "DILU", "ras": "RAS(0, xy-layers) + DILU"}
 
 
 def log(msg):
@@ -48,7 +52,7 @@ def spmv_roofline(rs, A, n, reps=20):
     return ms, nbytes
 
 
-def run_variant(rs, dp, A, prec, steps, warmup, tag):
+def run_variant(rs, dp, A, prec, steps, warmup, tag, smoother):
     import torch
     times, infos, phases = [], [], []
     for it in range(warmup + steps):
@@ -57,7 +61,7 @@ def run_variant(rs, dp, A, prec, steps, warmup, tag):
         rs.bsr_update(A, dp.vals)
         D = rs.decouple(A, rs.ABF, prec)
         t1 = time.perf_counter()
-        M = rs.cpr_setup(A, D)
+        M = rs.cpr_setup(A, D, rs.cpr_opts(smoother=smoother))
         t2 = time.perf_counter()
         x = torch.zeros_like(dp.b)
         info = rs.gmres_solve(A, M, dp.b, x)
@@ -73,12 +77,12 @@ def run_variant(rs, dp, A, prec, steps, warmup, tag):
     return times, infos, phases
 
 
-def cpu_baseline(prob):
+def cpu_baseline(prob, smoother):
     import oracle
     t0 = time.perf_counter()
     A = oracle.assemble(prob)
     t1 = time.perf_counter()
-    M = oracle.CPR(A)
+    M = oracle.CPR(A, smoother=smoother)
     x, info = oracle.gmres(A, prob.b, M, rtol=1e-8)
     t2 = time.perf_counter()
     return t2 - t1, info
@@ -92,6 +96,7 @@ def main():
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--smoother", choices=list(SMOOTHERS), default="ras")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -116,7 +121,7 @@ def main():
     res = {}
     variants = [("fp32", 32)] + ([] if args.no_fp64 else [("fp64", 64)])
     for tag, prec in variants:
-        times, infos, phases = run_variant(rs, dp, A, prec, args.steps, args.warmup, tag)
+        times, infos, phases = run_variant(rs, dp, A, prec, args.steps, args.warmup, tag, SMOOTHERS[args.smoother])
         tmax = max(times)
         tmed = float(np.median(times))
         ph = np.median(np.array(phases), axis=0)
@@ -142,8 +147,9 @@ def main():
         "dtype": "fp32-preconditioner/fp64-gmres",
         "data": "synthetic",
         "config": {"workload": f"{prob.name}: 4x4-block 7-point Jacobian, {n} cells, {4 * n} unknowns, "
-                               f"nnzb {A.nnzb}; ABF + CPR(AMG V-cycle, DILU) + FGMRES(30), rtol 1e-8",
-                   "cells": n, "unknowns": 4 * n, "nnzb": A.nnzb, "restart": 30, "rtol": 1e-8},
+                               f"nnzb {A.nnzb}; ABF + CPR(AMG V-cycle, {SMOOTHER_NAMES[args.smoother]}) + FGMRES(30), rtol 1e-8",
+                   "cells": n, "unknowns": 4 * n, "nnzb": A.nnzb, "restart": 30, "rtol": 1e-8,
+                   "smoother": args.smoother},
         "fp32_precond": res["fp32"],
         "fp64": res.get("fp64"),
         "spmv": {"ms": spmv_ms, "GB_per_s": achieved, "bytes": spmv_bytes},
@@ -153,7 +159,7 @@ def main():
     }
     if not args.no_cpu_baseline:
         log("cpu baseline: FP64 oracle, one full solve of the same system (1 thread) ...")
-        t_cpu, info = cpu_baseline(prob)
+        t_cpu, info = cpu_baseline(prob, SMOOTHERS[args.smoother])
         out["cpu_baseline"] = {"value": 1.0 / t_cpu, "unit": "solves/s", "cores": 1, "kind": "oracle",
                                "sample": f"one FP64 CPR-GMRES solve of {prob.name} (decouple, AMG/DILU setup, "
                                          f"GMRES to 1e-8: {info['iters']} iterations), {t_cpu:.1f} s"}

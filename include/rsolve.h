@@ -53,11 +53,14 @@ typedef enum {
 
 #define RS_ABF 0        /* alternate block factorisation, Eq. decoupled-abf */
 #define RS_QIMPES 1     /* quasi-IMPES: pressure row of A_ii^{-1} only      */
-#define RS_SM_BJ 0      /* second stage: block Jacobi (RAS, overlap 0)      */
-#define RS_SM_DILU 1    /* second stage: block ILU(0), natural order        */
+#define RS_SM_BJ 0      /* second stage: block Jacobi over cells (RAS, overlap 0, one cell each) */
+#define RS_SM_DILU 1    /* second stage: block ILU(0) of the whole matrix, natural order        */
+#define RS_SM_RAS 2     /* second stage: RAS, overlap 0, one xy-layer per subdomain, block
+                           ILU(0) in each (Section "Preconditioners"); needs ny <= 480 with
+                           FP64 storage, ny <= 960 with FP32, else RS_E_ARG               */
 
 typedef struct {
-  int smoother;        /* RS_SM_BJ or RS_SM_DILU (default DILU)                  */
+  int smoother;        /* RS_SM_BJ, RS_SM_DILU or RS_SM_RAS (default DILU)       */
   double theta;        /* AMG strength threshold (default 0.5, Fig. fig-ds-amg-par) */
   double max_row_sum;  /* AMG weak-row threshold (default 0.9, same figure)       */
   int coarse_n;        /* stop coarsening at <= this many rows (default 500)     */

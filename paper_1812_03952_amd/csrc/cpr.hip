@@ -168,7 +168,8 @@ extern "C" rs_status rs_cpr_setup(rs_bsr A, rs_dcpl D, const rs_cpr_opts *o, voi
   *out = nullptr;
   rs_cpr_opts opts;
   if (o) opts = *o; else rs_cpr_opts_default(&opts);
-  if ((opts.smoother != RS_SM_BJ && opts.smoother != RS_SM_DILU) || opts.coarse_n < 1 ||
+  if ((opts.smoother != RS_SM_BJ && opts.smoother != RS_SM_DILU && opts.smoother != RS_SM_RAS) ||
+      (opts.smoother == RS_SM_RAS && rs_ras_check_shape(A->g, D->prec) != RS_OK) || opts.coarse_n < 1 ||
       opts.max_levels < 1 || opts.lu_max < 1 || opts.lu_max > 8192 || opts.coarse_sweeps < 1)
     return RS_E_ARG;
   hipStream_t s = rs_stream(stream);
@@ -191,6 +192,8 @@ extern "C" rs_status rs_cpr_setup(rs_bsr A, rs_dcpl D, const rs_cpr_opts *o, voi
     if (opts.smoother == RS_SM_BJ) {
       if (M->prec == 64) k_bj_setup<double><<<rs_grid(n), RS_BLOCK, 0, s>>>(n, D->t7.as<double>(), M->dinv2.as<double>(), flag.as<int>());
       else k_bj_setup<float><<<rs_grid(n), RS_BLOCK, 0, s>>>(n, D->t7.as<float>(), M->dinv2.as<float>(), flag.as<int>());
+    } else if (opts.smoother == RS_SM_RAS) {
+      if ((st = rs_ras_setup_run(M, flag.as<int>(), s)) != RS_OK) break;
     } else {
       if ((st = rs_dilu_prepare(M)) != RS_OK) break;
       if ((st = rs_dilu_setup_run(M, flag.as<int>(), s)) != RS_OK) break;
@@ -221,6 +224,8 @@ static rs_status cpr_apply_t(rs_cpr_s *M, const double *r, T *z, hipStream_t s) 
   if (M->o.smoother == RS_SM_BJ) {
     k_bj_apply<T><<<rs_grid(4 * n), RS_BLOCK, 0, s>>>(n, g.nx, g.nxy, M->rt.as<T>(), M->D->col0.as<T>(), xp,
                                                      M->dinv2.as<T>(), z);
+  } else if (M->o.smoother == RS_SM_RAS) {
+    RS_TRY(rs_ras_apply_run<T>(M, xp, z, s));
   } else {
     RS_TRY(rs_dilu_apply_run<T>(M, xp, z, s));
   }

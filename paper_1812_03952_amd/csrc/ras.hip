@@ -1,0 +1,469 @@
+// ras.hip -- second stage as zero-overlap restricted additive Schwarz (RAS)
+// with the xy-layers of the grid as subdomains and block ILU(0) inside each
+// layer (Section "Preconditioners": RAS with overlap 0 is block Jacobi over
+// the subdomains; the subdomain problems are solved by ILU(k) or block
+// ILU(k), here k = 0).  On the 7-point block pattern in natural order block
+// ILU(0) only modifies the diagonal blocks, so it is DILU; restricted to a
+// layer the stencil is the in-plane 5-point one.
+//
+// Layers are independent, so each is one workgroup and no workgroup ever
+// waits on another.  Inside a layer the recurrences run over the lines
+// i + j = lambda (nx + ny - 1 levels): the thread group of line j handles
+// cell (lambda - j, j) at level lambda, reads the previous level's values of
+// its own line and of line j-1 (j+1 backward) from LDS, and one barrier
+// separates the levels.  The factorisation uses one thread per cell in FP64.
+//
+// The sweeps are written with D^{-1} folded in, which is the same operator
+// in exact arithmetic:
+//   forward   y = rh - Lh_y y_{c-nx} - Lh_x y_{c-1},   rh = D^{-1} r~2,
+//   backward  z = y  - Uh_x z_{c+1}  - Uh_y z_{c+nx},
+// with Lh = D^{-1} L and Uh = D^{-1} U formed once at set-up.  Their operands
+// are stored level by level ("wavefront order": within a layer, by lambda,
+// then by j), so the cells of one level are contiguous in memory; rh is
+// formed (and permuted) by an elementwise pass over the whole grid.
+//
+// Layout: A~ blocks by stencil slot t7[7][n][16] (slots -z -y -x self +x +y
+// +z, zeros off-grid), D^{-1} blocks dinv2[n][16]; scaled blocks
+// blk[4][n][16] (Lh_y, Lh_x, Uh_x, Uh_y) in wavefront order; vectors [n][4];
+// all in the preconditioner's precision.
+#include "rs_internal.h"
+#include <math.h>
+
+namespace {
+#pragma clang fp contract(off)
+#include "block4.h"
+#pragma clang fp contract(fast)
+#include "quad4.h"
+
+// ---- wavefront order --------------------------------------------------------
+// Number of cells (i, j) of an nx x ny layer with i + j < lambda.
+__device__ __forceinline__ int64_t tri(int64_t x) { return x > 0 ? x * (x + 1) / 2 : 0; }
+__device__ __forceinline__ int64_t wf_off(int lam, int nx, int ny) {
+  return tri(lam) - tri(lam - nx) - tri(lam - ny) + tri(lam - nx - ny);
+}
+__device__ __forceinline__ int wf_jlo(int lam, int nx) { return max(0, lam - nx + 1); }
+// position of cell (i, j) of its layer in wavefront order
+__device__ __forceinline__ int64_t wf_pos(int i, int j, int nx, int ny) {
+  return wf_off(i + j, nx, ny) + (j - wf_jlo(i + j, nx));
+}
+
+// ---- right-hand side of the forward sweep, per (cell, block row) ------------
+// rh = D^{-1} (r~ - A~[:,0] x_p) in wavefront order, and x_p permuted alike.
+// x_p carries nx*ny zero guard entries on each side, so every stencil
+// neighbour is in bounds, and off-grid column-0 entries are zero.
+template <class T>
+__global__ __launch_bounds__(256) void k_ras_in(int nx, int ny, int64_t n, const T *__restrict__ rt,
+                                                const T *__restrict__ col0, const T *__restrict__ xp,
+                                                const T *__restrict__ dinv2, T *__restrict__ rh,
+                                                T *__restrict__ xpw) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 4 * n) return;                               // whole quads (4n and the block are multiples of 4)
+  const int64_t nxy = (int64_t)nx * ny, c = t >> 2;
+  const int row = (int)(t & 3);
+  const int64_t off[7] = {-nxy, -(int64_t)nx, -1, 0, 1, (int64_t)nx, nxy};
+  T col[8], dv[4];
+  ld8v(col0 + c * 32 + 8 * row, col);
+  ld4v(dinv2 + c * 16 + 4 * row, dv);
+  T v = rt[t];
+#pragma unroll
+  for (int s = 0; s < 7; ++s) v = v - col[s] * xp[c + off[s]];
+  const T o = quad_mv<T>(dv, v);
+  const int64_t k = c / nxy, rem = c - k * nxy;
+  const int j = (int)(rem / nx), i = (int)(rem - (int64_t)j * nx);
+  const int64_t p = k * nxy + wf_pos(i, j, nx, ny);
+  rh[4 * p + row] = o;
+  if (row == 0) xpw[p] = xp[c];
+}
+
+// ---- factorisation, per layer: D_c = A~_cc - sum_{q in {c-nx, c-1}} A~_cq D_q^{-1} A~_qc
+// One thread per line and U lines per thread (line j = tid + blockDim*u).
+// The D^{-1} block of the cell before in x stays in the thread's registers;
+// that of the cell before in y comes from LDS (one slot per line: a barrier
+// after the reads of a level and one after its writes).  Same operation
+// order as the definition; D^{-1} blocks are rounded to the stored precision
+// before they are used by the next cells.
+template <class T, int U>
+__global__ __launch_bounds__(256) void k_ras_setup(int nx, int ny, int64_t n, const T *__restrict__ t7,
+                                                   T *__restrict__ dinv2, int *__restrict__ flag) {
+#pragma clang fp contract(off)
+  extern __shared__ __align__(16) unsigned char smem[];
+  T *ring = (T *)smem;                                  // [ny][16]
+  const int tid = threadIdx.x, TB = blockDim.x;
+  const int64_t nxy = (int64_t)nx * ny, cl = nxy * blockIdx.x;
+  const int Lv = nx + ny - 1;
+  const T *Ad = t7 + 3 * n * 16, *Ay = t7 + 1 * n * 16, *Ax = t7 + 2 * n * 16;
+  const T *Upx = t7 + 4 * n * 16, *Upy = t7 + 5 * n * 16;
+  T own[U][16];
+  int bad = 0;
+  for (int lam = 0; lam < Lv; ++lam) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int j = tid + TB * u, i = lam - j;
+      if (j < ny && i >= 0 && i < nx) {
+        const int64_t c = cl + (int64_t)j * nx + i;
+        double D[4][4];
+#pragma unroll
+        for (int e = 0; e < 16; ++e) D[e >> 2][e & 3] = (double)Ad[c * 16 + e];
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {                   // -y, then -x (ascending column)
+          if (s == 0 ? j == 0 : i == 0) continue;
+          const int64_t q = s == 0 ? c - nx : c - 1;
+          double Dq[4][4], Aqc[4][4], Acq[4][4], T1[4][4];
+#pragma unroll
+          for (int e = 0; e < 16; ++e) {
+            Dq[e >> 2][e & 3] = (double)(s == 0 ? ring[(j - 1) * 16 + e] : own[u][e]);
+            Aqc[e >> 2][e & 3] = (double)(s == 0 ? Upy : Upx)[q * 16 + e];
+            Acq[e >> 2][e & 3] = (double)(s == 0 ? Ay : Ax)[c * 16 + e];
+          }
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int cc = 0; cc < 4; ++cc) {
+              double v = 0.0;
+#pragma unroll
+              for (int m = 0; m < 4; ++m) v = v + Dq[r][m] * Aqc[m][cc];
+              T1[r][cc] = v;
+            }
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int cc = 0; cc < 4; ++cc) {
+              double v = 0.0;
+#pragma unroll
+              for (int m = 0; m < 4; ++m) v = v + Acq[r][m] * T1[m][cc];
+              D[r][cc] = D[r][cc] - v;
+            }
+        }
+        double R[4][4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+          for (int cc = 0; cc < 4; ++cc) R[r][cc] = (r == cc) ? 1.0 : 0.0;
+        bad |= gje4<4>(D, R);
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+          const T v = (T)R[e >> 2][e & 3];
+          own[u][e] = v;
+          dinv2[c * 16 + e] = v;
+        }
+      }
+    }
+    __syncthreads();                                    // level lam-1 reads done
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int j = tid + TB * u, i = lam - j;
+      if (j < ny && i >= 0 && i < nx) {
+#pragma unroll
+        for (int e = 0; e < 16; ++e) ring[j * 16 + e] = own[u][e];
+      }
+    }
+    __syncthreads();                                    // level lam visible
+  }
+  if (bad) atomicOr(flag, bad);
+}
+
+// ---- scaled blocks for the sweeps, per (cell, block row) ---------------------
+// blk[b][p] = D_c^{-1} A~_{c, nb(b)} for b = 0..3: -y, -x, +x, +y (slots 1, 2,
+// 4, 5), at the cell's wavefront position p; FP64 products rounded once.
+template <class T>
+__global__ __launch_bounds__(256) void k_ras_scale(int nx, int ny, int64_t n, const T *__restrict__ t7,
+                                                   const T *__restrict__ dinv2, T *__restrict__ blk) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 4 * n) return;
+  const int64_t nxy = (int64_t)nx * ny, c = t >> 2;
+  const int row = (int)(t & 3);
+  double dv[4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) dv[m] = (double)dinv2[c * 16 + 4 * row + m];
+  const int64_t k = c / nxy, rem = c - k * nxy;
+  const int j = (int)(rem / nx), i = (int)(rem - (int64_t)j * nx);
+  const int64_t p = k * nxy + wf_pos(i, j, nx, ny);
+  const int slot[4] = {1, 2, 4, 5};
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const T *a = t7 + ((int64_t)slot[b] * n + c) * 16;
+    T o[4];
+#pragma unroll
+    for (int cc = 0; cc < 4; ++cc) {
+      double v = 0.0;
+#pragma unroll
+      for (int m = 0; m < 4; ++m) v = fma(dv[m], (double)a[4 * m + cc], v);
+      o[cc] = (T)v;
+    }
+#pragma unroll
+    for (int cc = 0; cc < 4; ++cc) blk[((int64_t)b * n + p) * 16 + 4 * row + cc] = o[cc];
+  }
+}
+
+// ---- sweeps ----------------------------------------------------------------
+// A sweep workgroup has 4*LW compute lanes (lines j = q + LW*u, q = lane/4,
+// U passes per level) and one writer wave.  Compute waves only load from
+// global memory and keep the loads of the next P levels in flight in
+// registers; their results go to an LDS ring of two levels.  The writer wave
+// only stores: during level lambda it copies the outputs of level lambda-1
+// from the ring to global memory.  On this architecture one counter tracks
+// both loads and stores of a wave, and with both kinds in flight a wave can
+// only wait for all of them; keeping them in different waves lets a compute
+// wave wait for just the oldest of its prefetched loads.
+template <class T> struct vec4t;
+template <> struct vec4t<float> { typedef float4 type; };
+template <> struct vec4t<double> { typedef double4 type; };
+
+// copy the outputs of level m (lines j with 0 <= m - j < nx) from an LDS ring
+// buffer [ny][4] to out: in wavefront order (WF) or natural order
+template <class T, bool WF>
+__device__ __forceinline__ void ras_write_level(int m, int nx, int ny, int64_t cl, const T *__restrict__ src,
+                                                T *__restrict__ out, int w, int nw) {
+  if (m < 0) return;
+  const int jlo = max(0, m - nx + 1), jhi = min(ny - 1, m);
+  const int64_t base = cl + (WF ? wf_off(m, nx, ny) - jlo : 0);
+  for (int j = jlo + w; j <= jhi; j += nw) {
+    const int64_t c = WF ? base + j : cl + (int64_t)j * nx + (m - j);
+    *(typename vec4t<T>::type *)(out + 4 * c) = *(const typename vec4t<T>::type *)(src + 4 * j);
+  }
+}
+
+// The loads that refill a level's registers must come after the level's last
+// use of them.  Loads from read-only restrict arguments are free to move, and
+// once hoisted above that use the registers rotate through copies that wait
+// for every load in flight; an empty asm statement that takes the level's
+// result and "changes" the refill's line index pins the order (it emits no
+// instruction).
+template <class T> __device__ __forceinline__ void order_after(int &idx, T tok) {
+  asm volatile("" : "+v"(idx) : "v"(tok));
+}
+
+// wavefront index (within the grid) of line j at level lam, clamped to the
+// level's cells and the level to the layer's levels: always in bounds
+__device__ __forceinline__ int64_t wf_clamped(int64_t cl, int lam, int j, int nx, int ny) {
+  lam = min(max(lam, 0), nx + ny - 2);
+  const int jlo = wf_jlo(lam, nx), jhi = min(ny - 1, lam);
+  return cl + wf_off(lam, nx, ny) + (min(max(j, jlo), jhi) - jlo);
+}
+
+// forward, per layer: y = rh - Lh_y y_{c-nx} - Lh_x y_{c-1}
+// The level count is padded to a multiple of P and every load and LDS read is
+// issued unconditionally at clamped (in-bounds) addresses, with the terms of
+// inactive cells dropped by selects: then every path through a level issues
+// the same loads, and the compiler waits only for the level's own data.
+template <class T> struct ras_fpre { T r, a1[4], a2[4]; };
+
+template <class T, int U, int P>
+__global__ __launch_bounds__(1024) void k_ras_fwd(int nx, int ny, int64_t n, int LW, const T *__restrict__ blk,
+                                                  const T *__restrict__ rh, T *__restrict__ y) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  T *ring = (T *)smem;                                  // [2][ny][4]
+  const int q = threadIdx.x >> 2, row = threadIdx.x & 3;
+  const bool compute = (int)threadIdx.x < 4 * LW;       // wave-uniform (LW is a multiple of 16)
+  const int w = threadIdx.x - 4 * LW, nw = blockDim.x - 4 * LW;
+  const int64_t nxy = (int64_t)nx * ny, cl = nxy * blockIdx.x;
+  const int Lv = nx + ny - 1, Lpad = (Lv + P - 1) / P * P;
+  if (!compute) {
+    // the writer wave: its own level loop with one barrier per level, like
+    // the compute waves, so that no path mixes its stores with the loads
+    for (int lam = 0; lam < Lpad; ++lam) {
+      ras_write_level<T, true>(lam - 1, nx, ny, cl, ring + ((lam & 1) ^ 1) * ny * 4, y, w, nw);
+      __syncthreads();
+    }
+    ras_write_level<T, true>(Lpad - 1, nx, ny, cl, ring + ((Lpad - 1) & 1) * ny * 4, y, w, nw);
+    return;
+  }
+  const T *By = blk, *Bx = blk + n * 16;
+  ras_fpre<T> R[P][U];
+  auto load = [&](int lam, ras_fpre<T> &p, int u, T tok) {
+    int j = q + LW * u;
+    order_after(j, tok);
+    const int64_t c = wf_clamped(cl, lam, j, nx, ny);
+    p.r = rh[4 * c + row];
+    ld4v(By + c * 16 + 4 * row, p.a1);
+    ld4v(Bx + c * 16 + 4 * row, p.a2);
+  };
+#pragma unroll
+  for (int d = 0; d < P; ++d)
+#pragma unroll
+    for (int u = 0; u < U; ++u) load(d, R[d][u], u, (T)0);
+  for (int lam0 = 0; lam0 < Lpad; lam0 += P) {
+#pragma unroll
+    for (int d = 0; d < P; ++d) {
+      const int lam = lam0 + d;
+      T *cur = ring + (lam & 1) * ny * 4;
+      const T *prv = ring + ((lam & 1) ^ 1) * ny * 4;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int j = q + LW * u, i = lam - j;
+        const bool act = j < ny && i >= 0 && i < nx;
+        const int jr = min(j, ny - 1);
+        T yy[4], yx[4];
+        ld4v(prv + 4 * max(jr - 1, 0), yy);
+        ld4v(prv + 4 * jr, yx);
+        const T ty = dot4(R[d][u].a1, yy), tx = dot4(R[d][u].a2, yx);
+        T v = R[d][u].r;
+        v = (act && j > 0) ? v - ty : v;
+        v = (act && i > 0) ? v - tx : v;
+        if (act) cur[4 * j + row] = v;
+        load(lam + P, R[d][u], u, v);
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// backward, per layer: z = y - Uh_x z_{c+1} - Uh_y z_{c+nx}, output z + Pi_p x_p
+// (x_p added to unknown 0) in natural order through a second LDS ring
+template <class T> struct ras_bpre { T yc, xpc, a4[4], a5[4]; };
+
+template <class T, int U, int P>
+__global__ __launch_bounds__(1024) void k_ras_bwd(int nx, int ny, int64_t n, int LW, const T *__restrict__ blk,
+                                                  const T *__restrict__ y, const T *__restrict__ xpw,
+                                                  T *__restrict__ out) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  T *ring = (T *)smem;                                  // [2][ny][4]: z
+  T *oring = ring + 2 * ny * 4;                         // [2][ny][4]: output
+  const int q = threadIdx.x >> 2, row = threadIdx.x & 3;
+  const bool compute = (int)threadIdx.x < 4 * LW;
+  const int w = threadIdx.x - 4 * LW, nw = blockDim.x - 4 * LW;
+  const int64_t nxy = (int64_t)nx * ny, cl = nxy * blockIdx.x;
+  const int Lv = nx + ny - 1, Lpad = (Lv + P - 1) / P * P;
+  if (!compute) {
+    // step s handles level Lv-1-s; the writer copies the previous step's
+    for (int step = 0; step < Lpad; ++step) {
+      ras_write_level<T, false>(step >= 1 ? Lv - step : -1, nx, ny, cl, oring + ((step & 1) ^ 1) * ny * 4, out, w,
+                                nw);
+      __syncthreads();
+    }
+    ras_write_level<T, false>(Lv - Lpad, nx, ny, cl, oring + ((Lpad - 1) & 1) * ny * 4, out, w, nw);
+    return;
+  }
+  const T *Bx = blk + 2 * n * 16, *By = blk + 3 * n * 16;
+  ras_bpre<T> R[P][U];
+  auto load = [&](int step, ras_bpre<T> &p, int u, T tok) {
+    int j = q + LW * u;
+    order_after(j, tok);
+    const int64_t c = wf_clamped(cl, Lv - 1 - step, j, nx, ny);
+    p.yc = y[4 * c + row];
+    p.xpc = xpw[c];
+    ld4v(Bx + c * 16 + 4 * row, p.a4);
+    ld4v(By + c * 16 + 4 * row, p.a5);
+  };
+#pragma unroll
+  for (int d = 0; d < P; ++d)
+#pragma unroll
+    for (int u = 0; u < U; ++u) load(d, R[d][u], u, (T)0);
+  for (int s0 = 0; s0 < Lpad; s0 += P) {
+#pragma unroll
+    for (int d = 0; d < P; ++d) {
+      const int step = s0 + d;
+      const int lam = Lv - 1 - step;
+      const int cb = (step & 1) * ny * 4, pb = ((step & 1) ^ 1) * ny * 4;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int j = q + LW * u, i = lam - j;
+        const bool act = j < ny && i >= 0 && i < nx;
+        const int jr = min(j, ny - 1);
+        T zx[4], zy[4];
+        ld4v(ring + pb + 4 * jr, zx);
+        ld4v(ring + pb + 4 * min(jr + 1, ny - 1), zy);
+        const T tx = dot4(R[d][u].a4, zx), ty = dot4(R[d][u].a5, zy);
+        T zc = R[d][u].yc;
+        zc = (act && i < nx - 1) ? zc - tx : zc;
+        zc = (act && j < ny - 1) ? zc - ty : zc;
+        if (act) {
+          ring[cb + 4 * j + row] = zc;
+          oring[cb + 4 * j + row] = row == 0 ? zc + R[d][u].xpc : zc;
+        }
+        load(step + P, R[d][u], u, zc);
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// launch shape of the sweeps: LW lines per pass (a multiple of 16, so whole
+// waves), U passes per level
+struct sweep_shape { int lw, u; };
+static sweep_shape ras_sweep_shape(int ny) {
+  int u = 1;
+  while ((ny + u - 1) / u > 240) u *= 2;
+  int lw = (ny + u - 1) / u;
+  lw = (lw + 15) / 16 * 16;
+  return {lw, u};
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+rs_status rs_ras_check_shape(const grid3 &g, int prec) {
+  // sweeps: at most 240 lines per pass and 2 passes (FP64) or 4 (FP32);
+  // LDS: the factorisation keeps one D^{-1} block per line, the backward
+  // sweep four 4-vectors per line, both within 64 KiB
+  int max_ny = prec == 64 ? 480 : 960;
+  if (g.ny < 1 || g.ny > max_ny || g.nx < 1 || g.nz < 1) return RS_E_ARG;
+  return RS_OK;
+}
+
+rs_status rs_ras_setup_run(rs_cpr_s *M, int *flag, hipStream_t s) {
+  const grid3 &g = M->A->g;
+  RS_TRY(rs_ras_check_shape(g, M->prec));
+  int tb = g.ny < 256 ? (g.ny + 63) / 64 * 64 : 256;
+  int u = (g.ny + tb - 1) / tb;                       // 1, 2 or 4
+  size_t es = M->prec == 64 ? sizeof(double) : sizeof(float);
+  size_t lds = es * 16 * (size_t)g.ny;
+  RS_TRY(M->rblk.alloc(es * 4 * 16 * (size_t)g.n));
+  RS_TRY(M->rxp.alloc(es * (size_t)g.n));
+#define RS_RSET(T, UU)                                                                                \
+  k_ras_setup<T, UU><<<g.nz, tb, lds, s>>>(g.nx, g.ny, g.n, M->D->t7.as<T>(), M->dinv2.as<T>(), flag)
+  if (M->prec == 64) {
+    if (u == 1) RS_RSET(double, 1); else RS_RSET(double, 2);
+  } else {
+    if (u == 1) RS_RSET(float, 1); else if (u == 2) RS_RSET(float, 2); else RS_RSET(float, 4);
+  }
+#undef RS_RSET
+  RS_HIP(hipGetLastError());
+  if (M->prec == 64)
+    k_ras_scale<double><<<rs_grid(4 * g.n), RS_BLOCK, 0, s>>>(g.nx, g.ny, g.n, M->D->t7.as<double>(),
+                                                             M->dinv2.as<double>(), M->rblk.as<double>());
+  else
+    k_ras_scale<float><<<rs_grid(4 * g.n), RS_BLOCK, 0, s>>>(g.nx, g.ny, g.n, M->D->t7.as<float>(),
+                                                            M->dinv2.as<float>(), M->rblk.as<float>());
+  RS_HIP(hipGetLastError());
+  return RS_OK;
+}
+
+template <class T>
+rs_status rs_ras_apply_run(rs_cpr_s *M, const T *xp, T *out, hipStream_t s) {
+  const grid3 &g = M->A->g;
+  const rs_dcpl_s *D = M->D;
+  // rh goes to zt, the forward result (wavefront order) to yv
+  T *rh = M->zt.as<T>(), *y = M->yv.as<T>(), *xpw = M->rxp.as<T>();
+  const T *blk = M->rblk.as<T>();
+  k_ras_in<T><<<rs_grid(4 * g.n), RS_BLOCK, 0, s>>>(g.nx, g.ny, g.n, M->rt.as<T>(), D->col0.as<T>(), xp,
+                                                    M->dinv2.as<T>(), rh, xpw);
+  RS_HIP(hipGetLastError());
+  const sweep_shape sh = ras_sweep_shape(g.ny);
+  // compute lanes (at most 960) + one writer wave
+  const int nt = 4 * sh.lw + 64;
+  // loads in flight per thread: P levels x U lines
+#define RS_RSWEEP(K, UU, PP, LDS, ...) K<T, UU, PP><<<g.nz, nt, LDS, s>>>(__VA_ARGS__)
+#define RS_RDISPATCH(K, LDS, ...)                                                                     \
+  do {                                                                                                \
+    if constexpr (sizeof(T) == 8) {                                                                   \
+      if (sh.u == 1) RS_RSWEEP(K, 1, 4, LDS, __VA_ARGS__);                                            \
+      else RS_RSWEEP(K, 2, 2, LDS, __VA_ARGS__);                                                      \
+    } else {                                                                                          \
+      if (sh.u == 1) RS_RSWEEP(K, 1, 8, LDS, __VA_ARGS__);                                            \
+      else if (sh.u == 2) RS_RSWEEP(K, 2, 4, LDS, __VA_ARGS__);                                       \
+      else RS_RSWEEP(K, 4, 2, LDS, __VA_ARGS__);                                                      \
+    }                                                                                                 \
+  } while (0)
+  const size_t ring_bytes = sizeof(T) * 8 * (size_t)g.ny;     // two levels of [ny][4]
+  RS_RDISPATCH(k_ras_fwd, ring_bytes, g.nx, g.ny, g.n, sh.lw, blk, rh, y);
+  RS_HIP(hipGetLastError());
+  RS_RDISPATCH(k_ras_bwd, 2 * ring_bytes, g.nx, g.ny, g.n, sh.lw, blk, y, xpw, out);
+  RS_HIP(hipGetLastError());
+#undef RS_RDISPATCH
+#undef RS_RSWEEP
+  return RS_OK;
+}
+
+template rs_status rs_ras_apply_run<double>(rs_cpr_s *, const double *, double *, hipStream_t);
+template rs_status rs_ras_apply_run<float>(rs_cpr_s *, const float *, float *, hipStream_t);

@@ -109,6 +109,8 @@ struct rs_cpr_s {
   int pb = 0, pnj = 0, pnk = 0;
   uint32_t pepoch = 0;       // tag of the last pipelined sweep
   dbuf pord, pdone, pctl, pxch;
+  // RAS sweeps: scaled blocks and x_p in wavefront order
+  dbuf rblk, rxp;
   // CPR work
   dbuf rt, bp, xp, yv, zt;   // prec vectors
   // GMRES work (allocated on first solve)
@@ -129,3 +131,6 @@ rs_status rs_dilu_prepare(rs_cpr_s *M);
 rs_status rs_dilu_setup_run(rs_cpr_s *M, int *flag, hipStream_t s);
 template <class T> rs_status rs_dilu_apply_run(rs_cpr_s *M, const T *xp, T *out, hipStream_t s);
 rs_status rs_dilu_check(rs_cpr_s *M, hipStream_t s);
+rs_status rs_ras_check_shape(const grid3 &g, int prec);
+rs_status rs_ras_setup_run(rs_cpr_s *M, int *flag, hipStream_t s);
+template <class T> rs_status rs_ras_apply_run(rs_cpr_s *M, const T *xp, T *out, hipStream_t s);

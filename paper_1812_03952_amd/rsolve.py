@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "librsolve.so")
 
 RS_OK, RS_NOT_CONVERGED = 0, 1
 ABF, QIMPES = 0, 1
-SM_BJ, SM_DILU = 0, 1
+SM_BJ, SM_DILU, SM_RAS = 0, 1, 2
 
 
 class RsError(RuntimeError):

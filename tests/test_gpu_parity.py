@@ -113,7 +113,7 @@ def test_amg_hierarchy_bitwise(dims, sigma):
             assert np.array_equal(Lo["agg"], Lg["agg"])
 
 
-@pytest.mark.parametrize("smoother", [rs.SM_BJ, rs.SM_DILU])
+@pytest.mark.parametrize("smoother", [rs.SM_BJ, rs.SM_DILU, rs.SM_RAS])
 @pytest.mark.parametrize("method", [rs.ABF, rs.QIMPES])
 def test_smoother_factors(method, smoother):
     p = _prob((20, 20, 10), sigma=1.5)
@@ -137,7 +137,7 @@ def test_vcycle():
     assert relerr(x.cpu().numpy(), ref) <= 1e-11
 
 
-@pytest.mark.parametrize("smoother", [rs.SM_BJ, rs.SM_DILU])
+@pytest.mark.parametrize("smoother", [rs.SM_BJ, rs.SM_DILU, rs.SM_RAS])
 @pytest.mark.parametrize("method", [rs.ABF, rs.QIMPES])
 @pytest.mark.parametrize("dims", [(20, 20, 10), (7, 1, 5), (1, 1, 1)])
 def test_cpr_apply(method, smoother, dims):
@@ -152,6 +152,34 @@ def test_cpr_apply(method, smoother, dims):
     assert relerr(z.cpu().numpy(), Mo.apply(r)) <= 1e-10
 
 
+@pytest.mark.parametrize("dims,prec", [((5, 300, 2), 64), ((3, 480, 2), 64), ((3, 520, 2), 32),
+                                       ((2, 960, 1), 32), ((37, 19, 3), 64), ((1, 241, 2), 32)])
+def test_ras_wide_layers(dims, prec):
+    """Layers with more lines than one pass of the sweep covers (several lines
+    per thread group) and odd extents: factors bitwise (FP64) and the apply."""
+    p = _prob(dims, sigma=1.5)
+    A = oracle.assemble(p)
+    Mo = oracle.CPR(A, smoother=oracle.SM_RAS)
+    B = upload(A)
+    Mg = rs.cpr_setup(B, rs.decouple(B, rs.ABF, prec), rs.cpr_opts(smoother=rs.SM_RAS))
+    if prec == 64:
+        assert np.array_equal(rs.cpr_smoother_get(Mg), Mo.dinv2())
+    r = np.random.default_rng(9).standard_normal(4 * A.n)
+    z = torch.empty(4 * A.n, dtype=torch.float64, device="cuda")
+    rs.cpr_apply(Mg, dev(r), z)
+    assert relerr(z.cpu().numpy(), Mo.apply(r)) <= (1e-10 if prec == 64 else 1e-4)
+
+
+def test_ras_layer_limit():
+    """Layers wider than the sweep kernels take (ny > 480 in FP64, > 960 in FP32) are refused."""
+    for ny, prec in ((481, 64), (961, 32)):
+        p = _prob((2, ny, 1), sigma=1.0)
+        A = oracle.assemble(p)
+        B = upload(A)
+        with pytest.raises(rs.RsError):
+            rs.cpr_setup(B, rs.decouple(B, rs.ABF, prec), rs.cpr_opts(smoother=rs.SM_RAS))
+
+
 def test_cpr_apply_fp32_close_to_fp64():
     p = _prob((20, 20, 10), sigma=1.5)
     A = oracle.assemble(p)
@@ -164,14 +192,15 @@ def test_cpr_apply_fp32_close_to_fp64():
     assert relerr(z.cpu().numpy(), Mo.apply(r)) <= 1e-4
 
 
+@pytest.mark.parametrize("smoother", [rs.SM_DILU, rs.SM_RAS])
 @pytest.mark.parametrize("cfg", [0])
 @pytest.mark.parametrize("prec", [64, 32])
-def test_gmres_solution(cfg, prec):
+def test_gmres_solution(cfg, prec, smoother):
     p = synth.config(cfg)
     A = oracle.assemble(p)
-    xo, io = oracle.gmres(A, p.b, oracle.CPR(A), rtol=1e-13, maxit=300)
+    xo, io = oracle.gmres(A, p.b, oracle.CPR(A, smoother=smoother), rtol=1e-13, maxit=300)
     B = upload(A)
-    M = rs.cpr_setup(B, rs.decouple(B, rs.ABF, prec))
+    M = rs.cpr_setup(B, rs.decouple(B, rs.ABF, prec), rs.cpr_opts(smoother=smoother))
     x = torch.zeros(4 * A.n, dtype=torch.float64, device="cuda")
     info = rs.gmres_solve(B, M, dev(p.b), x, rs.gmres_opts(rtol=1e-8))
     xg = x.cpu().numpy()
@@ -179,7 +208,7 @@ def test_gmres_solution(cfg, prec):
     assert info["return"] == 0 and true <= 1e-8 and abs(true - info["relres"]) <= 1e-12
     assert relerr(xg, xo) <= 1e-5
     if prec == 64:
-        xo8, io8 = oracle.gmres(A, p.b, oracle.CPR(A), rtol=1e-8)
+        xo8, io8 = oracle.gmres(A, p.b, oracle.CPR(A, smoother=smoother), rtol=1e-8)
         assert info["iters"] == io8["iters"]
 
 

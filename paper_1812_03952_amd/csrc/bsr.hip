@@ -116,8 +116,10 @@ __global__ __launch_bounds__(256) void k_spmv7(int64_t n, int64_t nx, int64_t nx
     int64_t q = slot_nbr(c, s, nx, nxy);
     q = (q < 0 || q >= n) ? c : q;           // off-grid blocks are zero
     const v2d *ap = (const v2d *)(a7 + ((int64_t)s * n + c) * 16 + 4 * r);
-    v2d a01 = __builtin_nontemporal_load(ap);
-    v2d a23 = __builtin_nontemporal_load(ap + 1);
+    // plain loads: the non-temporal hint measured about 8 points of HBM
+    // bandwidth slower here
+    v2d a01 = ap[0];
+    v2d a23 = ap[1];
     double xv[4];
     vec4_of<TX>::load(x + 4 * q, xv);
     acc = fma(a01.x, xv[0], acc);

@@ -52,6 +52,41 @@ def spmv_roofline(rs, A, n, reps=20):
     return ms, nbytes
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_spmv7_cfg2_traffic.txt")
+SPMV_SOURCE = os.path.join(ROOT, "paper_1812_03952_amd", "csrc", "bsr.hip")
+
+
+def spmv_traffic():
+    """HBM bytes per SpMV launch from the committed counter summary, or None
+    when the SpMV source has changed since the counters were taken."""
+    import hashlib
+    try:
+        kv = {}
+        for line in open(TRAFFIC_FILE):
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+        cur = hashlib.sha256(open(SPMV_SOURCE, "rb").read()).hexdigest()
+        if kv.get("source_sha256") != cur:
+            return None
+        return float(kv["traffic_bytes"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def calibration_copy():
+    """A plain copy of exactly 1 GiB (read) into 1 GiB (write), outside every
+    timed region: under rocprofv3 --pmc its FETCH_SIZE/WRITE_SIZE give the
+    scale between the counters and bytes."""
+    import torch
+    src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    torch.mul(src, 1.0, out=dst)
+    torch.cuda.synchronize()
+    del src, dst
+
+
 def run_variant(rs, dp, A, prec, steps, warmup, tag, smoother):
     import torch
     times, infos, phases = [], [], []
@@ -97,6 +132,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--smoother", choices=list(SMOOTHERS), default="ras")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run one 1 GiB copy kernel (for counter calibration under rocprofv3 --pmc)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -110,6 +147,8 @@ def main():
     from paper_1812_03952_amd import rsolve as rs
 
     torch.cuda.set_device(0)
+    if args.calib_copy:
+        calibration_copy()
     t = time.perf_counter()
     prob = synth.config(args.config)
     log(f"draws for {prob.name}: {time.perf_counter() - t:.1f} s")
@@ -155,7 +194,7 @@ def main():
         "spmv": {"ms": spmv_ms, "GB_per_s": achieved, "bytes": spmv_bytes},
         "roofline": {"bound": "hbm", "kernel": "k_spmv7<double,false> (y = A x)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": spmv_traffic()},
     }
     if not args.no_cpu_baseline:
         log("cpu baseline: FP64 oracle, one full solve of the same system (1 thread) ...")

@@ -28,9 +28,14 @@
  *   - Vectors hold 4 doubles per cell (unknown 0 is pressure), length 4*n.
  *   - Errors are returned, never raised or aborted on; rs_status_string()
  *     names them.  RS_NOT_CONVERGED is not fatal: x holds the last iterate.
+ *   - Device memory of handles comes from the library's pool: a destroyed
+ *     handle's blocks are kept and reused by later calls (see rs_pool_trim).
+ *     Reuse on the same stream is ordered by the stream; before destroying a
+ *     handle whose work may still be pending on another stream, synchronise.
  */
 #ifndef RSOLVE_H
 #define RSOLVE_H
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -187,6 +192,15 @@ rs_status rs_grad_logk(int nx, int ny, int nz, const double *d_logk, double kvkh
                        int nw, const int32_t *d_wcell, const double *d_wu,
                        const int32_t *d_row_ptr, const double *d_G, double *d_g,
                        void *stream);
+
+/* ---- device memory pool -------------------------------------------------- */
+
+/* Return every cached (unused) pool block to the HIP runtime.  Blocks held
+ * by live handles are not affected.  Call it when another allocator needs
+ * the memory; no stream work may still use a destroyed handle's memory. */
+void rs_pool_trim(void);
+/* Bytes held by live handles and bytes cached for reuse (either may be NULL). */
+void rs_pool_usage(size_t *live_bytes, size_t *cached_bytes);
 
 /* ---- inspection (copies to host; synchronise the stream) --------------- */
 

@@ -402,6 +402,59 @@ __global__ void k_gj_elim(int n, int k, double *__restrict__ G) {
   G[(int64_t)r * 2 * n + c] -= f * G[(int64_t)k * 2 * n + c];
 }
 
+// The same elimination for small n in one workgroup: the pivot search, row
+// swap, scaling and elimination of every column k run back to back with
+// barriers instead of two launches per column.  Same pivot choice (largest
+// |value|, lowest row on ties) and the same update per entry.
+constexpr int GJ_FUSED_MAX = 256;
+__global__ __launch_bounds__(1024) void k_gj_fused(int n, double *__restrict__ G, int *__restrict__ bad) {
+  __shared__ double sv[1024];
+  __shared__ int si[1024];
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int64_t ld = 2 * (int64_t)n;
+  for (int k = 0; k < n; ++k) {
+    double best = -1.0;
+    int bi = k;
+    for (int r = k + tid; r < n; r += nt) {
+      double v = fabs(G[(int64_t)r * ld + k]);
+      if (v > best) { best = v; bi = r; }
+    }
+    sv[tid] = best; si[tid] = bi;
+    __syncthreads();
+    for (int st = nt / 2; st > 0; st >>= 1) {
+      if (tid < st) {
+        if (sv[tid + st] > sv[tid] || (sv[tid + st] == sv[tid] && si[tid + st] < si[tid])) {
+          sv[tid] = sv[tid + st]; si[tid] = si[tid + st];
+        }
+      }
+      __syncthreads();
+    }
+    const int piv = si[0];
+    double *rk = G + (int64_t)k * ld, *rpv = G + (int64_t)piv * ld;
+    if (piv != k)
+      for (int c = tid; c < ld; c += nt) { double t = rk[c]; rk[c] = rpv[c]; rpv[c] = t; }
+    __syncthreads();
+    const double pv = rk[k];
+    if (tid == 0 && !(fabs(pv) > 0.0)) atomicOr(bad, 1);
+    const double inv = 1.0 / pv;
+    __syncthreads();
+    for (int c = tid; c < ld; c += nt)
+      if (c != k) rk[c] = rk[c] * inv;
+    __syncthreads();
+    if (tid == 0) rk[k] = 1.0;
+    __syncthreads();
+    const int64_t w = ld - (k + 1);
+    for (int64_t t = tid; t < (int64_t)n * w; t += nt) {
+      const int r = (int)(t / w);
+      const int c = (int)(t - (int64_t)r * w) + k + 1;
+      if (r == k) continue;
+      double f = G[(int64_t)r * ld + k];
+      G[(int64_t)r * ld + c] -= f * G[(int64_t)k * ld + c];
+    }
+    __syncthreads();
+  }
+}
+
 __global__ void k_extract_inv(int n, const double *__restrict__ G, double *__restrict__ inv) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (int64_t)n * n) return;
@@ -629,10 +682,14 @@ rs_status rs_amg_build(rs_cpr_s *M, hipStream_t s) {
     RS_TRY(M->cx.alloc(sizeof(double) * (nC + 1)));
     RS_HIP(hipMemsetAsync(flag.p, 0, sizeof(int), s));
     k_densify<<<rs_grid(nC), RS_BLOCK, 0, s>>>(nC, C->rp.as<int32_t>(), C->ci.as<int32_t>(), C->a.as<double>(), G.as<double>());
-    for (int k = 0; k < nC; ++k) {
-      k_gj_pivot<<<1, 256, 0, s>>>(nC, k, G.as<double>(), flag.as<int>());
-      int64_t work = (int64_t)nC * (2 * (int64_t)nC - (k + 1));
-      if (work > 0) k_gj_elim<<<rs_grid(work), RS_BLOCK, 0, s>>>(nC, k, G.as<double>());
+    if (nC <= GJ_FUSED_MAX) {
+      k_gj_fused<<<1, 1024, 0, s>>>(nC, G.as<double>(), flag.as<int>());
+    } else {
+      for (int k = 0; k < nC; ++k) {
+        k_gj_pivot<<<1, 256, 0, s>>>(nC, k, G.as<double>(), flag.as<int>());
+        int64_t work = (int64_t)nC * (2 * (int64_t)nC - (k + 1));
+        if (work > 0) k_gj_elim<<<rs_grid(work), RS_BLOCK, 0, s>>>(nC, k, G.as<double>());
+      }
     }
     k_extract_inv<<<rs_grid((int64_t)nC * nC), RS_BLOCK, 0, s>>>(nC, G.as<double>(), M->cinv.as<double>());
     RS_HIP(hipGetLastError());

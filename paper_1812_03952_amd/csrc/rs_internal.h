@@ -21,24 +21,31 @@
 
 static inline hipStream_t rs_stream(void *s) { return (hipStream_t)s; }
 
-// A device allocation owned by a handle.
+// Device memory comes from the library's pool (pool.hip): a freed block is
+// cached and reused by later requests of a similar size.
+void *rs_pool_get(size_t bytes, size_t *got);   // nullptr when out of memory
+void rs_pool_put(void *p, size_t bytes);
+
+// A device allocation owned by a handle.  `bytes` is the size of the block
+// actually held (at least what was asked for).
 struct dbuf {
   void *p = nullptr;
   size_t bytes = 0;
-  ~dbuf() { if (p) (void)hipFree(p); }
+  ~dbuf() { release(); }
   dbuf() = default;
   dbuf(const dbuf &) = delete;
   dbuf &operator=(const dbuf &) = delete;
   rs_status alloc(size_t b) {
     if (p && bytes >= b) return RS_OK;
-    if (p) { (void)hipFree(p); p = nullptr; bytes = 0; }
+    release();
     if (b == 0) b = 16;
-    hipError_t e = hipMalloc(&p, b);
-    if (e != hipSuccess) { p = nullptr; return RS_E_NOMEM; }
-    bytes = b;
+    size_t got = 0;
+    p = rs_pool_get(b, &got);
+    if (!p) return RS_E_NOMEM;
+    bytes = got;
     return RS_OK;
   }
-  void release() { if (p) (void)hipFree(p); p = nullptr; bytes = 0; }
+  void release() { if (p) rs_pool_put(p, bytes); p = nullptr; bytes = 0; }
   template <class T> T *as() const { return (T *)p; }
 };
 

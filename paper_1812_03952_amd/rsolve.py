@@ -81,6 +81,8 @@ def lib():
             "rs_cpr_level": (_i, [_vp, _i, C.POINTER(_i), C.POINTER(_i64), _vp, _vp, _vp, _vp, _vp]),
             "rs_cpr_smoother_get": (_i, [_vp, _vp]),
             "rs_cpr_vcycle": (_i, [_vp, _vp, _vp, _vp]),
+            "rs_pool_trim": (None, []),
+            "rs_pool_usage": (None, [C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -88,6 +90,18 @@ def lib():
             f.argtypes = args
         _lib = L
     return _lib
+
+
+def pool_trim():
+    """Return the library's cached device blocks to the HIP runtime."""
+    lib().rs_pool_trim()
+
+
+def pool_usage() -> tuple[int, int]:
+    """(bytes held by live handles, bytes cached for reuse)."""
+    live, cached = C.c_size_t(0), C.c_size_t(0)
+    lib().rs_pool_usage(C.byref(live), C.byref(cached))
+    return live.value, cached.value
 
 
 def status_string(st: int) -> str:

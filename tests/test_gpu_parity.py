@@ -124,12 +124,17 @@ def test_smoother_factors(method, smoother):
     assert np.array_equal(rs.cpr_smoother_get(Mg), Mo.dinv2())
 
 
-def test_vcycle():
+@pytest.mark.parametrize("coarse_n,max_levels", [(50, 20), (200, 20), (5000, 2)])
+def test_vcycle(coarse_n, max_levels):
+    """The coarsest inverse: one-workgroup elimination (<= 256 rows) and the
+    launch-per-column one (larger coarsest level)."""
     p = _prob((33, 17, 9), sigma=2.0, shale=0.1)
     A = oracle.assemble(p)
-    Mo = oracle.CPR(A, coarse_n=50)
+    Mo = oracle.CPR(A, coarse_n=coarse_n, max_levels=max_levels)
     B = upload(A)
-    Mg = rs.cpr_setup(B, rs.decouple(B, rs.ABF, 64), rs.cpr_opts(coarse_n=50))
+    Mg = rs.cpr_setup(B, rs.decouple(B, rs.ABF, 64), rs.cpr_opts(coarse_n=coarse_n, max_levels=max_levels))
+    nc = rs.cpr_level(Mg, rs.cpr_nlevels(Mg) - 1)["n"]
+    assert (nc > 256) == (coarse_n == 5000)
     b = np.random.default_rng(5).standard_normal(A.n)
     x = torch.empty(A.n, dtype=torch.float64, device="cuda")
     rs.cpr_vcycle(Mg, dev(b), x)
@@ -253,3 +258,25 @@ def test_dilu_pipeline_repeatable(prec):
         Mo = oracle.CPR(A)
         assert np.array_equal(rs.cpr_smoother_get(Mg), Mo.dinv2())
         assert relerr(z0.cpu().numpy(), Mo.apply(r.cpu().numpy())) <= 1e-10
+
+
+def test_pool_reuse_is_transparent():
+    """Handles destroyed and rebuilt reuse pooled (dirty) device memory: the
+    solve is bitwise the same, before and after returning the cache."""
+    p = synth.config(0)
+    A = oracle.assemble(p)
+    xs = []
+    for trim in (False, False, True):
+        if trim:
+            rs.pool_trim()
+            assert rs.pool_usage()[1] == 0
+        B = upload(A)
+        M = rs.cpr_setup(B, rs.decouple(B, rs.ABF, 32), rs.cpr_opts(smoother=rs.SM_RAS))
+        x = torch.zeros(4 * A.n, dtype=torch.float64, device="cuda")
+        info = rs.gmres_solve(B, M, dev(p.b), x)
+        assert info["return"] == 0
+        xs.append(x.cpu().numpy())
+        del M, B
+        torch.cuda.synchronize()
+        assert rs.pool_usage()[1] > 0
+    assert np.array_equal(xs[0], xs[1]) and np.array_equal(xs[0], xs[2])

@@ -100,7 +100,8 @@ const char *rs_status_string(int status);
  * validated against the 7-point pattern of the nx x ny x nz grid described
  * above (RS_E_ARG otherwise).  Values (d_vals, 16*nnzb doubles) are copied
  * into the library's own device layout; the caller may free its buffers
- * afterwards.  Non-finite values give RS_E_NONFINITE. */
+ * afterwards.  d_vals must be 16-byte aligned (RS_E_ARG otherwise).
+ * Non-finite values give RS_E_NONFINITE. */
 rs_status rs_bsr_create(int nx, int ny, int nz, int bs, int64_t nnzb,
                         const int32_t *d_row_ptr, const int32_t *d_col_idx,
                         const double *d_vals, void *stream, rs_bsr *out);

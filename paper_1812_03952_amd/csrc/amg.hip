@@ -28,8 +28,10 @@
 //              coarse matrices are bitwise reproducible.
 //   cycle      l1-Jacobi (d_i = sgn(a_ii) sum_j |a_ij|), one sweep before and
 //              one after the coarse correction; dense FP64 inverse at the
-//              coarsest level.  The pre-smoothed iterate b/d is never stored:
-//              the residual and the post-smoother recompute it on the fly.
+//              coarsest level.  On the coarser levels the pre-smoothed
+//              iterate b/d is not stored (the residual and the post-smoother
+//              recompute it); on the fine level, which keeps the 7-point
+//              pattern and is stored by stencil slot, it is formed once.
 #include "rs_internal.h"
 #include <math.h>
 
@@ -402,54 +404,56 @@ __global__ void k_gj_elim(int n, int k, double *__restrict__ G) {
   G[(int64_t)r * 2 * n + c] -= f * G[(int64_t)k * 2 * n + c];
 }
 
-// The same elimination for small n in one workgroup: the pivot search, row
-// swap, scaling and elimination of every column k run back to back with
-// barriers instead of two launches per column.  Same pivot choice (largest
-// |value|, lowest row on ties) and the same update per entry.
+// The same elimination for small n in one workgroup, three barriers per
+// column: the pivot (largest |value|, lowest row on ties) is reduced per wave
+// with shuffles and then across the waves from LDS; the row swap and the
+// scaling of the pivot row are one pass (each thread owns whole columns);
+// then the elimination.  Every entry gets the same operations as in the
+// two-launch form.
 constexpr int GJ_FUSED_MAX = 256;
 __global__ __launch_bounds__(1024) void k_gj_fused(int n, double *__restrict__ G, int *__restrict__ bad) {
-  __shared__ double sv[1024];
-  __shared__ int si[1024];
-  const int tid = threadIdx.x, nt = blockDim.x;
+  __shared__ double sv[16], sp[16];
+  __shared__ int si[16];
+  const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wv = tid >> 6, nwv = nt >> 6;
   const int64_t ld = 2 * (int64_t)n;
+  const int tpr = max(1, nt / n);             // threads per row in the elimination
+  const int rstep = nt / tpr, r0 = tid / tpr, c0 = tid - r0 * tpr;
   for (int k = 0; k < n; ++k) {
-    double best = -1.0;
+    // pivot: |value| compared, the signed value carried along
+    double best = -1.0, bval = 0.0;
     int bi = k;
     for (int r = k + tid; r < n; r += nt) {
-      double v = fabs(G[(int64_t)r * ld + k]);
-      if (v > best) { best = v; bi = r; }
+      double x = G[(int64_t)r * ld + k], v = fabs(x);
+      if (v > best) { best = v; bval = x; bi = r; }
     }
-    sv[tid] = best; si[tid] = bi;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      double ov = __shfl_down(best, off, 64), ox = __shfl_down(bval, off, 64);
+      int oi = __shfl_down(bi, off, 64);
+      if (ov > best || (ov == best && oi < bi)) { best = ov; bval = ox; bi = oi; }
+    }
+    if (lane == 0) { sv[wv] = best; sp[wv] = bval; si[wv] = bi; }
     __syncthreads();
-    for (int st = nt / 2; st > 0; st >>= 1) {
-      if (tid < st) {
-        if (sv[tid + st] > sv[tid] || (sv[tid + st] == sv[tid] && si[tid + st] < si[tid])) {
-          sv[tid] = sv[tid + st]; si[tid] = si[tid + st];
-        }
-      }
-      __syncthreads();
-    }
-    const int piv = si[0];
+    best = sv[0]; bval = sp[0]; bi = si[0];
+    for (int w = 1; w < nwv; ++w)
+      if (sv[w] > best || (sv[w] == best && si[w] < bi)) { best = sv[w]; bval = sp[w]; bi = si[w]; }
+    const int piv = bi;
     double *rk = G + (int64_t)k * ld, *rpv = G + (int64_t)piv * ld;
-    if (piv != k)
-      for (int c = tid; c < ld; c += nt) { double t = rk[c]; rk[c] = rpv[c]; rpv[c] = t; }
-    __syncthreads();
-    const double pv = rk[k];
+    const double pv = bval;
     if (tid == 0 && !(fabs(pv) > 0.0)) atomicOr(bad, 1);
     const double inv = 1.0 / pv;
+    for (int c = tid; c < ld; c += nt) {
+      const double vk = rk[c], vp = rpv[c];
+      if (piv != k) rpv[c] = vk;
+      rk[c] = (c == k) ? 1.0 : vp * inv;
+    }
     __syncthreads();
-    for (int c = tid; c < ld; c += nt)
-      if (c != k) rk[c] = rk[c] * inv;
-    __syncthreads();
-    if (tid == 0) rk[k] = 1.0;
-    __syncthreads();
-    const int64_t w = ld - (k + 1);
-    for (int64_t t = tid; t < (int64_t)n * w; t += nt) {
-      const int r = (int)(t / w);
-      const int c = (int)(t - (int64_t)r * w) + k + 1;
+    // thread -> (rows r0 + rstep*m, columns c0 + tpr*q): no divisions per entry
+    for (int r = r0; r < n && tid < rstep * tpr; r += rstep) {
       if (r == k) continue;
-      double f = G[(int64_t)r * ld + k];
-      G[(int64_t)r * ld + c] -= f * G[(int64_t)k * ld + c];
+      const double f = G[(int64_t)r * ld + k];
+      double *gr = G + (int64_t)r * ld;
+      for (int c = k + 1 + c0; c < ld; c += tpr) gr[c] -= f * rk[c];
     }
     __syncthreads();
   }
@@ -508,6 +512,64 @@ __global__ __launch_bounds__(256) void k_vc_post(int n, const int32_t *__restric
     s = fma(a[p], yj, s);
   }
   T yi = b[i] / d[i];
+  if (agg[i] >= 0) yi = yi + xc[agg[i]];
+  x[i] = yi + (b[i] - s) / d[i];
+}
+
+
+// ---- level 0 on the grid: the pressure matrix keeps the 7-point pattern, so
+// its values are stored by stencil slot and the neighbours follow from the
+// cell index (no column indices).  Slots run in column order and off-grid
+// slots hold zeros, so each sum is the same sequence of operations as the
+// row of the CSR form.  y = b ./ d is formed once instead of at every use.
+template <class T>
+__global__ __launch_bounds__(256) void k_cast7(int64_t m, const double *__restrict__ a, T *__restrict__ o) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < m) o[t] = (T)a[t];
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_vc_y(int n, const T *__restrict__ b, const T *__restrict__ d,
+                                               T *__restrict__ y) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = b[i] / d[i];
+}
+
+__device__ __forceinline__ int nbr7(int i, int s, int n, int nx, int nxy) {
+  const int off[7] = {-nxy, -nx, -1, 0, 1, nx, nxy};
+  int q = i + off[s];
+  return (q < 0 || q >= n) ? i : q;             // off-grid slots hold zero values
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_vc_pre7(int n, int nx, int nxy, const T *__restrict__ s7,
+                                                  const T *__restrict__ y, const T *__restrict__ b,
+                                                  T *__restrict__ r) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  T s = 0;
+#pragma unroll
+  for (int k = 0; k < 7; ++k) s = fma(s7[(int64_t)k * n + i], y[nbr7(i, k, n, nx, nxy)], s);
+  r[i] = b[i] - s;
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_vc_post7(int n, int nx, int nxy, const T *__restrict__ s7,
+                                                   const T *__restrict__ d, const int32_t *__restrict__ agg,
+                                                   const T *__restrict__ b, const T *__restrict__ y,
+                                                   const T *__restrict__ xc, T *__restrict__ x) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  T s = 0;
+#pragma unroll
+  for (int k = 0; k < 7; ++k) {
+    int q = nbr7(i, k, n, nx, nxy);
+    T yq = y[q];
+    int g = agg[q];
+    if (g >= 0) yq = yq + xc[g];
+    s = fma(s7[(int64_t)k * n + i], yq, s);
+  }
+  T yi = y[i];
   if (agg[i] >= 0) yi = yi + xc[agg[i]];
   x[i] = yi + (b[i] - s) / d[i];
 }
@@ -577,6 +639,14 @@ rs_status rs_amg_build(rs_cpr_s *M, hipStream_t s) {
     amg_level *L = M->lev[l];
     int n = L->n;
     RS_TRY(level_alloc_work(L, prec, l == 0 ? M->A->g.nxy : 0, s));
+    if (l == 0) {
+      size_t es = prec == 64 ? sizeof(double) : sizeof(float);
+      RS_TRY(L->s7.alloc(es * 7 * (size_t)n));
+      RS_TRY(L->y.alloc(es * ((size_t)n + 1)));
+      if (prec == 64) k_cast7<double><<<rs_grid(7 * (int64_t)n), RS_BLOCK, 0, s>>>(7 * (int64_t)n, M->D->ap7.as<double>(), L->s7.as<double>());
+      else k_cast7<float><<<rs_grid(7 * (int64_t)n), RS_BLOCK, 0, s>>>(7 * (int64_t)n, M->D->ap7.as<double>(), L->s7.as<float>());
+      RS_HIP(hipGetLastError());
+    }
     RS_TRY(L->agg.alloc(sizeof(int32_t) * (n + 1)));
     if (prec == 64) k_l1diag<double><<<rs_grid(n), RS_BLOCK, 0, s>>>(n, L->rp.as<int32_t>(), L->ci.as<int32_t>(), L->a.as<double>(), L->dl1.as<double>());
     else k_l1diag<float><<<rs_grid(n), RS_BLOCK, 0, s>>>(n, L->rp.as<int32_t>(), L->ci.as<int32_t>(), L->a.as<double>(), L->dl1.as<float>());
@@ -709,8 +779,15 @@ static rs_status vcycle_t(rs_cpr_s *M, hipStream_t s) {
   for (int l = 0; l < nl - 1; ++l) {
     amg_level *L = M->lev[l], *C = M->lev[l + 1];
     const T *a = (M->prec == 64) ? (const T *)L->a.p : (const T *)L->ap.p;
-    k_vc_pre<T><<<rs_grid(L->n), RS_BLOCK, 0, s>>>(L->n, L->rp.as<int32_t>(), L->ci.as<int32_t>(), a,
-                                                  L->dl1.as<T>(), L->b.as<T>(), L->r.as<T>());
+    if (l == 0 && L->s7.p) {
+      const grid3 &g = M->A->g;
+      k_vc_y<T><<<rs_grid(L->n), RS_BLOCK, 0, s>>>(L->n, L->b.as<T>(), L->dl1.as<T>(), L->y.as<T>());
+      k_vc_pre7<T><<<rs_grid(L->n), RS_BLOCK, 0, s>>>(L->n, g.nx, (int)g.nxy, L->s7.as<T>(), L->y.as<T>(),
+                                                      L->b.as<T>(), L->r.as<T>());
+    } else {
+      k_vc_pre<T><<<rs_grid(L->n), RS_BLOCK, 0, s>>>(L->n, L->rp.as<int32_t>(), L->ci.as<int32_t>(), a,
+                                                    L->dl1.as<T>(), L->b.as<T>(), L->r.as<T>());
+    }
     k_vc_restrict<T><<<rs_grid(L->nc), RS_BLOCK, 0, s>>>(L->nc, L->mptr.as<int32_t>(), L->mem.as<int32_t>(),
                                                          L->r.as<T>(), C->b.as<T>());
   }
@@ -733,9 +810,16 @@ static rs_status vcycle_t(rs_cpr_s *M, hipStream_t s) {
   for (int l = nl - 2; l >= 0; --l) {
     amg_level *L = M->lev[l], *Cl = M->lev[l + 1];
     const T *a = (M->prec == 64) ? (const T *)L->a.p : (const T *)L->ap.p;
-    k_vc_post<T><<<rs_grid(L->n), RS_BLOCK, 0, s>>>(L->n, L->rp.as<int32_t>(), L->ci.as<int32_t>(), a,
-                                                   L->dl1.as<T>(), L->agg.as<int32_t>(), L->b.as<T>(),
-                                                   Cl->xp<T>(), L->xp<T>());
+    if (l == 0 && L->s7.p) {
+      const grid3 &g = M->A->g;
+      k_vc_post7<T><<<rs_grid(L->n), RS_BLOCK, 0, s>>>(L->n, g.nx, (int)g.nxy, L->s7.as<T>(), L->dl1.as<T>(),
+                                                       L->agg.as<int32_t>(), L->b.as<T>(), L->y.as<T>(),
+                                                       Cl->xp<T>(), L->xp<T>());
+    } else {
+      k_vc_post<T><<<rs_grid(L->n), RS_BLOCK, 0, s>>>(L->n, L->rp.as<int32_t>(), L->ci.as<int32_t>(), a,
+                                                     L->dl1.as<T>(), L->agg.as<int32_t>(), L->b.as<T>(),
+                                                     Cl->xp<T>(), L->xp<T>());
+    }
   }
   RS_HIP(hipGetLastError());
   return RS_OK;

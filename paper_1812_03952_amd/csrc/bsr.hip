@@ -63,20 +63,24 @@ __global__ void k_validate(int nx, int ny, int nz, int64_t nnzb, const int32_t *
   if (err) atomicOr(bad, 1);
 }
 
-// Scatter caller-layout block values into the 7-slot layout (zeros off-grid).
-__global__ void k_to7(int64_t n, const int64_t *__restrict__ pos7, const double *__restrict__ vals,
-                      double *__restrict__ a7, int *__restrict__ bad) {
+// Scatter caller-layout block values into the 7-slot layout (zeros off-grid),
+// one block row (32 bytes) per thread.
+__global__ __launch_bounds__(256) void k_to7(int64_t n, const int64_t *__restrict__ pos7,
+                                             const double *__restrict__ vals, double *__restrict__ a7,
+                                             int *__restrict__ bad) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= 7 * n * 16) return;
-  int64_t sc = t >> 4;
-  int e = (int)(t & 15);
+  if (t >= 7 * n * 4) return;
+  int64_t sc = t >> 2;
+  int r = (int)(t & 3);
   int64_t p = pos7[sc];
-  double v = 0.0;
+  double2 v0 = make_double2(0.0, 0.0), v1 = v0;
   if (p >= 0) {
-    v = vals[16 * p + e];
-    if (!isfinite(v)) atomicOr(bad, 2);
+    const double2 *src = (const double2 *)(vals + 16 * p + 4 * r);
+    v0 = src[0]; v1 = src[1];
+    if (!(isfinite(v0.x) && isfinite(v0.y) && isfinite(v1.x) && isfinite(v1.y))) atomicOr(bad, 2);
   }
-  a7[t] = v;
+  double2 *dst = (double2 *)(a7 + 4 * t);
+  dst[0] = v0; dst[1] = v1;
 }
 
 typedef double v2d __attribute__((ext_vector_type(2)));
@@ -205,11 +209,12 @@ static int64_t grid_nnzb(int nx, int ny, int nz) {
 }
 
 static rs_status load_values(rs_bsr_s *A, const double *d_vals, hipStream_t s) {
+  if ((uintptr_t)d_vals & 15) return RS_E_ARG;         // block rows are read 16 bytes at a time
   int64_t n = A->g.n;
   dbuf flag;
   RS_TRY(flag.alloc(sizeof(int)));
   RS_HIP(hipMemsetAsync(flag.p, 0, sizeof(int), s));
-  k_to7<<<rs_grid(7 * n * 16), RS_BLOCK, 0, s>>>(n, A->pos7.as<int64_t>(), d_vals, A->a7.as<double>(),
+  k_to7<<<rs_grid(7 * n * 4), RS_BLOCK, 0, s>>>(n, A->pos7.as<int64_t>(), d_vals, A->a7.as<double>(),
                                                   flag.as<int>());
   RS_HIP(hipGetLastError());
   int h = 0;

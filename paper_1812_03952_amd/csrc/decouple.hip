@@ -20,22 +20,41 @@ namespace {
 #include "block4.h"
 
 template <class T>
-__device__ __forceinline__ void store_block(T *__restrict__ t7, T *__restrict__ col0, double *__restrict__ ap7,
-                                            int s, int64_t n, int64_t c, const double (&R)[4][4]) {
+__device__ __forceinline__ void store_block(T *__restrict__ t7, double *__restrict__ ap7, int s, int64_t n,
+                                            int64_t c, const double (&R)[4][4]) {
   T *o = t7 + ((int64_t)s * n + c) * 16;
 #pragma unroll
   for (int r = 0; r < 4; ++r)
 #pragma unroll
     for (int q = 0; q < 4; ++q) o[4 * r + q] = (T)R[r][q];
-  // column 0 of every block of the row, per block row: [c][row][slot], 8 wide
-  T *o0 = col0 + c * 32 + s;
-#pragma unroll
-  for (int r = 0; r < 4; ++r) o0[8 * r] = (T)R[r][0];
-  if (s == 6) {
-#pragma unroll
-    for (int r = 0; r < 4; ++r) o0[8 * r + 1] = (T)0;
-  }
   ap7[(int64_t)s * n + c] = R[0][0];
+}
+
+// Column 0 of every block of the row, per block row: col0[c][row][8] (the 7
+// slots, then a zero pad).  The 32 cells of a workgroup (8 lanes each, lane =
+// slot) stage their entries in LDS and write them out as contiguous 16-byte
+// chunks.  Every thread of the workgroup must call this.
+template <class T>
+__device__ __forceinline__ void store_col0(T *__restrict__ col0, int64_t n, int64_t c0, bool valid, int lane,
+                                           const double (&R)[4][4]) {
+  __shared__ T sh[32][32];
+  const int cl = threadIdx.x >> 3;
+  if (valid) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) sh[cl][8 * r + lane] = lane < 7 ? (T)R[r][0] : (T)0;
+  }
+  __syncthreads();
+  const int64_t c = c0 + cl;
+  if (c < n) {
+    const int q = threadIdx.x & 7;            // 4 consecutive entries of the cell's 32
+    T *dst = col0 + c * 32 + 4 * q;
+    if constexpr (sizeof(T) == 4) {
+      *(float4 *)dst = make_float4(sh[cl][4 * q], sh[cl][4 * q + 1], sh[cl][4 * q + 2], sh[cl][4 * q + 3]);
+    } else {
+      ((double2 *)dst)[0] = make_double2(sh[cl][4 * q], sh[cl][4 * q + 1]);
+      ((double2 *)dst)[1] = make_double2(sh[cl][4 * q + 2], sh[cl][4 * q + 3]);
+    }
+  }
 }
 
 template <class T>
@@ -43,10 +62,10 @@ __global__ __launch_bounds__(256) void k_decouple_abf(int64_t n, const double *_
                                                        T *__restrict__ t7, T *__restrict__ dinv,
                                                        double *__restrict__ ap7, T *__restrict__ col0,
                                                        int *__restrict__ flag) {
-  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= 8 * n) return;
-  int64_t c = t >> 3;
-  int lane = (int)(t & 7);
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = t < 8 * n;                 // all threads stay for the block-wide col0 store
+  const int64_t c = valid ? t >> 3 : n - 1;
+  const int lane = (int)(t & 7);
   double L[4][4], R[4][4];
   load16(a7 + (3 * n + c) * 16, L);
   if (lane < 7) {
@@ -58,22 +77,25 @@ __global__ __launch_bounds__(256) void k_decouple_abf(int64_t n, const double *_
       for (int q = 0; q < 4; ++q) R[r][q] = (r == q) ? 1.0 : 0.0;
   }
   int f = gje4<4>(L, R);
-  if (lane == 0 && f) atomicOr(flag, f);
-  if (lane == 7) {
-    T *o = dinv + c * 16;
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) o[4 * r + q] = (T)R[r][q];
-    return;
-  }
+  if (valid && lane == 0 && f) atomicOr(flag, f);
   if (lane == 3) {      // A~_ii = I exactly
 #pragma unroll
     for (int r = 0; r < 4; ++r)
 #pragma unroll
       for (int q = 0; q < 4; ++q) R[r][q] = (r == q) ? 1.0 : 0.0;
   }
-  store_block<T>(t7, col0, ap7, lane, n, c, R);
+  if (valid) {
+    if (lane == 7) {
+      T *o = dinv + c * 16;
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) o[4 * r + q] = (T)R[r][q];
+    } else {
+      store_block<T>(t7, ap7, lane, n, c, R);
+    }
+  }
+  store_col0<T>(col0, n, ((int64_t)blockIdx.x * blockDim.x) >> 3, valid, lane, R);
 }
 
 // Quasi-IMPES: w_i solves A_ii^T w_i = e_0; row 0 of each block in row i
@@ -83,10 +105,10 @@ __global__ __launch_bounds__(256) void k_decouple_qi(int64_t n, const double *__
                                                       T *__restrict__ t7, T *__restrict__ dinv,
                                                       double *__restrict__ ap7, T *__restrict__ col0,
                                                       int *__restrict__ flag) {
-  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= 8 * n) return;
-  int64_t c = t >> 3;
-  int lane = (int)(t & 7);
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = t < 8 * n;                 // all threads stay for the block-wide col0 store
+  const int64_t c = valid ? t >> 3 : n - 1;
+  const int lane = (int)(t & 7);
   double L[4][4], w[4][1];
   {
     double Aii[4][4];
@@ -99,30 +121,41 @@ __global__ __launch_bounds__(256) void k_decouple_qi(int64_t n, const double *__
 #pragma unroll
   for (int r = 0; r < 4; ++r) w[r][0] = (r == 0) ? 1.0 : 0.0;
   int f = gje4<1>(L, w);
-  if (lane == 0 && f) atomicOr(flag, f);
-  if (lane == 7) {
-    T *o = dinv + c * 16;
+  if (valid && lane == 0 && f) atomicOr(flag, f);
+  double R[4][4];
+  if (lane < 7) {
+    double A[4][4];
+    load16(a7 + ((int64_t)lane * n + c) * 16, A);
 #pragma unroll
-    for (int e = 0; e < 16; ++e) o[e] = (T)0.0;
+    for (int q = 0; q < 4; ++q) {
+      double s = 0.0;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) o[q] = (T)w[q][0];
-    o[5] = o[10] = o[15] = (T)1.0;
-    return;
+      for (int m = 0; m < 4; ++m) s = s + w[m][0] * A[m][q];
+      R[0][q] = s;
+    }
+#pragma unroll
+    for (int r = 1; r < 4; ++r)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) R[r][q] = A[r][q];
+  } else {
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) R[r][q] = 0.0;
   }
-  double A[4][4], R[4][4];
-  load16(a7 + ((int64_t)lane * n + c) * 16, A);
+  if (valid) {
+    if (lane == 7) {
+      T *o = dinv + c * 16;
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    double s = 0.0;
+      for (int e = 0; e < 16; ++e) o[e] = (T)0.0;
 #pragma unroll
-    for (int m = 0; m < 4; ++m) s = s + w[m][0] * A[m][q];
-    R[0][q] = s;
+      for (int q = 0; q < 4; ++q) o[q] = (T)w[q][0];
+      o[5] = o[10] = o[15] = (T)1.0;
+    } else {
+      store_block<T>(t7, ap7, lane, n, c, R);
+    }
   }
-#pragma unroll
-  for (int r = 1; r < 4; ++r)
-#pragma unroll
-    for (int q = 0; q < 4; ++q) R[r][q] = A[r][q];
-  store_block<T>(t7, col0, ap7, lane, n, c, R);
+  store_col0<T>(col0, n, ((int64_t)blockIdx.x * blockDim.x) >> 3, valid, lane, R);
 }
 
 }  // namespace

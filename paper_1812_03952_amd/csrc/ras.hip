@@ -75,93 +75,6 @@ __global__ __launch_bounds__(256) void k_ras_in(int nx, int ny, int64_t n, const
   if (row == 0) xpw[p] = xp[c];
 }
 
-// ---- factorisation, per layer: D_c = A~_cc - sum_{q in {c-nx, c-1}} A~_cq D_q^{-1} A~_qc
-// One thread per line and U lines per thread (line j = tid + blockDim*u).
-// The D^{-1} block of the cell before in x stays in the thread's registers;
-// that of the cell before in y comes from LDS (one slot per line: a barrier
-// after the reads of a level and one after its writes).  Same operation
-// order as the definition; D^{-1} blocks are rounded to the stored precision
-// before they are used by the next cells.
-template <class T, int U>
-__global__ __launch_bounds__(256) void k_ras_setup(int nx, int ny, int64_t n, const T *__restrict__ t7,
-                                                   T *__restrict__ dinv2, int *__restrict__ flag) {
-#pragma clang fp contract(off)
-  extern __shared__ __align__(16) unsigned char smem[];
-  T *ring = (T *)smem;                                  // [ny][16]
-  const int tid = threadIdx.x, TB = blockDim.x;
-  const int64_t nxy = (int64_t)nx * ny, cl = nxy * blockIdx.x;
-  const int Lv = nx + ny - 1;
-  const T *Ad = t7 + 3 * n * 16, *Ay = t7 + 1 * n * 16, *Ax = t7 + 2 * n * 16;
-  const T *Upx = t7 + 4 * n * 16, *Upy = t7 + 5 * n * 16;
-  T own[U][16];
-  int bad = 0;
-  for (int lam = 0; lam < Lv; ++lam) {
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int j = tid + TB * u, i = lam - j;
-      if (j < ny && i >= 0 && i < nx) {
-        const int64_t c = cl + (int64_t)j * nx + i;
-        double D[4][4];
-#pragma unroll
-        for (int e = 0; e < 16; ++e) D[e >> 2][e & 3] = (double)Ad[c * 16 + e];
-#pragma unroll
-        for (int s = 0; s < 2; ++s) {                   // -y, then -x (ascending column)
-          if (s == 0 ? j == 0 : i == 0) continue;
-          const int64_t q = s == 0 ? c - nx : c - 1;
-          double Dq[4][4], Aqc[4][4], Acq[4][4], T1[4][4];
-#pragma unroll
-          for (int e = 0; e < 16; ++e) {
-            Dq[e >> 2][e & 3] = (double)(s == 0 ? ring[(j - 1) * 16 + e] : own[u][e]);
-            Aqc[e >> 2][e & 3] = (double)(s == 0 ? Upy : Upx)[q * 16 + e];
-            Acq[e >> 2][e & 3] = (double)(s == 0 ? Ay : Ax)[c * 16 + e];
-          }
-#pragma unroll
-          for (int r = 0; r < 4; ++r)
-#pragma unroll
-            for (int cc = 0; cc < 4; ++cc) {
-              double v = 0.0;
-#pragma unroll
-              for (int m = 0; m < 4; ++m) v = v + Dq[r][m] * Aqc[m][cc];
-              T1[r][cc] = v;
-            }
-#pragma unroll
-          for (int r = 0; r < 4; ++r)
-#pragma unroll
-            for (int cc = 0; cc < 4; ++cc) {
-              double v = 0.0;
-#pragma unroll
-              for (int m = 0; m < 4; ++m) v = v + Acq[r][m] * T1[m][cc];
-              D[r][cc] = D[r][cc] - v;
-            }
-        }
-        double R[4][4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-#pragma unroll
-          for (int cc = 0; cc < 4; ++cc) R[r][cc] = (r == cc) ? 1.0 : 0.0;
-        bad |= gje4<4>(D, R);
-#pragma unroll
-        for (int e = 0; e < 16; ++e) {
-          const T v = (T)R[e >> 2][e & 3];
-          own[u][e] = v;
-          dinv2[c * 16 + e] = v;
-        }
-      }
-    }
-    __syncthreads();                                    // level lam-1 reads done
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int j = tid + TB * u, i = lam - j;
-      if (j < ny && i >= 0 && i < nx) {
-#pragma unroll
-        for (int e = 0; e < 16; ++e) ring[j * 16 + e] = own[u][e];
-      }
-    }
-    __syncthreads();                                    // level lam visible
-  }
-  if (bad) atomicOr(flag, bad);
-}
-
 // ---- scaled blocks for the sweeps, per (cell, block row) ---------------------
 // blk[b][p] = D_c^{-1} A~_{c, nb(b)} for b = 0..3: -y, -x, +x, +y (slots 1, 2,
 // 4, 5), at the cell's wavefront position p; FP64 products rounded once.
@@ -231,6 +144,146 @@ __device__ __forceinline__ void ras_write_level(int m, int nx, int ny, int64_t c
 // instruction).
 template <class T> __device__ __forceinline__ void order_after(int &idx, T tok) {
   asm volatile("" : "+v"(idx) : "v"(tok));
+}
+
+// ---- factorisation, per layer: D_c = A~_cc - sum_{q in {c-nx, c-1}} A~_cq D_q^{-1} A~_qc
+// One thread per line (line j = tid + LW*u) computes in FP64; the D^{-1}
+// block of the cell before in x stays in the thread's registers, that of the
+// cell before in y comes from an LDS slot per line (a barrier after the reads
+// of a level and one after its writes).  Same operation order as the
+// definition; D^{-1} blocks are rounded to the stored precision before the
+// next cells use them.  As in the sweeps, compute threads only load (the five
+// blocks of the next P levels stay in flight in registers, issued
+// unconditionally at clamped addresses over a level count padded to a
+// multiple of P) and one writer wave stores: while level lambda is computed
+// it copies the D^{-1} blocks of level lambda-1 from LDS to global memory.
+template <class T> struct ras_spre { T a[5][16]; };   // A~_cc, A~_{c,c-nx}, A~_{c,c-1}, A~_{c-nx,c}, A~_{c-1,c}
+
+template <class T, int U, int P>
+__global__ __launch_bounds__(320) void k_ras_setup(int nx, int ny, int64_t n, int LW, const T *__restrict__ t7,
+                                                   T *__restrict__ dinv2, int *__restrict__ flag) {
+#pragma clang fp contract(off)
+  extern __shared__ __align__(16) unsigned char smem[];
+  T *ring = (T *)smem;                                  // [ny][16]
+  const int tid = threadIdx.x;
+  const bool compute = tid < LW;                        // wave-uniform (LW is a multiple of 64)
+  const int64_t nxy = (int64_t)nx * ny, cl = nxy * blockIdx.x;
+  const int Lv = nx + ny - 1, Lpad = (Lv + P - 1) / P * P;
+  if (!compute) {
+    const int w = tid - LW;
+    auto write_level = [&](int m) {
+      if (m < 0 || m >= Lv) return;
+      const int jlo = max(0, m - nx + 1), jhi = min(ny - 1, m);
+      for (int j = jlo + w; j <= jhi; j += 64) {
+        const int64_t c = cl + (int64_t)j * nx + (m - j);
+#pragma unroll
+        for (int e = 0; e < 16; e += 4)
+          *(typename vec4t<T>::type *)(dinv2 + c * 16 + e) = *(const typename vec4t<T>::type *)(ring + j * 16 + e);
+      }
+    };
+    for (int lam = 0; lam < Lpad; ++lam) {
+      write_level(lam - 1);
+      __syncthreads();
+      __syncthreads();
+    }
+    write_level(Lpad - 1);
+    return;
+  }
+  const T *Ad = t7 + 3 * n * 16, *Ay = t7 + 1 * n * 16, *Ax = t7 + 2 * n * 16;
+  const T *Upx = t7 + 4 * n * 16, *Upy = t7 + 5 * n * 16;
+  ras_spre<T> R[P][U];
+  auto load = [&](int lam, ras_spre<T> &p, int u, T tok) {
+    int j = tid + LW * u;
+    order_after(j, tok);
+    j = min(j, ny - 1);
+    const int i = min(max(lam - j, 0), nx - 1);
+    const int64_t c = cl + (int64_t)j * nx + i;
+    const int64_t qy = j > 0 ? c - nx : c, qx = i > 0 ? c - 1 : c;
+    const T *src[5] = {Ad + c * 16, Ay + c * 16, Ax + c * 16, Upy + qy * 16, Upx + qx * 16};
+#pragma unroll
+    for (int b = 0; b < 5; ++b)
+#pragma unroll
+      for (int e = 0; e < 16; e += 4) {
+        T v4[4];
+        ld4v(src[b] + e, v4);
+#pragma unroll
+        for (int m = 0; m < 4; ++m) p.a[b][e + m] = v4[m];
+      }
+  };
+  T own[U][16];
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+#pragma unroll
+    for (int e = 0; e < 16; ++e) own[u][e] = (T)0;
+#pragma unroll
+  for (int d = 0; d < P; ++d)
+#pragma unroll
+    for (int u = 0; u < U; ++u) load(d, R[d][u], u, (T)0);
+  int bad = 0;
+  for (int lam0 = 0; lam0 < Lpad; lam0 += P) {
+#pragma unroll
+    for (int d = 0; d < P; ++d) {
+      const int lam = lam0 + d;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int j = tid + LW * u, i = lam - j;
+        if (j < ny && i >= 0 && i < nx) {
+          double D[4][4];
+#pragma unroll
+          for (int e = 0; e < 16; ++e) D[e >> 2][e & 3] = (double)R[d][u].a[0][e];
+#pragma unroll
+          for (int s = 0; s < 2; ++s) {                 // -y, then -x (ascending column)
+            if (s == 0 ? j == 0 : i == 0) continue;
+            double Dq[4][4], Aqc[4][4], Acq[4][4], T1[4][4];
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+              Dq[e >> 2][e & 3] = (double)(s == 0 ? ring[(j - 1) * 16 + e] : own[u][e]);
+              Aqc[e >> 2][e & 3] = (double)R[d][u].a[s == 0 ? 3 : 4][e];
+              Acq[e >> 2][e & 3] = (double)R[d][u].a[s == 0 ? 1 : 2][e];
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+              for (int cc = 0; cc < 4; ++cc) {
+                double v = 0.0;
+#pragma unroll
+                for (int m = 0; m < 4; ++m) v = v + Dq[r][m] * Aqc[m][cc];
+                T1[r][cc] = v;
+              }
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+              for (int cc = 0; cc < 4; ++cc) {
+                double v = 0.0;
+#pragma unroll
+                for (int m = 0; m < 4; ++m) v = v + Acq[r][m] * T1[m][cc];
+                D[r][cc] = D[r][cc] - v;
+              }
+          }
+          double Rm[4][4];
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int cc = 0; cc < 4; ++cc) Rm[r][cc] = (r == cc) ? 1.0 : 0.0;
+          bad |= gje4<4>(D, Rm);
+#pragma unroll
+          for (int e = 0; e < 16; ++e) own[u][e] = (T)Rm[e >> 2][e & 3];
+        }
+        load(lam + P, R[d][u], u, own[u][0]);
+      }
+      __syncthreads();                                  // level lam-1 reads done
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int j = tid + LW * u, i = lam - j;
+        if (j < ny && i >= 0 && i < nx) {
+#pragma unroll
+          for (int e = 0; e < 16; ++e) ring[j * 16 + e] = own[u][e];
+        }
+      }
+      __syncthreads();                                  // level lam visible
+    }
+  }
+  if (bad) atomicOr(flag, bad);
 }
 
 // wavefront index (within the grid) of line j at level lam, clamped to the
@@ -404,18 +457,20 @@ rs_status rs_ras_check_shape(const grid3 &g, int prec) {
 rs_status rs_ras_setup_run(rs_cpr_s *M, int *flag, hipStream_t s) {
   const grid3 &g = M->A->g;
   RS_TRY(rs_ras_check_shape(g, M->prec));
-  int tb = g.ny < 256 ? (g.ny + 63) / 64 * 64 : 256;
-  int u = (g.ny + tb - 1) / tb;                       // 1, 2 or 4
+  // compute threads: one per line, at most 256 lines per pass; one writer wave
+  int u = 1;
+  while ((g.ny + u - 1) / u > 256) u *= 2;            // 1, 2 or 4
+  const int lw = ((g.ny + u - 1) / u + 63) / 64 * 64;
   size_t es = M->prec == 64 ? sizeof(double) : sizeof(float);
   size_t lds = es * 16 * (size_t)g.ny;
   RS_TRY(M->rblk.alloc(es * 4 * 16 * (size_t)g.n));
   RS_TRY(M->rxp.alloc(es * (size_t)g.n));
-#define RS_RSET(T, UU)                                                                                \
-  k_ras_setup<T, UU><<<g.nz, tb, lds, s>>>(g.nx, g.ny, g.n, M->D->t7.as<T>(), M->dinv2.as<T>(), flag)
+#define RS_RSET(T, UU, PP)                                                                            \
+  k_ras_setup<T, UU, PP><<<g.nz, lw + 64, lds, s>>>(g.nx, g.ny, g.n, lw, M->D->t7.as<T>(), M->dinv2.as<T>(), flag)
   if (M->prec == 64) {
-    if (u == 1) RS_RSET(double, 1); else RS_RSET(double, 2);
+    if (u == 1) RS_RSET(double, 1, 1); else RS_RSET(double, 2, 1);
   } else {
-    if (u == 1) RS_RSET(float, 1); else if (u == 2) RS_RSET(float, 2); else RS_RSET(float, 4);
+    if (u == 1) RS_RSET(float, 1, 1); else if (u == 2) RS_RSET(float, 2, 1); else RS_RSET(float, 4, 1);
   }
 #undef RS_RSET
   RS_HIP(hipGetLastError());

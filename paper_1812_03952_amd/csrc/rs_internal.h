@@ -98,6 +98,9 @@ struct amg_level {
   dbuf mptr, mem;     // members of each aggregate (ascending), for restriction
   dbuf b, x, r;       // cycle work vectors, apply precision
   int64_t xoff = 0;   // x starts xoff elements into its buffer (zero guard planes at level 0)
+  // level 0 only: values by stencil slot [7][n] (zero off the grid) and
+  // y = b ./ d, apply precision, for the structured cycle kernels
+  dbuf s7, y;
   template <class T> T *xp() const { return x.as<T>() + xoff; }
 };
 

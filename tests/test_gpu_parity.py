@@ -280,3 +280,16 @@ def test_pool_reuse_is_transparent():
         torch.cuda.synchronize()
         assert rs.pool_usage()[1] > 0
     assert np.array_equal(xs[0], xs[1]) and np.array_equal(xs[0], xs[2])
+
+
+def test_bsr_values_must_be_16_byte_aligned():
+    p = synth.small(3, 3, 2, seed=4)
+    A = oracle.assemble(p)
+    rp, ci = dev(A.rp, torch.int32), dev(A.ci, torch.int32)
+    buf = torch.zeros(16 * A.nnzb + 1, dtype=torch.float64, device="cuda")
+    buf[1:] = dev(A.v.reshape(-1))
+    with pytest.raises(rs.RsError):
+        rs.bsr_create(A.nx, A.ny, A.nz, rp, ci, buf[1:])
+    B = rs.bsr_create(A.nx, A.ny, A.nz, rp, ci, buf[1:].clone())
+    with pytest.raises(rs.RsError):
+        rs.bsr_update(B, buf[1:])

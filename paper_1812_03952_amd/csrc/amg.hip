@@ -105,12 +105,20 @@ rs_status scan_i32(const int32_t *in, int32_t *out, int64_t n, int64_t *total, h
 }
 
 // ---- setup kernels -----------------------------------------------------------
-__global__ void k_gather_ap(int64_t m, const int64_t *__restrict__ pos7, const double *__restrict__ ap7,
-                            double *__restrict__ a) {
-  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= m) return;
-  int64_t p = pos7[t];
-  if (p >= 0) a[p] = ap7[t];
+// Fine-level CSR values from the pressure entries by stencil slot: one thread
+// per row writes its entries in column (= slot) order.  The pattern is the
+// validated 7-point one, so the slots inside the grid are exactly the row.
+__global__ __launch_bounds__(256) void k_csr_from7(int nx, int ny, int nz, const int32_t *__restrict__ rp,
+                                                   const double *__restrict__ ap7, double *__restrict__ a) {
+  const int64_t n = (int64_t)nx * ny * nz, nxy = (int64_t)nx * ny;
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  const int i = (int)(c % nx), j = (int)((c / nx) % ny), k = (int)(c / nxy);
+  const bool in[7] = {k > 0, j > 0, i > 0, true, i < nx - 1, j < ny - 1, k < nz - 1};
+  int64_t p = rp[c];
+#pragma unroll
+  for (int sl = 0; sl < 7; ++sl)
+    if (in[sl]) a[p++] = ap7[sl * n + c];
 }
 
 __global__ void k_strength_dir(int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
@@ -285,34 +293,60 @@ __global__ void k_cand(int nc, const int32_t *__restrict__ mptr, const int32_t *
   cand[I] = s;
 }
 
-// Coarse row I: accumulate members' rows into a first-seen list in scratch,
-// then sort the list by column (insertion sort on the short list).
-__global__ void k_galerkin(int nc, const int32_t *__restrict__ mptr, const int32_t *__restrict__ mem,
-                           const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
-                           const double *__restrict__ a, const int32_t *__restrict__ agg,
-                           const int32_t *__restrict__ off, int32_t *__restrict__ skey,
-                           double *__restrict__ sval, int32_t *__restrict__ cnt) {
-  int I = blockIdx.x * blockDim.x + threadIdx.x;
-  if (I >= nc) return;
-  int base = off[I], m = 0;
+// Coarse row I: accumulate members' rows into a first-seen list, then sort
+// the list by column (insertion sort on the short list).  The list lives in
+// LDS (one column per thread: entry s of thread t at [s][t]) when the row's
+// candidate count fits GAL_CAP, in the global scratch otherwise; the
+// additions happen in the same order either way.
+constexpr int GAL_BLOCK = 128, GAL_CAP = 32;
+
+template <class K, class V>
+__device__ __forceinline__ void gal_row(int I, const int32_t *__restrict__ mptr, const int32_t *__restrict__ mem,
+                                        const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                                        const double *__restrict__ a, const int32_t *__restrict__ agg, K key,
+                                        V val, int &m) {
+  m = 0;
   for (int x = mptr[I]; x < mptr[I + 1]; ++x) {
     int i = mem[x];
     for (int p = rp[i]; p < rp[i + 1]; ++p) {
       int J = agg[ci[p]];
       if (J < 0) continue;
       int s = 0;
-      while (s < m && skey[base + s] != J) ++s;
-      if (s == m) { skey[base + m] = J; sval[base + m] = 0.0; ++m; }
-      sval[base + s] = sval[base + s] + a[p];
+      while (s < m && key(s) != J) ++s;
+      if (s == m) { key(m) = J; val(m) = 0.0; ++m; }
+      val(s) = val(s) + a[p];
     }
   }
   for (int x = 1; x < m; ++x) {
-    int k = skey[base + x];
-    double v = sval[base + x];
+    int k = key(x);
+    double v = val(x);
     int y = x - 1;
-    while (y >= 0 && skey[base + y] > k) { skey[base + y + 1] = skey[base + y]; sval[base + y + 1] = sval[base + y]; --y; }
-    skey[base + y + 1] = k;
-    sval[base + y + 1] = v;
+    while (y >= 0 && key(y) > k) { key(y + 1) = key(y); val(y + 1) = val(y); --y; }
+    key(y + 1) = k;
+    val(y + 1) = v;
+  }
+}
+
+__global__ __launch_bounds__(GAL_BLOCK) void k_galerkin(int nc, const int32_t *__restrict__ mptr,
+                                                        const int32_t *__restrict__ mem,
+                                                        const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                                                        const double *__restrict__ a, const int32_t *__restrict__ agg,
+                                                        const int32_t *__restrict__ off, int32_t *__restrict__ skey,
+                                                        double *__restrict__ sval, int32_t *__restrict__ cnt) {
+  __shared__ int32_t lk[GAL_CAP][GAL_BLOCK];
+  __shared__ double lv[GAL_CAP][GAL_BLOCK];
+  const int t = threadIdx.x;
+  const int I = blockIdx.x * blockDim.x + t;
+  if (I >= nc) return;
+  const int base = off[I], ncand = cnt[I];       // candidate count from k_cand
+  int m = 0;
+  if (ncand <= GAL_CAP) {
+    gal_row(I, mptr, mem, rp, ci, a, agg, [&](int s) -> int32_t & { return lk[s][t]; },
+            [&](int s) -> double & { return lv[s][t]; }, m);
+    for (int s = 0; s < m; ++s) { skey[base + s] = lk[s][t]; sval[base + s] = lv[s][t]; }
+  } else {
+    gal_row(I, mptr, mem, rp, ci, a, agg, [&](int s) -> int32_t & { return skey[base + s]; },
+            [&](int s) -> double & { return sval[base + s]; }, m);
   }
   cnt[I] = m;
 }
@@ -456,6 +490,99 @@ __global__ __launch_bounds__(1024) void k_gj_fused(int n, double *__restrict__ G
       for (int c = k + 1 + c0; c < ld; c += tpr) gr[c] -= f * rk[c];
     }
     __syncthreads();
+  }
+}
+
+// Small coarsest levels (up to about 100 rows) are inverted with the matrix in
+// registers: each row is held by tpr = NT/n threads, thread (r, c0) owning
+// columns c0, c0+tpr, ...  Per column k the owners publish column k to LDS,
+// every wave finds the pivot from it (largest |value|, lowest row on ties),
+// the pivot row and row k go through LDS for the swap, and every thread
+// updates its own entries: the pivot row is scaled (rounded) first and each
+// other row gets G[r][c] -= f * G[k][c] for c > k, as in the launch-per-column
+// form.  The inverse (the right half) is written straight to cinv.
+constexpr int GJ_REG_MAX = 128;
+__device__ __forceinline__ bool gj_better(double v, int i, double bv, int bi) {
+  return v > bv || (v == bv && i < bi);
+}
+template <int NT, int GJ_Q>
+__global__ __launch_bounds__(NT) void k_gj_reg(int n, const double *__restrict__ G0, double *__restrict__ cinv,
+                                               int *__restrict__ bad) {
+  __shared__ double colk[GJ_REG_MAX], prow[2 * GJ_REG_MAX], krow[2 * GJ_REG_MAX];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int ld = 2 * n, tpr = NT / n;
+  const int r = tid / tpr, c0 = tid - r * tpr;
+  const bool own = r < n;
+  double g[GJ_Q];
+#pragma unroll
+  for (int q = 0; q < GJ_Q; ++q) {
+    const int c = c0 + tpr * q;
+    g[q] = (own && c < ld) ? G0[(int64_t)r * ld + c] : 0.0;
+  }
+  for (int k = 0; k < n; ++k) {
+    if (own) {
+#pragma unroll
+      for (int q = 0; q < GJ_Q; ++q)
+        if (c0 + tpr * q == k) colk[r] = g[q];
+    }
+    __syncthreads();
+    double best = -1.0, bval = 0.0;
+    int bi = k;
+    for (int rr = k + lane; rr < n; rr += 64) {
+      const double x = colk[rr], v = fabs(x);
+      if (gj_better(v, rr, best, bi)) { best = v; bval = x; bi = rr; }
+    }
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) {
+      const double ov = __shfl_xor(best, m, 64), ox = __shfl_xor(bval, m, 64);
+      const int oi = __shfl_xor(bi, m, 64);
+      if (gj_better(ov, oi, best, bi)) { best = ov; bval = ox; bi = oi; }
+    }
+    const int piv = bi;
+    const double inv = 1.0 / bval;
+    if (tid == 0 && !(fabs(bval) > 0.0)) atomicOr(bad, 1);
+    if (own && r == piv) {
+#pragma unroll
+      for (int q = 0; q < GJ_Q; ++q) { const int c = c0 + tpr * q; if (c < ld) prow[c] = g[q]; }
+    }
+    if (own && r == k && piv != k) {
+#pragma unroll
+      for (int q = 0; q < GJ_Q; ++q) { const int c = c0 + tpr * q; if (c < ld) krow[c] = g[q]; }
+    }
+    __syncthreads();
+    if (own) {
+      if (r == k) {
+#pragma unroll
+        for (int q = 0; q < GJ_Q; ++q) {
+          const int c = c0 + tpr * q;
+          if (c < ld) g[q] = (c == k) ? 1.0 : prow[c] * inv;
+        }
+      } else {
+        const bool sw = r == piv;               // this row now holds the old row k
+        const double f = sw ? krow[k] : colk[r];
+#pragma unroll
+        for (int q = 0; q < GJ_Q; ++q) {
+          const int c = c0 + tpr * q;
+          if (c < ld) {
+            const double base = sw ? krow[c] : g[q];
+            if (c > k) {
+              const double t = prow[c] * inv;
+              g[q] = base - f * t;
+            } else {
+              g[q] = base;
+            }
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (own) {
+#pragma unroll
+    for (int q = 0; q < GJ_Q; ++q) {
+      const int c = c0 + tpr * q;
+      if (c >= n && c < ld) cinv[(int64_t)r * n + (c - n)] = g[q];
+    }
   }
 }
 
@@ -717,7 +844,7 @@ rs_status rs_amg_build(rs_cpr_s *M, hipStream_t s) {
     RS_TRY(scan_i32(cnt.as<int32_t>(), off.as<int32_t>(), nc, &ncand, s));
     RS_TRY(skey.alloc(sizeof(int32_t) * (ncand + 1)));
     RS_TRY(sval.alloc(sizeof(double) * (ncand + 1)));
-    k_galerkin<<<rs_grid(nc), RS_BLOCK, 0, s>>>(nc, L->mptr.as<int32_t>(), L->mem.as<int32_t>(), rp, ci, L->a.as<double>(),
+    k_galerkin<<<rs_grid(nc, GAL_BLOCK), GAL_BLOCK, 0, s>>>(nc, L->mptr.as<int32_t>(), L->mem.as<int32_t>(), rp, ci, L->a.as<double>(),
                                                  L->agg.as<int32_t>(), off.as<int32_t>(), skey.as<int32_t>(),
                                                  sval.as<double>(), cnt.as<int32_t>());
     RS_HIP(hipGetLastError());
@@ -752,7 +879,18 @@ rs_status rs_amg_build(rs_cpr_s *M, hipStream_t s) {
     RS_TRY(M->cx.alloc(sizeof(double) * (nC + 1)));
     RS_HIP(hipMemsetAsync(flag.p, 0, sizeof(int), s));
     k_densify<<<rs_grid(nC), RS_BLOCK, 0, s>>>(nC, C->rp.as<int32_t>(), C->ci.as<int32_t>(), C->a.as<double>(), G.as<double>());
-    if (nC <= GJ_FUSED_MAX) {
+    bool inverted = false;
+    if (nC <= GJ_REG_MAX && (2 * nC + 512 / nC - 1) / (512 / nC) <= 48) {
+      // columns per thread ceil(2n / (NT / n)); 1024 threads while that is at
+      // most 16, else 512 threads (more registers per thread)
+      const int need1024 = (2 * nC + 1024 / nC - 1) / (1024 / nC), need512 = (2 * nC + 512 / nC - 1) / (512 / nC);
+      double *G0 = G.as<double>(), *Ci = M->cinv.as<double>();
+      int *fl = flag.as<int>();
+      if (need1024 <= 8) k_gj_reg<1024, 8><<<1, 1024, 0, s>>>(nC, G0, Ci, fl);
+      else if (need1024 <= 16) k_gj_reg<1024, 16><<<1, 1024, 0, s>>>(nC, G0, Ci, fl);
+      else k_gj_reg<512, 48><<<1, 512, 0, s>>>(nC, G0, Ci, fl);
+      inverted = true;
+    } else if (nC <= GJ_FUSED_MAX) {
       k_gj_fused<<<1, 1024, 0, s>>>(nC, G.as<double>(), flag.as<int>());
     } else {
       for (int k = 0; k < nC; ++k) {
@@ -761,7 +899,8 @@ rs_status rs_amg_build(rs_cpr_s *M, hipStream_t s) {
         if (work > 0) k_gj_elim<<<rs_grid(work), RS_BLOCK, 0, s>>>(nC, k, G.as<double>());
       }
     }
-    k_extract_inv<<<rs_grid((int64_t)nC * nC), RS_BLOCK, 0, s>>>(nC, G.as<double>(), M->cinv.as<double>());
+    if (!inverted)
+      k_extract_inv<<<rs_grid((int64_t)nC * nC), RS_BLOCK, 0, s>>>(nC, G.as<double>(), M->cinv.as<double>());
     RS_HIP(hipGetLastError());
     int h = 0;
     RS_HIP(hipMemcpyAsync(&h, flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -883,8 +1022,8 @@ rs_status rs_amg_level0(rs_cpr_s *M, hipStream_t s) {
   RS_TRY(L->a.alloc(sizeof(double) * L->nnz));
   RS_HIP(hipMemcpyAsync(L->rp.p, A->rp.p, sizeof(int32_t) * (L->n + 1), hipMemcpyDeviceToDevice, s));
   RS_HIP(hipMemcpyAsync(L->ci.p, A->ci.p, sizeof(int32_t) * L->nnz, hipMemcpyDeviceToDevice, s));
-  k_gather_ap<<<rs_grid(7 * A->g.n), RS_BLOCK, 0, s>>>(7 * A->g.n, A->pos7.as<int64_t>(), M->D->ap7.as<double>(),
-                                                       L->a.as<double>());
+  k_csr_from7<<<rs_grid(A->g.n), RS_BLOCK, 0, s>>>(A->g.nx, A->g.ny, A->g.nz, L->rp.as<int32_t>(),
+                                                   M->D->ap7.as<double>(), L->a.as<double>());
   RS_HIP(hipGetLastError());
   return RS_OK;
 }

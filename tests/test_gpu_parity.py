@@ -293,3 +293,24 @@ def test_bsr_values_must_be_16_byte_aligned():
     B = rs.bsr_create(A.nx, A.ny, A.nz, rp, ci, buf[1:].clone())
     with pytest.raises(rs.RsError):
         rs.bsr_update(B, buf[1:])
+
+
+@pytest.mark.parametrize("dims,lo,hi", [((7, 7, 7), 1, 64), ((10, 10, 6), 65, 86), ((10, 10, 7), 87, 102),
+                                        ((12, 12, 6), 103, 256), ((20, 20, 10), 257, 2048)])
+def test_coarsest_inverse_paths(dims, lo, hi):
+    """Two-level hierarchies whose coarsest level falls in each range of the
+    coarsest-inverse kernels (registers with 1024 or 512 threads, one
+    workgroup in global memory, one launch pair per column): the V-cycle
+    against the oracle's, which inverts by dense LU."""
+    p = _prob(dims, sigma=2.0, shale=0.1)
+    A = oracle.assemble(p)
+    opts = dict(coarse_n=A.n - 1, max_levels=2)
+    Mo = oracle.CPR(A, **opts)
+    B = upload(A)
+    Mg = rs.cpr_setup(B, rs.decouple(B, rs.ABF, 64), rs.cpr_opts(**opts))
+    nc = rs.cpr_level(Mg, 1)["n"]
+    assert lo <= nc <= hi or (lo == 1 and nc <= hi), nc
+    b = np.random.default_rng(11).standard_normal(A.n)
+    x = torch.empty(A.n, dtype=torch.float64, device="cuda")
+    rs.cpr_vcycle(Mg, dev(b), x)
+    assert relerr(x.cpu().numpy(), Mo.amg().vcycle(b)) <= 1e-11

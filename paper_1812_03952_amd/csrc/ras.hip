@@ -431,6 +431,169 @@ __global__ __launch_bounds__(1024) void k_ras_bwd(int nx, int ny, int64_t n, int
   }
 }
 
+// ---- sweeps with one lane per cell (FP32 storage) ---------------------------
+// The same recurrences, one lane per line handling all four block rows of its
+// cell: per cell the arithmetic is the same sequence as in the four-lane
+// form, but each level needs a quarter of the lanes, which cuts the per-level
+// instruction issue that bounds those kernels (address arithmetic, selects
+// and LDS traffic are per lane, not per row).  Lines j = tid + LW*u; loads of
+// the next P levels stay in flight per lane (36 values per level).
+template <class T> struct ras_f1 { T r[4], a1[16], a2[16]; };
+
+template <class T, int U, int P>
+__global__ __launch_bounds__(320) void k_ras_fwd1(int nx, int ny, int64_t n, int LW, const T *__restrict__ blk,
+                                                   const T *__restrict__ rh, T *__restrict__ y) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  T *ring = (T *)smem;                                  // [2][ny][4]
+  const int tid = threadIdx.x;
+  const bool compute = tid < LW;                        // wave-uniform (LW is a multiple of 64)
+  const int w = tid - LW, nw = blockDim.x - LW;
+  const int64_t nxy = (int64_t)nx * ny, cl = nxy * blockIdx.x;
+  const int Lv = nx + ny - 1, Lpad = (Lv + P - 1) / P * P;
+  if (!compute) {
+    for (int lam = 0; lam < Lpad; ++lam) {
+      ras_write_level<T, true>(lam - 1, nx, ny, cl, ring + ((lam & 1) ^ 1) * ny * 4, y, w, nw);
+      __syncthreads();
+    }
+    ras_write_level<T, true>(Lpad - 1, nx, ny, cl, ring + ((Lpad - 1) & 1) * ny * 4, y, w, nw);
+    return;
+  }
+  const T *By = blk, *Bx = blk + n * 16;
+  ras_f1<T> R[P][U];
+  auto load = [&](int lam, ras_f1<T> &p, int u, T tok) {
+    int j = tid + LW * u;
+    order_after(j, tok);
+    const int64_t c = wf_clamped(cl, lam, j, nx, ny);
+    ld4v(rh + 4 * c, p.r);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      T t4[4];
+      ld4v(By + c * 16 + 4 * m, t4);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) p.a1[4 * m + e] = t4[e];
+      ld4v(Bx + c * 16 + 4 * m, t4);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) p.a2[4 * m + e] = t4[e];
+    }
+  };
+#pragma unroll
+  for (int d = 0; d < P; ++d)
+#pragma unroll
+    for (int u = 0; u < U; ++u) load(d, R[d][u], u, (T)0);
+  for (int lam0 = 0; lam0 < Lpad; lam0 += P) {
+#pragma unroll
+    for (int d = 0; d < P; ++d) {
+      const int lam = lam0 + d;
+      T *cur = ring + (lam & 1) * ny * 4;
+      const T *prv = ring + ((lam & 1) ^ 1) * ny * 4;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int j = tid + LW * u, i = lam - j;
+        const bool act = j < ny && i >= 0 && i < nx;
+        const int jr = min(j, ny - 1);
+        T yy[4], yx[4], v[4];
+        ld4v(prv + 4 * max(jr - 1, 0), yy);
+        ld4v(prv + 4 * jr, yx);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          T a1r[4] = {R[d][u].a1[4 * r], R[d][u].a1[4 * r + 1], R[d][u].a1[4 * r + 2], R[d][u].a1[4 * r + 3]};
+          T a2r[4] = {R[d][u].a2[4 * r], R[d][u].a2[4 * r + 1], R[d][u].a2[4 * r + 2], R[d][u].a2[4 * r + 3]};
+          const T ty = dot4(a1r, yy), tx = dot4(a2r, yx);
+          T vr = R[d][u].r[r];
+          vr = (act && j > 0) ? vr - ty : vr;
+          vr = (act && i > 0) ? vr - tx : vr;
+          v[r] = vr;
+        }
+        if (act) *(typename vec4t<T>::type *)(cur + 4 * j) = typename vec4t<T>::type{v[0], v[1], v[2], v[3]};
+        load(lam + P, R[d][u], u, v[3]);
+      }
+      __syncthreads();
+    }
+  }
+}
+
+template <class T> struct ras_b1 { T yc[4], xpc, a4[16], a5[16]; };
+
+template <class T, int U, int P>
+__global__ __launch_bounds__(320) void k_ras_bwd1(int nx, int ny, int64_t n, int LW, const T *__restrict__ blk,
+                                                   const T *__restrict__ y, const T *__restrict__ xpw,
+                                                   T *__restrict__ out) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  T *ring = (T *)smem;                                  // [2][ny][4]: z
+  T *oring = ring + 2 * ny * 4;                         // [2][ny][4]: output
+  const int tid = threadIdx.x;
+  const bool compute = tid < LW;
+  const int w = tid - LW, nw = blockDim.x - LW;
+  const int64_t nxy = (int64_t)nx * ny, cl = nxy * blockIdx.x;
+  const int Lv = nx + ny - 1, Lpad = (Lv + P - 1) / P * P;
+  if (!compute) {
+    for (int step = 0; step < Lpad; ++step) {
+      ras_write_level<T, false>(step >= 1 ? Lv - step : -1, nx, ny, cl, oring + ((step & 1) ^ 1) * ny * 4, out, w,
+                                nw);
+      __syncthreads();
+    }
+    ras_write_level<T, false>(Lv - Lpad, nx, ny, cl, oring + ((Lpad - 1) & 1) * ny * 4, out, w, nw);
+    return;
+  }
+  const T *Bx = blk + 2 * n * 16, *By = blk + 3 * n * 16;
+  ras_b1<T> R[P][U];
+  auto load = [&](int step, ras_b1<T> &p, int u, T tok) {
+    int j = tid + LW * u;
+    order_after(j, tok);
+    const int64_t c = wf_clamped(cl, Lv - 1 - step, j, nx, ny);
+    ld4v(y + 4 * c, p.yc);
+    p.xpc = xpw[c];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      T t4[4];
+      ld4v(Bx + c * 16 + 4 * m, t4);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) p.a4[4 * m + e] = t4[e];
+      ld4v(By + c * 16 + 4 * m, t4);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) p.a5[4 * m + e] = t4[e];
+    }
+  };
+#pragma unroll
+  for (int d = 0; d < P; ++d)
+#pragma unroll
+    for (int u = 0; u < U; ++u) load(d, R[d][u], u, (T)0);
+  for (int s0 = 0; s0 < Lpad; s0 += P) {
+#pragma unroll
+    for (int d = 0; d < P; ++d) {
+      const int step = s0 + d;
+      const int lam = Lv - 1 - step;
+      const int cb = (step & 1) * ny * 4, pb = ((step & 1) ^ 1) * ny * 4;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int j = tid + LW * u, i = lam - j;
+        const bool act = j < ny && i >= 0 && i < nx;
+        const int jr = min(j, ny - 1);
+        T zx[4], zy[4], z[4];
+        ld4v(ring + pb + 4 * jr, zx);
+        ld4v(ring + pb + 4 * min(jr + 1, ny - 1), zy);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          T a4r[4] = {R[d][u].a4[4 * r], R[d][u].a4[4 * r + 1], R[d][u].a4[4 * r + 2], R[d][u].a4[4 * r + 3]};
+          T a5r[4] = {R[d][u].a5[4 * r], R[d][u].a5[4 * r + 1], R[d][u].a5[4 * r + 2], R[d][u].a5[4 * r + 3]};
+          const T tx = dot4(a4r, zx), ty = dot4(a5r, zy);
+          T zr = R[d][u].yc[r];
+          zr = (act && i < nx - 1) ? zr - tx : zr;
+          zr = (act && j < ny - 1) ? zr - ty : zr;
+          z[r] = zr;
+        }
+        if (act) {
+          *(typename vec4t<T>::type *)(ring + cb + 4 * j) = typename vec4t<T>::type{z[0], z[1], z[2], z[3]};
+          *(typename vec4t<T>::type *)(oring + cb + 4 * j) =
+              typename vec4t<T>::type{z[0] + R[d][u].xpc, z[1], z[2], z[3]};
+        }
+        load(step + P, R[d][u], u, z[3]);
+      }
+      __syncthreads();
+    }
+  }
+}
+
 // launch shape of the sweeps: LW lines per pass (a multiple of 16, so whole
 // waves), U passes per level
 struct sweep_shape { int lw, u; };
@@ -511,10 +674,27 @@ rs_status rs_ras_apply_run(rs_cpr_s *M, const T *xp, T *out, hipStream_t s) {
     }                                                                                                 \
   } while (0)
   const size_t ring_bytes = sizeof(T) * 8 * (size_t)g.ny;     // two levels of [ny][4]
-  RS_RDISPATCH(k_ras_fwd, ring_bytes, g.nx, g.ny, g.n, sh.lw, blk, rh, y);
-  RS_HIP(hipGetLastError());
-  RS_RDISPATCH(k_ras_bwd, 2 * ring_bytes, g.nx, g.ny, g.n, sh.lw, blk, y, xpw, out);
-  RS_HIP(hipGetLastError());
+  if constexpr (sizeof(T) == 4) {
+    // one lane per line, at most 240 lines per pass, and one writer wave
+    const int u1 = g.ny <= 240 ? 1 : (g.ny <= 480 ? 2 : 4);
+    const int lw1 = ((g.ny + u1 - 1) / u1 + 63) / 64 * 64, nt1 = lw1 + 64;
+    if (u1 == 1) {
+      k_ras_fwd1<T, 1, 4><<<g.nz, nt1, ring_bytes, s>>>(g.nx, g.ny, g.n, lw1, blk, rh, y);
+      k_ras_bwd1<T, 1, 4><<<g.nz, nt1, 2 * ring_bytes, s>>>(g.nx, g.ny, g.n, lw1, blk, y, xpw, out);
+    } else if (u1 == 2) {
+      k_ras_fwd1<T, 2, 2><<<g.nz, nt1, ring_bytes, s>>>(g.nx, g.ny, g.n, lw1, blk, rh, y);
+      k_ras_bwd1<T, 2, 2><<<g.nz, nt1, 2 * ring_bytes, s>>>(g.nx, g.ny, g.n, lw1, blk, y, xpw, out);
+    } else {
+      k_ras_fwd1<T, 4, 1><<<g.nz, nt1, ring_bytes, s>>>(g.nx, g.ny, g.n, lw1, blk, rh, y);
+      k_ras_bwd1<T, 4, 1><<<g.nz, nt1, 2 * ring_bytes, s>>>(g.nx, g.ny, g.n, lw1, blk, y, xpw, out);
+    }
+    RS_HIP(hipGetLastError());
+  } else {
+    RS_RDISPATCH(k_ras_fwd, ring_bytes, g.nx, g.ny, g.n, sh.lw, blk, rh, y);
+    RS_HIP(hipGetLastError());
+    RS_RDISPATCH(k_ras_bwd, 2 * ring_bytes, g.nx, g.ny, g.n, sh.lw, blk, y, xpw, out);
+    RS_HIP(hipGetLastError());
+  }
 #undef RS_RDISPATCH
 #undef RS_RSWEEP
   return RS_OK;

@@ -549,10 +549,12 @@ template rs_status rs_dilu_apply_run<double>(rs_cpr_s *, const double *, double 
 template rs_status rs_dilu_apply_run<float>(rs_cpr_s *, const float *, float *, hipStream_t);
 
 // error word of the pipelined kernels (time-out of a bounded wait)
+// error words of the pipelined sweeps (DILU bricks, RAS strips): a bounded
+// wait that timed out leaves a non-zero word
 rs_status rs_dilu_check(rs_cpr_s *M, hipStream_t s) {
-  if (!M->pctl.p) return RS_OK;
-  int h = 0;
-  RS_HIP(hipMemcpyAsync(&h, M->pctl.as<int>() + 1, sizeof(int), hipMemcpyDeviceToHost, s));
-  RS_HIP(hipStreamSynchronize(s));
-  return h ? RS_E_HIP : RS_OK;
+  int h = 0, r = 0;
+  if (M->pctl.p) RS_HIP(hipMemcpyAsync(&h, M->pctl.as<int>() + 1, sizeof(int), hipMemcpyDeviceToHost, s));
+  if (M->rctl.p) RS_HIP(hipMemcpyAsync(&r, M->rctl.as<int>() + 2, sizeof(int), hipMemcpyDeviceToHost, s));
+  if (M->pctl.p || M->rctl.p) RS_HIP(hipStreamSynchronize(s));
+  return (h || r) ? RS_E_HIP : RS_OK;
 }

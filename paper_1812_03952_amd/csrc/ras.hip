@@ -28,6 +28,7 @@
 // all in the preconditioner's precision.
 #include "rs_internal.h"
 #include <math.h>
+#include <algorithm>
 
 namespace {
 #pragma clang fp contract(off)
@@ -431,81 +432,163 @@ __global__ __launch_bounds__(1024) void k_ras_bwd(int nx, int ny, int64_t n, int
   }
 }
 
-// ---- sweeps with one lane per cell (FP32 storage) ---------------------------
-// The same recurrences, one lane per line handling all four block rows of its
-// cell: per cell the arithmetic is the same sequence as in the four-lane
-// form, but each level needs a quarter of the lanes, which cuts the per-level
-// instruction issue that bounds those kernels (address arithmetic, selects
-// and LDS traffic are per lane, not per row).  Lines j = tid + LW*u; loads of
-// the next P levels stay in flight per lane (36 values per level).
+// ---- sweeps with one lane per cell, layers split into strips (FP32) ---------
+// One lane per line handles all four block rows of its cell (per cell the
+// same arithmetic sequence as the four-lane form; a quarter of the lanes).
+// A workgroup keeps a layer's lines streamed through one CU, which bounds it
+// at that CU's memory stream, so each layer is further split into S strips
+// of H consecutive lines, one workgroup each.  A strip needs, at every level,
+// the value of the line just before it (after it, backward) computed one
+// level earlier by the neighbouring strip:
+//   - the producer's writer wave publishes its boundary line, level by level,
+//     as 64-bit words (launch tag << 32 | FP32 bits), one per block row,
+//     with device-scope stores;
+//   - the consumer's writer wave polls those words with device-scope loads
+//     until the tag matches and puts the value into a ghost slot of its LDS
+//     ring, ready for the next level;
+//   - workgroups take tickets in dependency order (every strip of a layer
+//     after the one it reads), so a workgroup only waits on workgroups that
+//     are already running; every wait is bounded, and a time-out latches an
+//     error word (ctl[2]) that the host turns into RS_E_HIP.
+// Compute waves only load; the writer wave stores (see above).
+constexpr int RAS_SPIN_LIMIT = 1 << 20;     // polls with a short sleep: about a second
+
+__device__ __forceinline__ void ras_put(uint64_t *p, float v, uint32_t tag) {
+  __hip_atomic_store(p, ((uint64_t)tag << 32) | (uint64_t)__float_as_uint(v), __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+}
+// value of the word at p once its tag is `tag`; false on time-out
+__device__ __forceinline__ bool ras_get(const uint64_t *p, uint32_t tag, float &v, bool &failed) {
+  int spins = 0;
+  for (;;) {
+    uint64_t w = __hip_atomic_load(const_cast<uint64_t *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if ((uint32_t)(w >> 32) == tag) { v = __uint_as_float((uint32_t)w); return true; }
+    if (failed || ++spins > RAS_SPIN_LIMIT) { failed = true; return false; }
+    __builtin_amdgcn_s_sleep(1);
+  }
+}
+
+// store the outputs of level lam (own lines [j0, j1)) from an LDS ring
+// buffer [H+2][4] (slot of line j: j - j0 + 1) to out, in wavefront order
+// (WF) or natural order
+template <bool WF>
+__device__ __forceinline__ void ras_write_strip(int lam, int nx, int ny, int j0, int j1, int64_t cl,
+                                                const float *__restrict__ src, float *__restrict__ out, int w, int nw) {
+  if (lam < 0 || lam > nx + ny - 2) return;
+  const int jlo = max(j0, lam - nx + 1), jhi = min(j1 - 1, lam);
+  const int64_t base = WF ? cl + wf_off(lam, nx, ny) - max(0, lam - nx + 1) : 0;
+  for (int j = jlo + w; j <= jhi; j += nw) {
+    const int64_t c = WF ? base + j : cl + (int64_t)j * nx + (lam - j);
+    *(float4 *)(out + 4 * c) = *(const float4 *)(src + 4 * (j - j0 + 1));
+  }
+}
+
+// word of the boundary value (row r) of strip s of layer k at column i
+__device__ __forceinline__ int64_t ras_xword(int k, int s, int S, int nx, int i) {
+  return (((int64_t)k * S + s) * nx + i) * 4;
+}
+
 template <class T> struct ras_f1 { T r[4], a1[16], a2[16]; };
 
-template <class T, int U, int P>
-__global__ __launch_bounds__(320) void k_ras_fwd1(int nx, int ny, int64_t n, int LW, const T *__restrict__ blk,
-                                                   const T *__restrict__ rh, T *__restrict__ y) {
+template <int U, int P>
+__global__ __launch_bounds__(320) void k_ras_fwd1(int nx, int ny, int nz, int S, int H, int64_t n, int LW,
+                                                  const float *__restrict__ blk, const float *__restrict__ rh,
+                                                  float *__restrict__ y, int *__restrict__ ctl,
+                                                  uint64_t *__restrict__ xw, uint32_t tag) {
   extern __shared__ __align__(16) unsigned char smem[];
-  T *ring = (T *)smem;                                  // [2][ny][4]
+  float *ring = (float *)smem;                          // [2][H+2][4]
+  __shared__ int s_t;
+  __shared__ float gh[32][4];                           // ghost line j0-1, by level mod 32
   const int tid = threadIdx.x;
+  if (tid == 0) s_t = atomicAdd(&ctl[0], 1);
+  __syncthreads();
+  const int s = s_t / nz, k = s_t - (s_t / nz) * nz;
+  const int j0 = s * H, j1 = min(ny, j0 + H), RS = H + 2;
   const bool compute = tid < LW;                        // wave-uniform (LW is a multiple of 64)
-  const int w = tid - LW, nw = blockDim.x - LW;
-  const int64_t nxy = (int64_t)nx * ny, cl = nxy * blockIdx.x;
-  const int Lv = nx + ny - 1, Lpad = (Lv + P - 1) / P * P;
+  const int64_t nxy = (int64_t)nx * ny, cl = nxy * k;
+  const int Lw = nx + (j1 - j0) - 1, Lpad = (Lw + P - 1) / P * P;   // levels j0 .. j0+Lw-1
   if (!compute) {
-    for (int lam = 0; lam < Lpad; ++lam) {
-      ras_write_level<T, true>(lam - 1, nx, ny, cl, ring + ((lam & 1) ^ 1) * ny * 4, y, w, nw);
+    const int w = tid - LW, nw = blockDim.x - LW;
+    bool failed = false;
+    // ghost line j0-1 for local level m (cell i = m) goes to gh[m % 32]; the
+    // writer fetches 16 levels at a time (64 lanes: level offset, block row),
+    // 16 levels ahead of their use, so the neighbour's words are normally
+    // published by then and one load latency covers 16 levels
+    auto fetch16 = [&](int m16) {
+      const int m = m16 + (w >> 2), r = w & 3;
+      if (s == 0 || w >= 64 || m >= nx) return;
+      float v;
+      if (!ras_get(xw + ras_xword(k, s - 1, S, nx, m) + r, tag, v, failed)) atomicOr(&ctl[2], 1);
+      gh[m & 31][r] = v;
+    };
+    // own last line j1-1 at local level m (cell i = m + j0 - (j1-1)), buffer m&1
+    auto publish = [&](int m) {
+      if (s == S - 1 || w >= 4 || m < 0) return;
+      const int i = m + j0 - (j1 - 1);
+      if (i < 0 || i >= nx) return;
+      ras_put(xw + ras_xword(k, s, S, nx, i) + w, ring[(m & 1) * RS * 4 + (j1 - j0) * 4 + w], tag);
+    };
+    fetch16(0);
+    __syncthreads();
+    for (int m = 0; m < Lpad; ++m) {
+      ras_write_strip<true>(j0 + m - 1, nx, ny, j0, j1, cl, ring + ((m + 1) & 1) * RS * 4, y, w, nw);
+      publish(m - 1);
+      if ((m & 15) == 0) fetch16(m + 16);
       __syncthreads();
     }
-    ras_write_level<T, true>(Lpad - 1, nx, ny, cl, ring + ((Lpad - 1) & 1) * ny * 4, y, w, nw);
+    ras_write_strip<true>(j0 + Lpad - 1, nx, ny, j0, j1, cl, ring + ((Lpad + 1) & 1) * RS * 4, y, w, nw);
+    publish(Lpad - 1);
     return;
   }
-  const T *By = blk, *Bx = blk + n * 16;
-  ras_f1<T> R[P][U];
-  auto load = [&](int lam, ras_f1<T> &p, int u, T tok) {
-    int j = tid + LW * u;
+  __syncthreads();
+  const float *By = blk, *Bx = blk + n * 16;
+  ras_f1<float> R[P][U];
+  auto load = [&](int m, ras_f1<float> &p, int u, float tok) {
+    int j = j0 + tid + LW * u;
     order_after(j, tok);
-    const int64_t c = wf_clamped(cl, lam, j, nx, ny);
+    const int64_t c = wf_clamped(cl, j0 + m, j, nx, ny);
     ld4v(rh + 4 * c, p.r);
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      T t4[4];
-      ld4v(By + c * 16 + 4 * m, t4);
+    for (int q = 0; q < 4; ++q) {
+      float t4[4];
+      ld4v(By + c * 16 + 4 * q, t4);
 #pragma unroll
-      for (int e = 0; e < 4; ++e) p.a1[4 * m + e] = t4[e];
-      ld4v(Bx + c * 16 + 4 * m, t4);
+      for (int e = 0; e < 4; ++e) p.a1[4 * q + e] = t4[e];
+      ld4v(Bx + c * 16 + 4 * q, t4);
 #pragma unroll
-      for (int e = 0; e < 4; ++e) p.a2[4 * m + e] = t4[e];
+      for (int e = 0; e < 4; ++e) p.a2[4 * q + e] = t4[e];
     }
   };
 #pragma unroll
   for (int d = 0; d < P; ++d)
 #pragma unroll
-    for (int u = 0; u < U; ++u) load(d, R[d][u], u, (T)0);
-  for (int lam0 = 0; lam0 < Lpad; lam0 += P) {
+    for (int u = 0; u < U; ++u) load(d, R[d][u], u, 0.f);
+  for (int m0 = 0; m0 < Lpad; m0 += P) {
 #pragma unroll
     for (int d = 0; d < P; ++d) {
-      const int lam = lam0 + d;
-      T *cur = ring + (lam & 1) * ny * 4;
-      const T *prv = ring + ((lam & 1) ^ 1) * ny * 4;
+      const int m = m0 + d, lam = j0 + m;
+      float *cur = ring + (m & 1) * RS * 4;
+      const float *prv = ring + ((m + 1) & 1) * RS * 4;
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int j = tid + LW * u, i = lam - j;
-        const bool act = j < ny && i >= 0 && i < nx;
-        const int jr = min(j, ny - 1);
-        T yy[4], yx[4], v[4];
-        ld4v(prv + 4 * max(jr - 1, 0), yy);
-        ld4v(prv + 4 * jr, yx);
+        const int j = j0 + tid + LW * u, i = lam - j;
+        const bool act = j < j1 && i >= 0 && i < nx;
+        const int sl = min(j, j1 - 1) - j0 + 1;         // slot of line j
+        float yy[4], yx[4], v[4];
+        ld4v(sl == 1 ? &gh[m & 31][0] : prv + 4 * (sl - 1), yy);   // line j0-1: the ghost
+        ld4v(prv + 4 * sl, yx);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          T a1r[4] = {R[d][u].a1[4 * r], R[d][u].a1[4 * r + 1], R[d][u].a1[4 * r + 2], R[d][u].a1[4 * r + 3]};
-          T a2r[4] = {R[d][u].a2[4 * r], R[d][u].a2[4 * r + 1], R[d][u].a2[4 * r + 2], R[d][u].a2[4 * r + 3]};
-          const T ty = dot4(a1r, yy), tx = dot4(a2r, yx);
-          T vr = R[d][u].r[r];
+          float a1r[4] = {R[d][u].a1[4 * r], R[d][u].a1[4 * r + 1], R[d][u].a1[4 * r + 2], R[d][u].a1[4 * r + 3]};
+          float a2r[4] = {R[d][u].a2[4 * r], R[d][u].a2[4 * r + 1], R[d][u].a2[4 * r + 2], R[d][u].a2[4 * r + 3]};
+          const float ty = dot4(a1r, yy), tx = dot4(a2r, yx);
+          float vr = R[d][u].r[r];
           vr = (act && j > 0) ? vr - ty : vr;
           vr = (act && i > 0) ? vr - tx : vr;
           v[r] = vr;
         }
-        if (act) *(typename vec4t<T>::type *)(cur + 4 * j) = typename vec4t<T>::type{v[0], v[1], v[2], v[3]};
-        load(lam + P, R[d][u], u, v[3]);
+        if (act) *(float4 *)(cur + 4 * sl) = make_float4(v[0], v[1], v[2], v[3]);
+        load(m + P, R[d][u], u, v[3]);
       }
       __syncthreads();
     }
@@ -514,84 +597,117 @@ __global__ __launch_bounds__(320) void k_ras_fwd1(int nx, int ny, int64_t n, int
 
 template <class T> struct ras_b1 { T yc[4], xpc, a4[16], a5[16]; };
 
-template <class T, int U, int P>
-__global__ __launch_bounds__(320) void k_ras_bwd1(int nx, int ny, int64_t n, int LW, const T *__restrict__ blk,
-                                                   const T *__restrict__ y, const T *__restrict__ xpw,
-                                                   T *__restrict__ out) {
+template <int U, int P>
+__global__ __launch_bounds__(320) void k_ras_bwd1(int nx, int ny, int nz, int S, int H, int64_t n, int LW,
+                                                  const float *__restrict__ blk, const float *__restrict__ y,
+                                                  const float *__restrict__ xpw, float *__restrict__ out,
+                                                  int *__restrict__ ctl, uint64_t *__restrict__ xw, uint32_t tag) {
   extern __shared__ __align__(16) unsigned char smem[];
-  T *ring = (T *)smem;                                  // [2][ny][4]: z
-  T *oring = ring + 2 * ny * 4;                         // [2][ny][4]: output
+  float *ring = (float *)smem;                          // [2][H+2][4]: z
+  __shared__ int s_t;
+  __shared__ float gh[32][4];                           // ghost line j1, by step mod 32
   const int tid = threadIdx.x;
+  if (tid == 0) s_t = atomicAdd(&ctl[1], 1);
+  __syncthreads();
+  const int st = s_t / nz, k = s_t - st * nz, s = S - 1 - st;   // last strip first
+  const int j0 = s * H, j1 = min(ny, j0 + H), RS = H + 2, nl = j1 - j0;
+  float *oring = ring + 2 * RS * 4;                     // [2][H+2][4]: output
   const bool compute = tid < LW;
-  const int w = tid - LW, nw = blockDim.x - LW;
-  const int64_t nxy = (int64_t)nx * ny, cl = nxy * blockIdx.x;
-  const int Lv = nx + ny - 1, Lpad = (Lv + P - 1) / P * P;
+  const int64_t nxy = (int64_t)nx * ny, cl = nxy * k;
+  const int Lw = nx + nl - 1, Lpad = (Lw + P - 1) / P * P;
+  const int ltop = j1 - 1 + nx - 1;                     // step m handles level ltop - m
   if (!compute) {
-    for (int step = 0; step < Lpad; ++step) {
-      ras_write_level<T, false>(step >= 1 ? Lv - step : -1, nx, ny, cl, oring + ((step & 1) ^ 1) * ny * 4, out, w,
-                                nw);
+    const int w = tid - LW, nw = blockDim.x - LW;
+    bool failed = false;
+    // ghost line j1 for step m (cell i = ltop - m - (j1-1)) goes to gh[m % 32],
+    // fetched 16 steps at a time, 16 steps ahead (as in the forward sweep)
+    auto fetch16 = [&](int m16) {
+      const int m = m16 + (w >> 2), r = w & 3;
+      const int i = ltop - m - (j1 - 1);
+      if (s == S - 1 || w >= 64 || i < 0 || i >= nx) return;
+      float v;
+      if (!ras_get(xw + ras_xword(k, s + 1, S, nx, i) + r, tag, v, failed)) atomicOr(&ctl[2], 1);
+      gh[m & 31][r] = v;
+    };
+    // own first line j0 at step m (cell i = ltop - m - j0), buffer m&1, slot 1
+    auto publish = [&](int m) {
+      if (s == 0 || w >= 4 || m < 0) return;
+      const int i = ltop - m - j0;
+      if (i < 0 || i >= nx) return;
+      ras_put(xw + ras_xword(k, s, S, nx, i) + w, ring[(m & 1) * RS * 4 + 4 + w], tag);
+    };
+    fetch16(0);
+    __syncthreads();
+    for (int m = 0; m < Lpad; ++m) {
+      if (m >= 1) ras_write_strip<false>(ltop - m + 1, nx, ny, j0, j1, cl, oring + ((m + 1) & 1) * RS * 4, out, w, nw);
+      publish(m - 1);
+      if ((m & 15) == 0) fetch16(m + 16);
       __syncthreads();
     }
-    ras_write_level<T, false>(Lv - Lpad, nx, ny, cl, oring + ((Lpad - 1) & 1) * ny * 4, out, w, nw);
+    ras_write_strip<false>(ltop - Lpad + 1, nx, ny, j0, j1, cl, oring + ((Lpad + 1) & 1) * RS * 4, out, w, nw);
+    publish(Lpad - 1);
     return;
   }
-  const T *Bx = blk + 2 * n * 16, *By = blk + 3 * n * 16;
-  ras_b1<T> R[P][U];
-  auto load = [&](int step, ras_b1<T> &p, int u, T tok) {
-    int j = tid + LW * u;
+  __syncthreads();
+  const float *Bx = blk + 2 * n * 16, *By = blk + 3 * n * 16;
+  ras_b1<float> R[P][U];
+  auto load = [&](int m, ras_b1<float> &p, int u, float tok) {
+    int j = j0 + tid + LW * u;
     order_after(j, tok);
-    const int64_t c = wf_clamped(cl, Lv - 1 - step, j, nx, ny);
+    const int64_t c = wf_clamped(cl, ltop - m, j, nx, ny);
     ld4v(y + 4 * c, p.yc);
     p.xpc = xpw[c];
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      T t4[4];
-      ld4v(Bx + c * 16 + 4 * m, t4);
+    for (int q = 0; q < 4; ++q) {
+      float t4[4];
+      ld4v(Bx + c * 16 + 4 * q, t4);
 #pragma unroll
-      for (int e = 0; e < 4; ++e) p.a4[4 * m + e] = t4[e];
-      ld4v(By + c * 16 + 4 * m, t4);
+      for (int e = 0; e < 4; ++e) p.a4[4 * q + e] = t4[e];
+      ld4v(By + c * 16 + 4 * q, t4);
 #pragma unroll
-      for (int e = 0; e < 4; ++e) p.a5[4 * m + e] = t4[e];
+      for (int e = 0; e < 4; ++e) p.a5[4 * q + e] = t4[e];
     }
   };
 #pragma unroll
   for (int d = 0; d < P; ++d)
 #pragma unroll
-    for (int u = 0; u < U; ++u) load(d, R[d][u], u, (T)0);
-  for (int s0 = 0; s0 < Lpad; s0 += P) {
+    for (int u = 0; u < U; ++u) load(d, R[d][u], u, 0.f);
+  for (int m0 = 0; m0 < Lpad; m0 += P) {
 #pragma unroll
     for (int d = 0; d < P; ++d) {
-      const int step = s0 + d;
-      const int lam = Lv - 1 - step;
-      const int cb = (step & 1) * ny * 4, pb = ((step & 1) ^ 1) * ny * 4;
+      const int m = m0 + d, lam = ltop - m;
+      const int cb = (m & 1) * RS * 4, pb = ((m + 1) & 1) * RS * 4;
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int j = tid + LW * u, i = lam - j;
-        const bool act = j < ny && i >= 0 && i < nx;
-        const int jr = min(j, ny - 1);
-        T zx[4], zy[4], z[4];
-        ld4v(ring + pb + 4 * jr, zx);
-        ld4v(ring + pb + 4 * min(jr + 1, ny - 1), zy);
+        const int j = j0 + tid + LW * u, i = lam - j;
+        const bool act = j < j1 && i >= 0 && i < nx;
+        const int sl = min(j, j1 - 1) - j0 + 1;
+        float zx[4], zy[4], z[4];
+        ld4v(ring + pb + 4 * sl, zx);
+        ld4v(sl == nl ? &gh[m & 31][0] : ring + pb + 4 * (sl + 1), zy);   // line j1: the ghost
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          T a4r[4] = {R[d][u].a4[4 * r], R[d][u].a4[4 * r + 1], R[d][u].a4[4 * r + 2], R[d][u].a4[4 * r + 3]};
-          T a5r[4] = {R[d][u].a5[4 * r], R[d][u].a5[4 * r + 1], R[d][u].a5[4 * r + 2], R[d][u].a5[4 * r + 3]};
-          const T tx = dot4(a4r, zx), ty = dot4(a5r, zy);
-          T zr = R[d][u].yc[r];
+          float a4r[4] = {R[d][u].a4[4 * r], R[d][u].a4[4 * r + 1], R[d][u].a4[4 * r + 2], R[d][u].a4[4 * r + 3]};
+          float a5r[4] = {R[d][u].a5[4 * r], R[d][u].a5[4 * r + 1], R[d][u].a5[4 * r + 2], R[d][u].a5[4 * r + 3]};
+          const float tx = dot4(a4r, zx), ty = dot4(a5r, zy);
+          float zr = R[d][u].yc[r];
           zr = (act && i < nx - 1) ? zr - tx : zr;
           zr = (act && j < ny - 1) ? zr - ty : zr;
           z[r] = zr;
         }
         if (act) {
-          *(typename vec4t<T>::type *)(ring + cb + 4 * j) = typename vec4t<T>::type{z[0], z[1], z[2], z[3]};
-          *(typename vec4t<T>::type *)(oring + cb + 4 * j) =
-              typename vec4t<T>::type{z[0] + R[d][u].xpc, z[1], z[2], z[3]};
+          *(float4 *)(ring + cb + 4 * sl) = make_float4(z[0], z[1], z[2], z[3]);
+          *(float4 *)(oring + cb + 4 * sl) = make_float4(z[0] + R[d][u].xpc, z[1], z[2], z[3]);
         }
-        load(step + P, R[d][u], u, z[3]);
+        load(m + P, R[d][u], u, z[3]);
       }
       __syncthreads();
     }
   }
+}
+
+__global__ void k_ras_reset(int *__restrict__ ctl) {
+  if (threadIdx.x < 2) ctl[threadIdx.x] = 0;
 }
 
 // launch shape of the sweeps: LW lines per pass (a multiple of 16, so whole
@@ -628,6 +744,19 @@ rs_status rs_ras_setup_run(rs_cpr_s *M, int *flag, hipStream_t s) {
   size_t lds = es * 16 * (size_t)g.ny;
   RS_TRY(M->rblk.alloc(es * 4 * 16 * (size_t)g.n));
   RS_TRY(M->rxp.alloc(es * (size_t)g.n));
+  if (M->prec == 32) {
+    // strips per layer: enough workgroups for the CUs, at least 32 lines each
+    int S = std::max(1, std::min(256 / std::max(g.nz, 1), (g.ny + 31) / 32));
+    int H = (g.ny + S - 1) / S;
+    S = (g.ny + H - 1) / H;                          // every strip non-empty
+    M->rs_strips = S; M->rs_h = H;
+    const size_t words = (size_t)g.nz * S * g.nx * 4;
+    RS_TRY(M->rxw.alloc(sizeof(uint64_t) * words));
+    RS_TRY(M->rctl.alloc(sizeof(int) * 4));
+    RS_HIP(hipMemsetAsync(M->rxw.p, 0, sizeof(uint64_t) * words, s));
+    RS_HIP(hipMemsetAsync(M->rctl.p, 0, sizeof(int) * 4, s));
+    M->repoch = 0;
+  }
 #define RS_RSET(T, UU, PP)                                                                            \
   k_ras_setup<T, UU, PP><<<g.nz, lw + 64, lds, s>>>(g.nx, g.ny, g.n, lw, M->D->t7.as<T>(), M->dinv2.as<T>(), flag)
   if (M->prec == 64) {
@@ -675,19 +804,25 @@ rs_status rs_ras_apply_run(rs_cpr_s *M, const T *xp, T *out, hipStream_t s) {
   } while (0)
   const size_t ring_bytes = sizeof(T) * 8 * (size_t)g.ny;     // two levels of [ny][4]
   if constexpr (sizeof(T) == 4) {
-    // one lane per line, at most 240 lines per pass, and one writer wave
-    const int u1 = g.ny <= 240 ? 1 : (g.ny <= 480 ? 2 : 4);
-    const int lw1 = ((g.ny + u1 - 1) / u1 + 63) / 64 * 64, nt1 = lw1 + 64;
-    if (u1 == 1) {
-      k_ras_fwd1<T, 1, 4><<<g.nz, nt1, ring_bytes, s>>>(g.nx, g.ny, g.n, lw1, blk, rh, y);
-      k_ras_bwd1<T, 1, 4><<<g.nz, nt1, 2 * ring_bytes, s>>>(g.nx, g.ny, g.n, lw1, blk, y, xpw, out);
-    } else if (u1 == 2) {
-      k_ras_fwd1<T, 2, 2><<<g.nz, nt1, ring_bytes, s>>>(g.nx, g.ny, g.n, lw1, blk, rh, y);
-      k_ras_bwd1<T, 2, 2><<<g.nz, nt1, 2 * ring_bytes, s>>>(g.nx, g.ny, g.n, lw1, blk, y, xpw, out);
-    } else {
-      k_ras_fwd1<T, 4, 1><<<g.nz, nt1, ring_bytes, s>>>(g.nx, g.ny, g.n, lw1, blk, rh, y);
-      k_ras_bwd1<T, 4, 1><<<g.nz, nt1, 2 * ring_bytes, s>>>(g.nx, g.ny, g.n, lw1, blk, y, xpw, out);
-    }
+    // strips of H lines, one lane per line (at most 256 per pass), one
+    // writer wave per workgroup
+    const int S = M->rs_strips, H = M->rs_h;
+    const int u1 = H <= 256 ? 1 : (H <= 512 ? 2 : 4);
+    const int lw1 = ((H + u1 - 1) / u1 + 63) / 64 * 64, nt1 = lw1 + 64;
+    const size_t rb = sizeof(float) * 8 * (size_t)(H + 2);
+    int *ctl = M->rctl.as<int>();
+    uint64_t *xw = M->rxw.as<uint64_t>();
+    const unsigned nwg = (unsigned)(g.nz * S);
+    k_ras_reset<<<1, 64, 0, s>>>(ctl);
+    const uint32_t tf = ++M->repoch, tb = ++M->repoch;
+#define RS_R1(UU, PP)                                                                                  \
+    do {                                                                                               \
+      k_ras_fwd1<UU, PP><<<nwg, nt1, rb, s>>>(g.nx, g.ny, g.nz, S, H, g.n, lw1, blk, rh, y, ctl, xw, tf); \
+      k_ras_bwd1<UU, PP><<<nwg, nt1, 2 * rb, s>>>(g.nx, g.ny, g.nz, S, H, g.n, lw1, blk, y, xpw, out, ctl, \
+                                                  xw, tb);                                             \
+    } while (0)
+    if (u1 == 1) RS_R1(1, 4); else if (u1 == 2) RS_R1(2, 2); else RS_R1(4, 1);
+#undef RS_R1
     RS_HIP(hipGetLastError());
   } else {
     RS_RDISPATCH(k_ras_fwd, ring_bytes, g.nx, g.ny, g.n, sh.lw, blk, rh, y);

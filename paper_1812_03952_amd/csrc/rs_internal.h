@@ -119,8 +119,12 @@ struct rs_cpr_s {
   int pb = 0, pnj = 0, pnk = 0;
   uint32_t pepoch = 0;       // tag of the last pipelined sweep
   dbuf pord, pdone, pctl, pxch;
-  // RAS sweeps: scaled blocks and x_p in wavefront order
-  dbuf rblk, rxp;
+  // RAS sweeps: scaled blocks and x_p in wavefront order; strips per layer,
+  // their boundary exchange words, [fwd ticket, bwd ticket, error] and the
+  // tag of the last sweep
+  dbuf rblk, rxp, rxw, rctl;
+  int rs_strips = 1, rs_h = 0;
+  uint32_t repoch = 0;
   // CPR work
   dbuf rt, bp, xp, yv, zt;   // prec vectors
   // GMRES work (allocated on first solve)

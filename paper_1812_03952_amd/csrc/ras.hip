@@ -559,16 +559,24 @@ __global__ __launch_bounds__(320) void k_ras_fwd1(int nx, int ny, int nz, int S,
       for (int e = 0; e < 4; ++e) p.a2[4 * q + e] = t4[e];
     }
   };
+  // slot d of R holds level m0 + d; the slot of the previous level is
+  // refilled at the start of each level (before its LDS reads, so that the
+  // load issue overlaps their latency), keeping P-1 levels in flight
 #pragma unroll
-  for (int d = 0; d < P; ++d)
+  for (int d = 0; d < P - 1; ++d)
 #pragma unroll
     for (int u = 0; u < U; ++u) load(d, R[d][u], u, 0.f);
+  float tok[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) tok[u] = 0.f;
   for (int m0 = 0; m0 < Lpad; m0 += P) {
 #pragma unroll
     for (int d = 0; d < P; ++d) {
       const int m = m0 + d, lam = j0 + m;
       float *cur = ring + (m & 1) * RS * 4;
       const float *prv = ring + ((m + 1) & 1) * RS * 4;
+#pragma unroll
+      for (int u = 0; u < U; ++u) load(m + P - 1, R[(d + P - 1) % P][u], u, tok[u]);
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int j = j0 + tid + LW * u, i = lam - j;
@@ -588,7 +596,7 @@ __global__ __launch_bounds__(320) void k_ras_fwd1(int nx, int ny, int nz, int S,
           v[r] = vr;
         }
         if (act) *(float4 *)(cur + 4 * sl) = make_float4(v[0], v[1], v[2], v[3]);
-        load(m + P, R[d][u], u, v[3]);
+        tok[u] = v[3];
       }
       __syncthreads();
     }
@@ -669,14 +677,19 @@ __global__ __launch_bounds__(320) void k_ras_bwd1(int nx, int ny, int nz, int S,
     }
   };
 #pragma unroll
-  for (int d = 0; d < P; ++d)
+  for (int d = 0; d < P - 1; ++d)
 #pragma unroll
     for (int u = 0; u < U; ++u) load(d, R[d][u], u, 0.f);
+  float tok[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) tok[u] = 0.f;
   for (int m0 = 0; m0 < Lpad; m0 += P) {
 #pragma unroll
     for (int d = 0; d < P; ++d) {
       const int m = m0 + d, lam = ltop - m;
       const int cb = (m & 1) * RS * 4, pb = ((m + 1) & 1) * RS * 4;
+#pragma unroll
+      for (int u = 0; u < U; ++u) load(m + P - 1, R[(d + P - 1) % P][u], u, tok[u]);
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int j = j0 + tid + LW * u, i = lam - j;
@@ -699,7 +712,7 @@ __global__ __launch_bounds__(320) void k_ras_bwd1(int nx, int ny, int nz, int S,
           *(float4 *)(ring + cb + 4 * sl) = make_float4(z[0], z[1], z[2], z[3]);
           *(float4 *)(oring + cb + 4 * sl) = make_float4(z[0] + R[d][u].xpc, z[1], z[2], z[3]);
         }
-        load(m + P, R[d][u], u, z[3]);
+        tok[u] = z[3];
       }
       __syncthreads();
     }
@@ -821,7 +834,7 @@ rs_status rs_ras_apply_run(rs_cpr_s *M, const T *xp, T *out, hipStream_t s) {
       k_ras_bwd1<UU, PP><<<nwg, nt1, 2 * rb, s>>>(g.nx, g.ny, g.nz, S, H, g.n, lw1, blk, y, xpw, out, ctl, \
                                                   xw, tb);                                             \
     } while (0)
-    if (u1 == 1) RS_R1(1, 4); else if (u1 == 2) RS_R1(2, 2); else RS_R1(4, 1);
+    if (u1 == 1) RS_R1(1, 5); else if (u1 == 2) RS_R1(2, 3); else RS_R1(4, 2);
 #undef RS_R1
     RS_HIP(hipGetLastError());
   } else {

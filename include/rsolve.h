@@ -217,6 +217,12 @@ rs_status rs_cpr_level(rs_cpr M, int l, int *h_n, int64_t *h_nnz, int32_t *h_rp,
                        int32_t *h_ci, double *h_a, double *h_dl1, int32_t *h_agg);
 /* Second-stage block inverses (16*n doubles, upcast if FP32). */
 rs_status rs_cpr_smoother_get(rs_cpr M, double *h_dinv2);
+/* Inverse of a dense n x n FP64 matrix (row-major, device) by the kernels
+ * that invert the coarsest AMG level (Gauss-Jordan with partial pivoting:
+ * register tiles up to n = 156, one workgroup up to 256, one launch pair per
+ * column beyond); 16 n^2 bytes of scratch.  A zero pivot gives
+ * RS_E_SINGULAR. */
+rs_status rs_dense_inverse(int n, const double *d_a, double *d_inv, void *stream);
 /* One V-cycle on the pressure hierarchy, b -> x (n doubles each, device). */
 rs_status rs_cpr_vcycle(rs_cpr M, const double *d_b, double *d_x, void *stream);
 

@@ -390,6 +390,13 @@ __global__ void k_densify(int n, const int32_t *__restrict__ rp, const int32_t *
   for (int p = rp[i]; p < rp[i + 1]; ++p) row[ci[p]] = a[p];
 }
 
+__global__ void k_augment(int n, const double *__restrict__ a, double *__restrict__ G) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 2 * (int64_t)n * n) return;
+  const int64_t r = t / (2 * n), c = t - r * 2 * n;
+  G[t] = c < n ? a[r * n + c] : (c - n == r ? 1.0 : 0.0);
+}
+
 // Gauss-Jordan with partial pivoting on [A | I] (n x 2n, row-major), one
 // pivot column per pair of launches.
 __global__ void k_gj_pivot(int n, int k, double *__restrict__ G, int *__restrict__ bad) {
@@ -493,97 +500,158 @@ __global__ __launch_bounds__(1024) void k_gj_fused(int n, double *__restrict__ G
   }
 }
 
-// Small coarsest levels (up to about 100 rows) are inverted with the matrix in
-// registers: each row is held by tpr = NT/n threads, thread (r, c0) owning
-// columns c0, c0+tpr, ...  Per column k the owners publish column k to LDS,
-// every wave finds the pivot from it (largest |value|, lowest row on ties),
-// the pivot row and row k go through LDS for the swap, and every thread
-// updates its own entries: the pivot row is scaled (rounded) first and each
-// other row gets G[r][c] -= f * G[k][c] for c > k, as in the launch-per-column
-// form.  The inverse (the right half) is written straight to cinv.
-constexpr int GJ_REG_MAX = 128;
-__device__ __forceinline__ bool gj_better(double v, int i, double bv, int bi) {
-  return v > bv || (v == bv && i < bi);
+// Coarsest levels up to GJ_BLK_MAX rows are inverted in one workgroup with
+// the n x n matrix in registers, by in-place Gauss-Jordan with implicit
+// partial pivoting: rows never move; at step k the pivot is the largest
+// |value| of column k among the rows not yet used as pivots (lowest row on
+// ties), and column k is then reused to hold the column of the inverse that
+// this step creates.  Thread (rg, cg) owns rows rg + nrg*i and columns
+// cg + ncg*j of an R x Q tile, so column k = kc + ncg*j0 always sits in
+// register slot j0, a compile-time index once the loop over j0 is unrolled.
+// Per step:
+//   - the owners of column k publish it to LDS (value, and |value| or -1
+//     for used rows);
+//   - every wave reduces max |value| with DPP and takes the lowest row
+//     holding it from a ballot, and its signed value with a readlane;
+//   - the owners set column k to e_p (the identity column of pivot row p);
+//   - the pivot row's threads publish that row times 1/pivot and zero it;
+//   - every row applies g -= f * prow, with f = -1 on the pivot row.
+// Each entry gets the operations of Gauss-Jordan on [A | I] with row swaps:
+// the same products and fused multiply-adds, in the same order.
+// With p_k the pivot row of step k, the final tile X gives
+// inverse[k][p_k'] = X[p_k][k'], which the last pass scatters.
+constexpr int GJ_BLK_MAX = 156;
+template <int CTRL, int RM>
+__device__ __forceinline__ double gj_dpp_max(double x) {
+  const int a0 = __double2loint(x), a1 = __double2hiint(x);
+  const double o = __hiloint2double(__builtin_amdgcn_update_dpp(a1, a1, CTRL, RM, 0xf, false),
+                                    __builtin_amdgcn_update_dpp(a0, a0, CTRL, RM, 0xf, false));
+  return fmax(x, o);
 }
-template <int NT, int GJ_Q>
-__global__ __launch_bounds__(NT) void k_gj_reg(int n, const double *__restrict__ G0, double *__restrict__ cinv,
+template <int NT, int R, int Q>
+__global__ __launch_bounds__(NT) void k_gj_blk(int n, int ld, const double *__restrict__ G0, double *__restrict__ cinv,
                                                int *__restrict__ bad) {
-  __shared__ double colk[GJ_REG_MAX], prow[2 * GJ_REG_MAX], krow[2 * GJ_REG_MAX];
+  __shared__ double colk[2][GJ_BLK_MAX + 8], cabs[2][GJ_BLK_MAX + 8], prow[GJ_BLK_MAX + 8];
+  __shared__ int pivrow[GJ_BLK_MAX];
   const int tid = threadIdx.x, lane = tid & 63;
-  const int ld = 2 * n, tpr = NT / n;
-  const int r = tid / tpr, c0 = tid - r * tpr;
-  const bool own = r < n;
-  double g[GJ_Q];
+  const int nrg = (n + R - 1) / R, ncg = (n + Q - 1) / Q;
+  const int rg = tid / ncg, cg = tid - rg * ncg;
+  const bool act = rg < nrg;
+  double g[R][Q];
+  bool used[R];
+  int pos[R];
 #pragma unroll
-  for (int q = 0; q < GJ_Q; ++q) {
-    const int c = c0 + tpr * q;
-    g[q] = (own && c < ld) ? G0[(int64_t)r * ld + c] : 0.0;
+  for (int i = 0; i < R; ++i) {
+    used[i] = false;
+    pos[i] = 0;
+    const int row = rg + nrg * i;
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      const int col = cg + ncg * j;
+      g[i][j] = (act && row < n && col < n) ? G0[(int64_t)row * ld + col] : 0.0;
+    }
   }
-  for (int k = 0; k < n; ++k) {
-    if (own) {
+  int b = 0;  // colk / cabs double buffer: step k+1 publishes while step k's f reads finish
 #pragma unroll
-      for (int q = 0; q < GJ_Q; ++q)
-        if (c0 + tpr * q == k) colk[r] = g[q];
-    }
-    __syncthreads();
-    double best = -1.0, bval = 0.0;
-    int bi = k;
-    for (int rr = k + lane; rr < n; rr += 64) {
-      const double x = colk[rr], v = fabs(x);
-      if (gj_better(v, rr, best, bi)) { best = v; bval = x; bi = rr; }
-    }
+  for (int j0 = 0; j0 < Q; ++j0) {
+    for (int kc = 0; kc < ncg; ++kc) {
+      const int k = kc + ncg * j0;
+      if (k >= n) break;
+      if (act && cg == kc) {
 #pragma unroll
-    for (int m = 32; m > 0; m >>= 1) {
-      const double ov = __shfl_xor(best, m, 64), ox = __shfl_xor(bval, m, 64);
-      const int oi = __shfl_xor(bi, m, 64);
-      if (gj_better(ov, oi, best, bi)) { best = ov; bval = ox; bi = oi; }
-    }
-    const int piv = bi;
-    const double inv = 1.0 / bval;
-    if (tid == 0 && !(fabs(bval) > 0.0)) atomicOr(bad, 1);
-    if (own && r == piv) {
-#pragma unroll
-      for (int q = 0; q < GJ_Q; ++q) { const int c = c0 + tpr * q; if (c < ld) prow[c] = g[q]; }
-    }
-    if (own && r == k && piv != k) {
-#pragma unroll
-      for (int q = 0; q < GJ_Q; ++q) { const int c = c0 + tpr * q; if (c < ld) krow[c] = g[q]; }
-    }
-    __syncthreads();
-    if (own) {
-      if (r == k) {
-#pragma unroll
-        for (int q = 0; q < GJ_Q; ++q) {
-          const int c = c0 + tpr * q;
-          if (c < ld) g[q] = (c == k) ? 1.0 : prow[c] * inv;
-        }
-      } else {
-        const bool sw = r == piv;               // this row now holds the old row k
-        const double f = sw ? krow[k] : colk[r];
-#pragma unroll
-        for (int q = 0; q < GJ_Q; ++q) {
-          const int c = c0 + tpr * q;
-          if (c < ld) {
-            const double base = sw ? krow[c] : g[q];
-            if (c > k) {
-              const double t = prow[c] * inv;
-              g[q] = base - f * t;
-            } else {
-              g[q] = base;
-            }
-          }
+        for (int i = 0; i < R; ++i) {
+          const int row = rg + nrg * i;
+          colk[b][row] = g[i][j0];
+          cabs[b][row] = (used[i] || row >= n) ? -1.0 : fabs(g[i][j0]);
         }
       }
-    }
-    __syncthreads();
-  }
-  if (own) {
+      __syncthreads();
+      // pivot: rows lane, lane+64, lane+128
+      double a[3], v[3];
 #pragma unroll
-    for (int q = 0; q < GJ_Q; ++q) {
-      const int c = c0 + tpr * q;
-      if (c >= n && c < ld) cinv[(int64_t)r * n + (c - n)] = g[q];
+      for (int m = 0; m < 3; ++m) {
+        const int rr = lane + 64 * m;
+        a[m] = -1.0;
+        v[m] = 0.0;
+        if (rr < n) { a[m] = cabs[b][rr]; v[m] = colk[b][rr]; }
+      }
+      double mx = fmax(a[0], fmax(a[1], a[2]));
+      mx = gj_dpp_max<0xB1, 0xf>(mx);   // quad_perm [1,0,3,2]
+      mx = gj_dpp_max<0x4E, 0xf>(mx);   // quad_perm [2,3,0,1]
+      mx = gj_dpp_max<0x141, 0xf>(mx);  // row_half_mirror
+      mx = gj_dpp_max<0x140, 0xf>(mx);  // row_mirror
+      mx = gj_dpp_max<0x142, 0xa>(mx);  // row_bcast:15 into rows 1, 3
+      mx = gj_dpp_max<0x143, 0xc>(mx);  // row_bcast:31 into rows 2, 3
+      const double gm = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(mx), 63),
+                                         __builtin_amdgcn_readlane(__double2loint(mx), 63));
+      int p = n - 1;
+      double pv = 0.0;
+#pragma unroll
+      for (int m = 2; m >= 0; --m) {
+        const unsigned long long bm = __ballot(a[m] == gm);
+        if (bm) {
+          const int l = __ffsll(bm) - 1;
+          p = 64 * m + l;
+          pv = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v[m]), l),
+                                __builtin_amdgcn_readlane(__double2loint(v[m]), l));
+        }
+      }
+      if (tid == 0 && !(fabs(pv) > 0.0)) atomicOr(bad, 1);
+      const double inv = 1.0 / pv;
+      if (act && cg == kc) {
+#pragma unroll
+        for (int i = 0; i < R; ++i) g[i][j0] = (rg + nrg * i == p) ? 1.0 : 0.0;
+      }
+      const int rgp = p % nrg, ip = p / nrg;
+      if (act && rg == rgp) {
+#pragma unroll
+        for (int i = 0; i < R; ++i)
+          if (i == ip) {
+#pragma unroll
+            for (int j = 0; j < Q; ++j) {
+              prow[cg + ncg * j] = g[i][j] * inv;
+              g[i][j] = 0.0;
+            }
+          }
+      }
+      if (tid == 0) pivrow[k] = p;
+#pragma unroll
+      for (int i = 0; i < R; ++i)
+        if (rg + nrg * i == p) {
+          used[i] = true;
+          pos[i] = k;
+        }
+      __syncthreads();
+      if (act) {
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+          const int row = rg + nrg * i;
+          const double f = (row == p) ? -1.0 : colk[b][row];
+#pragma unroll
+          for (int j = 0; j < Q; ++j) g[i][j] = fma(-f, prow[cg + ncg * j], g[i][j]);
+        }
+      }
+      b ^= 1;
     }
   }
+  __syncthreads();
+  if (act) {
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      const int row = rg + nrg * i;
+#pragma unroll
+      for (int j = 0; j < Q; ++j) {
+        const int col = cg + ncg * j;
+        if (row < n && col < n) cinv[(int64_t)pos[i] * n + pivrow[col]] = g[i][j];
+      }
+    }
+  }
+}
+
+// Tiles of k_gj_blk: R x Q per thread with 1024 threads (2 x 6 up to n = 108,
+// 4 x 6 up to 156).
+static bool gj_blk_fits(int n, int R, int Q) {
+  return n <= GJ_BLK_MAX && (int64_t)((n + R - 1) / R) * ((n + Q - 1) / Q) <= 1024;
 }
 
 __global__ void k_extract_inv(int n, const double *__restrict__ G, double *__restrict__ inv) {
@@ -591,6 +659,30 @@ __global__ void k_extract_inv(int n, const double *__restrict__ G, double *__res
   if (t >= (int64_t)n * n) return;
   int r = (int)(t / n), c = (int)(t % n);
   inv[t] = G[(int64_t)r * 2 * n + n + c];
+}
+
+// Inverse of the n x n matrix held in the left half of G (n x 2n, row-major,
+// right half the identity; G is overwritten) into cinv (n x n), by the path
+// that fits n.  A zero pivot sets *flag.
+static rs_status dense_inverse_run(int n, double *G, double *cinv, int *flag, hipStream_t s) {
+  if (gj_blk_fits(n, 2, 6)) {
+    k_gj_blk<1024, 2, 6><<<1, 1024, 0, s>>>(n, 2 * n, G, cinv, flag);
+  } else if (gj_blk_fits(n, 4, 6)) {
+    k_gj_blk<1024, 4, 6><<<1, 1024, 0, s>>>(n, 2 * n, G, cinv, flag);
+  } else {
+    if (n <= GJ_FUSED_MAX) {
+      k_gj_fused<<<1, 1024, 0, s>>>(n, G, flag);
+    } else {
+      for (int k = 0; k < n; ++k) {
+        k_gj_pivot<<<1, 256, 0, s>>>(n, k, G, flag);
+        int64_t work = (int64_t)n * (2 * (int64_t)n - (k + 1));
+        if (work > 0) k_gj_elim<<<rs_grid(work), RS_BLOCK, 0, s>>>(n, k, G);
+      }
+    }
+    k_extract_inv<<<rs_grid((int64_t)n * n), RS_BLOCK, 0, s>>>(n, G, cinv);
+  }
+  RS_HIP(hipGetLastError());
+  return RS_OK;
 }
 
 // ---- cycle kernels -----------------------------------------------------------
@@ -879,29 +971,7 @@ rs_status rs_amg_build(rs_cpr_s *M, hipStream_t s) {
     RS_TRY(M->cx.alloc(sizeof(double) * (nC + 1)));
     RS_HIP(hipMemsetAsync(flag.p, 0, sizeof(int), s));
     k_densify<<<rs_grid(nC), RS_BLOCK, 0, s>>>(nC, C->rp.as<int32_t>(), C->ci.as<int32_t>(), C->a.as<double>(), G.as<double>());
-    bool inverted = false;
-    if (nC <= GJ_REG_MAX && (2 * nC + 512 / nC - 1) / (512 / nC) <= 48) {
-      // columns per thread ceil(2n / (NT / n)); 1024 threads while that is at
-      // most 16, else 512 threads (more registers per thread)
-      const int need1024 = (2 * nC + 1024 / nC - 1) / (1024 / nC), need512 = (2 * nC + 512 / nC - 1) / (512 / nC);
-      double *G0 = G.as<double>(), *Ci = M->cinv.as<double>();
-      int *fl = flag.as<int>();
-      if (need1024 <= 8) k_gj_reg<1024, 8><<<1, 1024, 0, s>>>(nC, G0, Ci, fl);
-      else if (need1024 <= 16) k_gj_reg<1024, 16><<<1, 1024, 0, s>>>(nC, G0, Ci, fl);
-      else k_gj_reg<512, 48><<<1, 512, 0, s>>>(nC, G0, Ci, fl);
-      inverted = true;
-    } else if (nC <= GJ_FUSED_MAX) {
-      k_gj_fused<<<1, 1024, 0, s>>>(nC, G.as<double>(), flag.as<int>());
-    } else {
-      for (int k = 0; k < nC; ++k) {
-        k_gj_pivot<<<1, 256, 0, s>>>(nC, k, G.as<double>(), flag.as<int>());
-        int64_t work = (int64_t)nC * (2 * (int64_t)nC - (k + 1));
-        if (work > 0) k_gj_elim<<<rs_grid(work), RS_BLOCK, 0, s>>>(nC, k, G.as<double>());
-      }
-    }
-    if (!inverted)
-      k_extract_inv<<<rs_grid((int64_t)nC * nC), RS_BLOCK, 0, s>>>(nC, G.as<double>(), M->cinv.as<double>());
-    RS_HIP(hipGetLastError());
+    RS_TRY(dense_inverse_run(nC, G.as<double>(), M->cinv.as<double>(), flag.as<int>(), s));
     int h = 0;
     RS_HIP(hipMemcpyAsync(&h, flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
     RS_HIP(hipStreamSynchronize(s));
@@ -991,6 +1061,21 @@ extern "C" rs_status rs_cpr_level(rs_cpr M, int l, int *h_n, int64_t *h_nnz, int
     }
   }
   return RS_OK;
+}
+
+extern "C" rs_status rs_dense_inverse(int n, const double *d_a, double *d_inv, void *stream) {
+  if (n < 1 || !d_a || !d_inv) return RS_E_ARG;
+  hipStream_t s = rs_stream(stream);
+  dbuf G, flag;
+  RS_TRY(G.alloc(sizeof(double) * 2 * (size_t)n * n));
+  RS_TRY(flag.alloc(sizeof(int)));
+  RS_HIP(hipMemsetAsync(flag.p, 0, sizeof(int), s));
+  k_augment<<<rs_grid(2 * (int64_t)n * n), RS_BLOCK, 0, s>>>(n, d_a, G.as<double>());
+  RS_TRY(dense_inverse_run(n, G.as<double>(), d_inv, flag.as<int>(), s));
+  int h = 0;
+  RS_HIP(hipMemcpyAsync(&h, flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
+  RS_HIP(hipStreamSynchronize(s));
+  return h ? RS_E_SINGULAR : RS_OK;
 }
 
 extern "C" rs_status rs_cpr_vcycle(rs_cpr M, const double *d_b, double *d_x, void *stream) {

@@ -81,6 +81,7 @@ def lib():
             "rs_cpr_level": (_i, [_vp, _i, C.POINTER(_i), C.POINTER(_i64), _vp, _vp, _vp, _vp, _vp]),
             "rs_cpr_smoother_get": (_i, [_vp, _vp]),
             "rs_cpr_vcycle": (_i, [_vp, _vp, _vp, _vp]),
+            "rs_dense_inverse": (_i, [_i, _vp, _vp, _vp]),
             "rs_pool_trim": (None, []),
             "rs_pool_usage": (None, [C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
         }
@@ -258,6 +259,14 @@ def cpr_apply(M: Cpr, r, z, stream=None):
 def cpr_vcycle(M: Cpr, b, x, stream=None):
     _check(lib().rs_cpr_vcycle(M.h, _ptr(b, torch.float64, M.A.n), _ptr(x, torch.float64, M.A.n),
                                _stream(stream)), "rs_cpr_vcycle")
+
+
+def dense_inverse(a, inv, stream=None):
+    """inv = a^{-1} for a dense n x n FP64 device matrix (row-major), by the
+    AMG coarsest-level kernels."""
+    n = a.shape[0]
+    _check(lib().rs_dense_inverse(n, _ptr(a, torch.float64, n * n), _ptr(inv, torch.float64, n * n),
+                                  _stream(stream)), "rs_dense_inverse")
 
 
 def assemble(nx, ny, nz, logk, kvkh, tscale, Mf, Mb, B, dt, wcell, wu, row_ptr, vals, stream=None):

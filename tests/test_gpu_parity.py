@@ -295,13 +295,59 @@ def test_bsr_values_must_be_16_byte_aligned():
         rs.bsr_update(B, buf[1:])
 
 
-@pytest.mark.parametrize("dims,lo,hi", [((7, 7, 7), 1, 64), ((10, 10, 6), 65, 86), ((10, 10, 7), 87, 102),
-                                        ((12, 12, 6), 103, 256), ((20, 20, 10), 257, 2048)])
+INV_SIZES = [1, 2, 3, 45, 64, 65, 107, 108, 109, 150, 156, 157, 200, 256, 257, 300]
+
+
+def _inverse(a):
+    inv = torch.empty_like(a)
+    rs.dense_inverse(a, inv)
+    return inv.cpu().numpy()
+
+
+@pytest.mark.parametrize("n", INV_SIZES)
+def test_dense_inverse_needs_pivoting(n):
+    """Coarsest-level inverse on matrices that need row pivoting: a random
+    row permutation of a diagonally dominant matrix (zero diagonal wherever
+    the permutation moves a row) and a Gaussian matrix.  Checked by the
+    definition A X = I and against LAPACK's inverse."""
+    rng = np.random.default_rng(1000 + n)
+    D = rng.standard_normal((n, n)) + np.diag(n + rng.random(n))
+    for A in (D[rng.permutation(n)], rng.standard_normal((n, n))):
+        X = _inverse(dev(np.ascontiguousarray(A)))
+        cond = np.linalg.cond(A)
+        assert np.abs(A @ X - np.eye(n)).max() <= 1e-14 * n * cond
+        assert relerr(X, np.linalg.inv(A)) <= 1e-14 * n * cond
+
+
+@pytest.mark.parametrize("n", [64, 128])
+def test_dense_inverse_ties(n):
+    """Sylvester-Hadamard matrices: every pivot search is a tie between
+    entries of equal magnitude, and H^{-1} = H / n exactly."""
+    H = np.ones((1, 1))
+    while H.shape[0] < n:
+        H = np.block([[H, H], [H, -H]])
+    X = _inverse(dev(H))
+    assert np.abs(X - H / n).max() <= 1e-15
+
+
+@pytest.mark.parametrize("n", [1, 60, 130, 200, 300])
+def test_dense_inverse_singular(n):
+    """A zero row leaves no nonzero pivot for the last column it could hold."""
+    rng = np.random.default_rng(n)
+    A = rng.standard_normal((n, n))
+    A[rng.integers(n)] = 0.0
+    with pytest.raises(rs.RsError):
+        _inverse(dev(A))
+
+
+@pytest.mark.parametrize("dims,lo,hi", [((7, 7, 7), 1, 108), ((11, 11, 6), 89, 108), ((11, 11, 7), 109, 156),
+                                        ((13, 13, 7), 109, 156), ((13, 13, 8), 157, 256), ((20, 20, 10), 257, 2048)])
 def test_coarsest_inverse_paths(dims, lo, hi):
     """Two-level hierarchies whose coarsest level falls in each range of the
-    coarsest-inverse kernels (registers with 1024 or 512 threads, one
-    workgroup in global memory, one launch pair per column): the V-cycle
-    against the oracle's, which inverts by dense LU."""
+    coarsest-inverse kernels (register tiles 2 x 6 up to 108 rows and 4 x 6
+    up to 156, one workgroup in global memory up to 256, one launch pair per
+    column beyond): the V-cycle against the oracle's, which inverts by dense
+    LU."""
     p = _prob(dims, sigma=2.0, shale=0.1)
     A = oracle.assemble(p)
     opts = dict(coarse_n=A.n - 1, max_levels=2)

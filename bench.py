@@ -200,7 +200,7 @@ def main():
         log("cpu baseline: FP64 oracle, one full solve of the same system (1 thread) ...")
         t_cpu, info = cpu_baseline(prob, SMOOTHERS[args.smoother])
         out["cpu_baseline"] = {"value": 1.0 / t_cpu, "unit": "solves/s", "cores": 1, "kind": "oracle",
-                               "sample": f"one FP64 CPR-GMRES solve of {prob.name} (decouple, AMG/DILU setup, "
+                               "sample": f"one FP64 CPR-GMRES solve of {prob.name} (decouple, AMG and {args.smoother} set-up, "
                                          f"GMRES to 1e-8: {info['iters']} iterations), {t_cpu:.1f} s"}
     print(json.dumps(out), flush=True)
 

@@ -108,6 +108,8 @@ def lib():
         L.or_gmres.argtypes = [C.c_int, _i32p, _i32p, _f64p, C.c_void_p, _f64p, _f64p,
                                C.c_int, C.c_double, C.c_int, C.POINTER(Info), C.c_void_p,
                                C.c_int]
+        L.or_bicgstab.argtypes = [C.c_int, _i32p, _i32p, _f64p, C.c_void_p, _f64p, _f64p,
+                                  C.c_double, C.c_int, C.POINTER(Info), C.c_void_p, C.c_int]
         L.or_grad_logk.argtypes = [C.c_int] * 3 + [_f64p, C.c_double, C.c_double, _f64p, _f64p, C.c_int,
                                                    _i32p, _f64p, _f64p, _f64p, _f64p]
         _lib = L
@@ -368,6 +370,22 @@ def gmres(A: BSR, b, M: CPR | None = None, x0=None, restart=30, rtol=1e-8, maxit
                         None if h is None else h.ctypes.data, 0 if h is None else h.shape[0])
     if st < 0:
         _check(st, "or_gmres")
+    d = dict(iters=info.iters, cycles=info.cycles, status=info.status, relres=info.relres)
+    if hist:
+        d["hist"] = h[:info.iters]
+    return x, d
+
+
+def bicgstab(A: BSR, b, M: CPR | None = None, x0=None, rtol=1e-8, maxit=300, hist=False):
+    """Right-preconditioned BiCGSTAB; returns (x, info dict)."""
+    x = np.zeros(4 * A.n) if x0 is None else np.array(x0, dtype=np.float64)
+    info = Info()
+    h = np.zeros(maxit + 1) if hist else None
+    st = lib().or_bicgstab(A.n, A.rp, A.ci, A.v.reshape(-1), None if M is None else M._h,
+                           _c(b, np.float64), x, rtol, maxit, C.byref(info),
+                           None if h is None else h.ctypes.data, 0 if h is None else h.shape[0])
+    if st < 0:
+        _check(st, "or_bicgstab")
     d = dict(iters=info.iters, cycles=info.cycles, status=info.status, relres=info.relres)
     if hist:
         d["hist"] = h[:info.iters]

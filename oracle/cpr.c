@@ -205,6 +205,115 @@ done:
   return status;
 }
 
+/* Right-preconditioned BiCGSTAB (van der Vorst, 1992) for A x = b.  The
+ * paper names BiCGSTAB beside GMRES in Section "Linear Solver" and runs every
+ * experiment with it, without further detail; this is the textbook method
+ * with M applied on the right (p^ = M^{-1} p, s^ = M^{-1} s), so the
+ * residual it updates is that of the original system:
+ *   r = b - A x, shadow r^ = r, rho_0 = alpha = omega = 1, p = v = 0
+ *   iteration i:
+ *     rho_i = (r^, r)                          breakdown if rho_i == 0
+ *     p     = r + (rho_i / rho_{i-1})(alpha / omega) (p - omega v)
+ *     v     = A p^,  alpha = rho_i / (r^, v)   breakdown if (r^, v) == 0
+ *     s     = r - alpha v
+ *     if ||s|| <= rtol ||b||:  x += alpha p^, leave the loop
+ *     t     = A s^,  omega = (t, s) / (t, t)   breakdown if (t, t) == 0
+ *     x    += alpha p^ + omega s^,  r = s - omega t
+ *     leave the loop if ||r|| <= rtol ||b||;  breakdown if omega == 0
+ * (With p = v = 0 the first iteration gives p = r.)  When the loop is left
+ * (estimate met, breakdown, or maxit iterations) the true residual b - A x is
+ * recomputed; if it misses rtol and iterations remain, the method starts
+ * again from it with r^ = r.  A breakdown in the first iteration after a
+ * start ends the solve.  maxit counts iterations (two products with A and
+ * two applications of M each; one of each when it stops at s).
+ * M == NULL means no preconditioner.  hist (optional) receives ||r||/||b||
+ * (||s||/||b|| for an iteration that stops at s) per iteration.
+ * Pinned by: the iterates of an independent implementation of the same
+ * recurrence, convergence in one half-iteration when A is a multiple of I,
+ * the agreement of the updated and the recomputed residual, and the
+ * dense-LU solution on small grids. */
+int or_bicgstab(int n, const int *rp, const int *ci, const double *v, const or_cpr *M,
+                const double *b, double *x, double rtol, int maxit, or_info *info,
+                double *hist, int hist_len) {
+  int64_t N = 4 * (int64_t)n;
+  if (n < 1 || maxit < 0) return OR_E_ARG;
+  double *r = (double *)malloc(sizeof(double) * (size_t)N);
+  double *rh = (double *)malloc(sizeof(double) * (size_t)N);
+  double *p = (double *)malloc(sizeof(double) * (size_t)N);
+  double *vv = (double *)malloc(sizeof(double) * (size_t)N);
+  double *ph = (double *)malloc(sizeof(double) * (size_t)N);
+  double *sh = (double *)malloc(sizeof(double) * (size_t)N);
+  double *t = (double *)malloc(sizeof(double) * (size_t)N);
+  double bnorm = sqrt(dot(N, b, b));
+  int iters = 0, cycles = 0, status = 1;
+  double relres = 0.0;
+  if (!(bnorm == bnorm) || isinf(bnorm)) { status = OR_E_NONFINITE; goto done; }
+  if (bnorm == 0.0) { for (int64_t i = 0; i < N; ++i) x[i] = 0.0; status = 0; goto done; }
+  for (;;) {
+    or_spmv(n, rp, ci, v, x, r);
+    for (int64_t i = 0; i < N; ++i) r[i] = b[i] - r[i];
+    double rn = sqrt(dot(N, r, r));
+    relres = rn / bnorm;
+    if (!(rn == rn) || isinf(rn)) { status = OR_E_NONFINITE; break; }
+    if (rn <= rtol * bnorm) { status = 0; break; }
+    if (iters >= maxit) { status = 1; break; }
+    ++cycles;
+    memcpy(rh, r, sizeof(double) * (size_t)N);
+    for (int64_t i = 0; i < N; ++i) { p[i] = 0.0; vv[i] = 0.0; }
+    double rho_prev = 1.0, alpha = 1.0, omega = 1.0;
+    int first = 1, stop_early = 0;
+    while (iters < maxit) {
+      double rho = dot(N, rh, r);
+      if (rho == 0.0) { stop_early = first; break; }
+      double beta = (rho / rho_prev) * (alpha / omega);
+      for (int64_t i = 0; i < N; ++i) p[i] = r[i] + beta * (p[i] - omega * vv[i]);
+      if (M) or_cpr_apply(M, p, ph); else memcpy(ph, p, sizeof(double) * (size_t)N);
+      or_spmv(n, rp, ci, v, ph, vv);
+      double rv = dot(N, rh, vv);
+      if (rv == 0.0) { stop_early = first; break; }
+      alpha = rho / rv;
+      ++iters;
+      for (int64_t i = 0; i < N; ++i) r[i] = r[i] - alpha * vv[i];   /* r holds s */
+      double sn = sqrt(dot(N, r, r));
+      if (sn <= rtol * bnorm) {
+        for (int64_t i = 0; i < N; ++i) x[i] = x[i] + alpha * ph[i];
+        if (hist && iters - 1 < hist_len) hist[iters - 1] = sn / bnorm;
+        break;
+      }
+      if (M) or_cpr_apply(M, r, sh); else memcpy(sh, r, sizeof(double) * (size_t)N);
+      or_spmv(n, rp, ci, v, sh, t);
+      double tt = dot(N, t, t);
+      if (tt == 0.0) {
+        for (int64_t i = 0; i < N; ++i) x[i] = x[i] + alpha * ph[i];
+        stop_early = first;
+        break;
+      }
+      omega = dot(N, t, r) / tt;
+      for (int64_t i = 0; i < N; ++i) {
+        x[i] = x[i] + alpha * ph[i] + omega * sh[i];
+        r[i] = r[i] - omega * t[i];
+      }
+      double rnn = sqrt(dot(N, r, r));
+      if (hist && iters - 1 < hist_len) hist[iters - 1] = rnn / bnorm;
+      rho_prev = rho;
+      first = 0;
+      if (!(rnn == rnn) || isinf(rnn)) break;
+      if (rnn <= rtol * bnorm || omega == 0.0) break;
+    }
+    if (stop_early) {
+      or_spmv(n, rp, ci, v, x, r);
+      for (int64_t i = 0; i < N; ++i) r[i] = b[i] - r[i];
+      relres = sqrt(dot(N, r, r)) / bnorm;
+      status = relres <= rtol ? 0 : 1;
+      break;
+    }
+  }
+done:
+  if (info) { info->iters = iters; info->cycles = cycles; info->status = status; info->relres = relres; }
+  free(r); free(rh); free(p); free(vv); free(ph); free(sh); free(t);
+  return status;
+}
+
 /* Gradient of J = w^T x, A(theta) x = b, with respect to theta = log k, given
  * the adjoint state lambda (A^T lambda = w) and the solution x:
  *   dJ/dtheta_c = -lambda^T (dA/dtheta_c) x.

@@ -106,6 +106,11 @@ int or_gmres(int n, const int *rp, const int *ci, const double *v, const or_cpr 
              const double *b, double *x, int restart, double rtol, int maxit,
              or_info *info, double *hist, int hist_len);
 
+/* ---- right-preconditioned BiCGSTAB (Section "Linear Solver") */
+int or_bicgstab(int n, const int *rp, const int *ci, const double *v, const or_cpr *M,
+                const double *b, double *x, double rtol, int maxit, or_info *info,
+                double *hist, int hist_len);
+
 /* ---- adjoint gradient with respect to log-permeability */
 int or_grad_logk(int nx, int ny, int nz, const double *logk, double kvkh, double tscale,
                  const double *Mf, const double *Mb, int nw, const int *wcell,

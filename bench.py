@@ -87,7 +87,7 @@ def calibration_copy():
     del src, dst
 
 
-def run_variant(rs, dp, A, prec, steps, warmup, tag, smoother):
+def run_variant(rs, dp, A, prec, steps, warmup, tag, smoother, solver="gmres"):
     import torch
     times, infos, phases = [], [], []
     for it in range(warmup + steps):
@@ -99,7 +99,10 @@ def run_variant(rs, dp, A, prec, steps, warmup, tag, smoother):
         M = rs.cpr_setup(A, D, rs.cpr_opts(smoother=smoother))
         t2 = time.perf_counter()
         x = torch.zeros_like(dp.b)
-        info = rs.gmres_solve(A, M, dp.b, x)
+        if solver == "gmres":
+            info = rs.gmres_solve(A, M, dp.b, x)
+        else:
+            info = rs.bicgstab_solve(A, M, dp.b, x)
         torch.cuda.synchronize()
         t3 = time.perf_counter()
         del M, D
@@ -131,6 +134,9 @@ def main():
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--solvers", default="gmres,bicgstab",
+                    help="comma list of outer solvers, each run with the FP32 preconditioner; the first is the "
+                         "headline (the FP64 variant runs with GMRES when gmres is listed)")
     ap.add_argument("--smoother", choices=list(SMOOTHERS), default="ras")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 1 GiB copy kernel (for counter calibration under rocprofv3 --pmc)")
@@ -158,19 +164,27 @@ def main():
     n = prob.n
 
     res = {}
-    variants = [("fp32", 32)] + ([] if args.no_fp64 else [("fp64", 64)])
-    for tag, prec in variants:
-        times, infos, phases = run_variant(rs, dp, A, prec, args.steps, args.warmup, tag, SMOOTHERS[args.smoother])
+    solvers = [x for x in args.solvers.split(",") if x]
+    if not solvers or any(x not in ("gmres", "bicgstab") for x in solvers):
+        sys.exit("bench.py: --solvers takes gmres and/or bicgstab")
+    variants = []
+    for sv in solvers:
+        variants.append(("fp32" if sv == "gmres" else "bicgstab_fp32", 32, sv))
+        if sv == "gmres" and not args.no_fp64:
+            variants.append(("fp64", 64, "gmres"))
+    for tag, prec, solver in variants:
+        times, infos, phases = run_variant(rs, dp, A, prec, args.steps, args.warmup, tag, SMOOTHERS[args.smoother],
+                                           solver)
         tmax = max(times)
         tmed = float(np.median(times))
         ph = np.median(np.array(phases), axis=0)
         res[tag] = dict(solves_per_s=len(times) / sum(times), ms_per_solve=1e3 * tmed, ms_max=1e3 * tmax,
                         iters=infos[-1]["iters"], relres=infos[-1]["relres"],
-                        ms_decouple=1e3 * ph[0], ms_cpr_setup=1e3 * ph[1], ms_gmres=1e3 * ph[2],
+                        ms_decouple=1e3 * ph[0], ms_cpr_setup=1e3 * ph[1], ms_krylov=1e3 * ph[2], solver=solver,
                         solve_only_per_s=1.0 / ph[2])
     spmv_ms, spmv_bytes = spmv_roofline(rs, A, n)
     achieved = spmv_bytes / (spmv_ms * 1e-3) / 1e9
-    head = res["fp32"]
+    head = res[variants[0][0]]
     steps_total = sum(1 for _ in range(args.steps))
     out = {
         "metric": "CPR-GMRES solves/s + SpMV HBM GB/s at 4M cells; FP32-precond vs FP64",
@@ -188,11 +202,12 @@ def main():
         "config": {"workload": f"{prob.name}: 4x4-block 7-point Jacobian, {n} cells, {4 * n} unknowns, "
                                f"nnzb {A.nnzb}; ABF + CPR(AMG V-cycle, {SMOOTHER_NAMES[args.smoother]}) + FGMRES(30), rtol 1e-8",
                    "cells": n, "unknowns": 4 * n, "nnzb": A.nnzb, "restart": 30, "rtol": 1e-8,
-                   "smoother": args.smoother},
-        "fp32_precond": res["fp32"],
+                   "smoother": args.smoother, "headline_solver": solvers[0]},
+        "fp32_precond": res.get("fp32"),
         "fp64": res.get("fp64"),
+        "bicgstab_fp32_precond": res.get("bicgstab_fp32"),
         "spmv": {"ms": spmv_ms, "GB_per_s": achieved, "bytes": spmv_bytes},
-        "roofline": {"bound": "hbm", "kernel": "k_spmv7<double,false> (y = A x)",
+        "roofline": {"bound": "hbm", "kernel": "k_spmv7<double,false,0> (y = A x)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": spmv_traffic()},
     }

@@ -81,16 +81,24 @@ typedef struct {
 } rs_gmres_opts;
 
 typedef struct {
-  int iters;           /* Arnoldi steps run                                      */
+  double rtol;         /* stop at ||b - A x|| <= rtol ||b|| (default 1e-8)       */
+  int maxit;           /* iterations in total (default 300); each applies A and
+                          M twice (once if it stops half-way)                    */
+} rs_bicgstab_opts;
+
+typedef struct {
+  int iters;           /* Arnoldi steps (GMRES) or iterations (BiCGSTAB) run      */
   int cycles;          /* restart cycles run                                     */
   int status;          /* rs_status of the solve                                 */
   double relres;       /* true FP64 ||b - A x|| / ||b|| at exit                  */
-  double est_relres;   /* last rotated-residual estimate |g_{j+1}| / ||b||        */
+  double est_relres;   /* last residual estimate / ||b||: |g_{j+1}| (GMRES), the
+                          updated ||r|| or ||s|| (BiCGSTAB)                      */
   double ms;           /* wall time of the solve on the stream (hipEvents)       */
 } rs_solve_info;
 
 void rs_cpr_opts_default(rs_cpr_opts *o);
 void rs_gmres_opts_default(rs_gmres_opts *o);
+void rs_bicgstab_opts_default(rs_bicgstab_opts *o);
 const char *rs_status_string(int status);
 
 /* ---- the five calls of the solve ---------------------------------------- */
@@ -138,6 +146,19 @@ rs_status rs_cpr_setup(rs_bsr A, rs_dcpl D, const rs_cpr_opts *o, void *stream,
  * RS_OK when the true residual meets rtol, RS_NOT_CONVERGED at maxit. */
 rs_status rs_gmres_solve(rs_bsr A, rs_cpr M, const double *d_b, double *d_x,
                          const rs_gmres_opts *o, rs_solve_info *info, void *stream);
+
+/* Solve A x = b with BiCGSTAB right-preconditioned by M, the Krylov method
+ * of the paper's experiments (Section "Linear Solver" names it).  The
+ * textbook recurrence with p^ = M^{-1} p, s^ = M^{-1} s; it stops when the
+ * updated residual (||s|| half-way, ||r|| at the end of an iteration) meets
+ * rtol, then recomputes the true residual and starts again from it (shadow
+ * r^ = r) if that misses rtol.  A breakdown ((r^, r), (r^, v) or (t, t)
+ * zero) restarts likewise, and ends the solve when it comes in the first
+ * iteration after a start.  d_x holds the initial guess on entry.  o == NULL
+ * takes the defaults.  The work vectors (7 of 4n entries) live in M.  Returns
+ * RS_OK when the true residual meets rtol, RS_NOT_CONVERGED otherwise. */
+rs_status rs_bicgstab_solve(rs_bsr A, rs_cpr M, const double *d_b, double *d_x,
+                            const rs_bicgstab_opts *o, rs_solve_info *info, void *stream);
 
 /* Adjoint solve A^T lambda = w (not in the paper; gives dJ/dA = -lambda x^T
  * for J = w^T x).  Builds on first use and caches, inside A, the block

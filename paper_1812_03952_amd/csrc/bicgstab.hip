@@ -1,0 +1,309 @@
+// bicgstab.hip -- right-preconditioned BiCGSTAB with M = CPR, the Krylov
+// method the paper's experiments use (Section "Linear Solver" names it beside
+// GMRES).  Textbook recurrence (van der Vorst, 1992) with p^ = M^{-1} p and
+// s^ = M^{-1} s, so the residual it updates is the original system's:
+//   rho_i = (r^, r),  p = r + (rho_i / rho_{i-1})(alpha / omega)(p - omega v)
+//   v = A p^,  alpha = rho_i / (r^, v),  s = r - alpha v
+//   t = A s^,  omega = (t, s) / (t, t),  x += alpha p^ + omega s^,  r = s - omega t
+// One iteration is five launches besides the two CPR applications:
+//   k_bcg_p      p = r + beta (p - omega v)                       (beta from device scalars)
+//   SpMV         v = A p^  with the epilogue dot (r^, v)
+//   k_bcg_s      s = r - alpha v in place of r, ||s||^2
+//   SpMV         t = A s^  with the epilogue dots (t, s), (t, t)
+//   k_bcg_xr     x += alpha p^ + omega s^, r = s - omega t, (r^, r), ||r||^2
+// Every dot is reduced in two fixed-order stages, so a solve is bitwise
+// reproducible.  alpha, beta and omega are formed on the device from the
+// reduced dots; the host reads a few doubles twice per iteration (after s and
+// after r) to test convergence and breakdown.  p^ and s^ are stored in the
+// preconditioner's precision and read as stored, so v = A p^ and t = A s^
+// hold for the stored vectors.
+#include "rs_internal.h"
+#include <math.h>
+#include <string.h>
+
+namespace {
+
+constexpr int NBLK = 1024;   // blocks of the vector kernels (partials per dot)
+
+// Device scalar block (doubles).
+enum {
+  B_RHO = 0,     // rho_i = (r^, r)
+  B_RHOP,        // rho_{i-1}
+  B_ALPHA,
+  B_OMEGA,
+  B_RV,          // (r^, v)
+  B_SN,          // ||s||^2
+  B_TS,          // (t, s)
+  B_TT,          // (t, t)
+  B_RN,          // ||r||^2
+  B_TOTAL
+};
+
+// Two partials per workgroup (dots d0, d1) into part[k * NBLK + blockIdx.x].
+template <int ND>
+__device__ __forceinline__ void store_partials(double d0, double d1, double *__restrict__ part) {
+  __shared__ double sh[2][4];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  double d[2] = {d0, d1};
+#pragma unroll
+  for (int k = 0; k < ND; ++k) {
+    double v = d[k];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if (lane == 0) sh[k][wv] = v;
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < ND)
+    part[(int64_t)threadIdx.x * NBLK + blockIdx.x] =
+        ((sh[threadIdx.x][0] + sh[threadIdx.x][1]) + sh[threadIdx.x][2]) + sh[threadIdx.x][3];
+}
+
+// out[k] = sum of part[k * stride + b], b < nparts, in a fixed order (one
+// workgroup per dot).
+__global__ __launch_bounds__(1024) void k_bcg_reduce(int nparts, int stride, const double *__restrict__ part,
+                                                     double *__restrict__ out) {
+  __shared__ double sh[1024];
+  const int k = blockIdx.x;
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nparts; b += blockDim.x) s += part[(int64_t)k * stride + b];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[k] = sh[0];
+}
+
+// partial ||b||^2
+__global__ __launch_bounds__(256) void k_bcg_norm2(int64_t N, const double *__restrict__ b, double *__restrict__ part) {
+  double acc = 0.0;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < N; t += (int64_t)NBLK * blockDim.x)
+    acc = fma(b[t], b[t], acc);
+  store_partials<1>(acc, 0.0, part);
+}
+
+__global__ void k_bcg_zero(int64_t N, double *__restrict__ x) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < N) x[t] = 0.0;
+}
+
+// start of a cycle: p = v = 0, rho_{i-1} = alpha = omega = 1, rho = ||r||^2
+// (the shadow r^ is a copy of r, so (r^, r) = ||r||^2)
+__global__ void k_bcg_start(int64_t N, double *__restrict__ p, double *__restrict__ v, double *__restrict__ S) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < N) { p[t] = 0.0; v[t] = 0.0; }
+  if (t == 0) {
+    S[B_RHO] = S[B_RN];
+    S[B_RHOP] = 1.0;
+    S[B_ALPHA] = 1.0;
+    S[B_OMEGA] = 1.0;
+  }
+}
+
+// p = r + beta (p - omega v), beta = (rho / rho_prev) (alpha / omega)
+__global__ __launch_bounds__(256) void k_bcg_p(int64_t N, const double *__restrict__ r, const double *__restrict__ v,
+                                               double *__restrict__ p, const double *__restrict__ S) {
+  const double beta = (S[B_RHO] / S[B_RHOP]) * (S[B_ALPHA] / S[B_OMEGA]), omega = S[B_OMEGA];
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < N; t += (int64_t)gridDim.x * blockDim.x)
+    p[t] = r[t] + beta * (p[t] - omega * v[t]);
+}
+
+// alpha = rho / (r^, v);  s = r - alpha v (in place);  partial ||s||^2
+__global__ __launch_bounds__(256) void k_bcg_s(int64_t N, double *__restrict__ r, const double *__restrict__ v,
+                                               double *__restrict__ S, double *__restrict__ part) {
+  const double alpha = S[B_RHO] / S[B_RV];
+  double acc = 0.0;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < N; t += (int64_t)NBLK * blockDim.x) {
+    const double sv = r[t] - alpha * v[t];
+    r[t] = sv;
+    acc = fma(sv, sv, acc);
+  }
+  store_partials<1>(acc, 0.0, part);
+  if (blockIdx.x == 0 && threadIdx.x == 0) S[B_ALPHA] = alpha;
+}
+
+// x += alpha p^ (the iteration stopped at s)
+template <class TZ>
+__global__ void k_bcg_xa(int64_t N, const TZ *__restrict__ ph, const double *__restrict__ S, double *__restrict__ x) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < N) x[t] = x[t] + S[B_ALPHA] * (double)ph[t];
+}
+
+// omega = (t, s) / (t, t);  x += alpha p^ + omega s^;  r = s - omega t;
+// partials (r^, r) and ||r||^2.  (t, t) == 0 (breakdown) takes omega = 0:
+// x += alpha p^ and r = s.
+template <class TZ>
+__global__ __launch_bounds__(256) void k_bcg_xr(int64_t N, const TZ *__restrict__ ph, const TZ *__restrict__ sh,
+                                                const double *__restrict__ tv, const double *__restrict__ rh,
+                                                double *__restrict__ r, double *__restrict__ x,
+                                                const double *__restrict__ S, double *__restrict__ part) {
+  const double alpha = S[B_ALPHA], omega = S[B_TT] != 0.0 ? S[B_TS] / S[B_TT] : 0.0;
+  double a0 = 0.0, a1 = 0.0;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < N; t += (int64_t)NBLK * blockDim.x) {
+    x[t] = x[t] + alpha * (double)ph[t] + omega * (double)sh[t];
+    const double rv = r[t] - omega * tv[t];
+    r[t] = rv;
+    a0 = fma(rh[t], rv, a0);
+    a1 = fma(rv, rv, a1);
+  }
+  store_partials<2>(a0, a1, part);
+}
+
+// after k_bcg_xr's dots are reduced: omega stored, rho_prev = rho, rho = (r^, r)
+__global__ void k_bcg_next(double *__restrict__ S, const double *__restrict__ d) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  S[B_OMEGA] = S[B_TT] != 0.0 ? S[B_TS] / S[B_TT] : 0.0;
+  S[B_RHOP] = S[B_RHO];
+  S[B_RHO] = d[0];
+  S[B_RN] = d[1];
+}
+
+}  // namespace
+
+extern "C" void rs_bicgstab_opts_default(rs_bicgstab_opts *o) {
+  if (!o) return;
+  o->rtol = 1e-8;
+  o->maxit = 300;
+}
+
+static rs_status bcg_read(double *h, const double *d, int cnt, hipStream_t s) {
+  RS_HIP(hipMemcpyAsync(h, d, sizeof(double) * cnt, hipMemcpyDeviceToHost, s));
+  RS_HIP(hipStreamSynchronize(s));
+  return RS_OK;
+}
+
+template <class TZ>
+static rs_status bicgstab_t(rs_bsr_s *A, rs_cpr_s *M, const double *b, double *x, const rs_bicgstab_opts &o,
+                            rs_solve_info *info, hipStream_t s) {
+  const int64_t N = 4 * A->g.n;
+  const unsigned nsp = rs_spmv_blocks(A);
+  const int zp = sizeof(TZ) == 8 ? 64 : 32;
+  if (M->bprec != zp || !M->bvec.p) {
+    RS_TRY(M->bvec.alloc(sizeof(double) * N * 5 + sizeof(TZ) * N * 2));
+    RS_TRY(M->bpart.alloc(sizeof(double) * 2 * ((size_t)nsp > NBLK ? nsp : NBLK)));
+    RS_TRY(M->bscal.alloc(sizeof(double) * (B_TOTAL + 4)));
+    M->bprec = zp;
+  }
+  double *r = M->bvec.as<double>(), *rh = r + N, *p = rh + N, *v = p + N, *tv = v + N;
+  TZ *ph = (TZ *)(tv + N), *shv = ph + N;
+  double *part = M->bpart.as<double>(), *S = M->bscal.as<double>(), *D = S + B_TOTAL;
+  if (!M->bpin) RS_HIP(hipHostMalloc((void **)&M->bpin, sizeof(double) * B_TOTAL, hipHostMallocDefault));
+  double *hp = M->bpin;
+  hipEvent_t e0, e1;
+  RS_HIP(hipEventCreate(&e0));
+  RS_HIP(hipEventCreate(&e1));
+  RS_HIP(hipEventRecord(e0, s));
+  rs_status st = RS_OK;
+  int iters = 0, cycles = 0;
+  double relres = 0.0, est = 0.0;
+  const unsigned gN = rs_grid(N);
+  // host copy of the scalar block, refreshed twice per iteration
+  double *h = hp;
+  auto read_scalars = [&]() -> rs_status { return bcg_read(h, S, B_TOTAL, s); };
+  // r = b - A x and ||r||^2 into S[B_RN]
+  auto residual = [&]() -> rs_status {
+    RS_TRY(rs_spmv_dots(A, x, 64, r, b, 1, nullptr, part, s));
+    k_bcg_reduce<<<1, 1024, 0, s>>>(nsp, nsp, part, S + B_RN);
+    RS_HIP(hipGetLastError());
+    return read_scalars();
+  };
+  do {
+    k_bcg_norm2<<<NBLK, 256, 0, s>>>(N, b, part);
+    k_bcg_reduce<<<1, 1024, 0, s>>>(NBLK, NBLK, part, D);
+    if ((st = bcg_read(h, D, 1, s)) != RS_OK) break;
+    const double bnorm = sqrt(h[0]);
+    if (!isfinite(bnorm)) { st = RS_E_NONFINITE; break; }
+    if (bnorm == 0.0) {
+      k_bcg_zero<<<gN, RS_BLOCK, 0, s>>>(N, x);
+      relres = 0.0;
+      break;
+    }
+    for (;;) {
+      if ((st = residual()) != RS_OK) break;
+      const double rn = sqrt(h[B_RN]);
+      relres = rn / bnorm;
+      if (!isfinite(rn)) { st = RS_E_NONFINITE; break; }
+      if (rn <= o.rtol * bnorm) { st = RS_OK; break; }
+      if (iters >= o.maxit) { st = RS_NOT_CONVERGED; break; }
+      ++cycles;
+      RS_HIP(hipMemcpyAsync(rh, r, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+      k_bcg_start<<<gN, RS_BLOCK, 0, s>>>(N, p, v, S);
+      double rho = h[B_RN];                  // (r^, r) with r^ = r
+      bool first = true, stop_early = false;
+      while (iters < o.maxit) {
+        if (rho == 0.0) { stop_early = first; break; }
+        k_bcg_p<<<NBLK, 256, 0, s>>>(N, r, v, p, S);
+        if ((st = rs_cpr_apply_any(M, p, ph, zp, s)) != RS_OK) break;
+        if ((st = rs_spmv_dots(A, ph, zp, v, nullptr, 1, rh, part, s)) != RS_OK) break;
+        k_bcg_reduce<<<1, 1024, 0, s>>>(nsp, nsp, part, S + B_RV);
+        k_bcg_s<<<NBLK, 256, 0, s>>>(N, r, v, S, part);
+        k_bcg_reduce<<<1, 1024, 0, s>>>(NBLK, NBLK, part, S + B_SN);
+        if ((st = read_scalars()) != RS_OK) break;
+        if (h[B_RV] == 0.0) { stop_early = first; break; }   // r now holds garbage; x is untouched
+        ++iters;
+        const double sn = sqrt(h[B_SN]);
+        est = sn;
+        if (!isfinite(sn)) { st = RS_E_NONFINITE; break; }
+        if (sn <= o.rtol * bnorm) {
+          k_bcg_xa<TZ><<<gN, RS_BLOCK, 0, s>>>(N, ph, S, x);
+          break;
+        }
+        if ((st = rs_cpr_apply_any(M, r, shv, zp, s)) != RS_OK) break;
+        if ((st = rs_spmv_dots(A, shv, zp, tv, nullptr, 2, r, part, s)) != RS_OK) break;
+        k_bcg_reduce<<<2, 1024, 0, s>>>(nsp, nsp, part, S + B_TS);
+        k_bcg_xr<TZ><<<NBLK, 256, 0, s>>>(N, ph, shv, tv, rh, r, x, S, part);
+        k_bcg_reduce<<<2, 1024, 0, s>>>(NBLK, NBLK, part, D);
+        k_bcg_next<<<1, 64, 0, s>>>(S, D);
+        if (hipGetLastError() != hipSuccess) { st = RS_E_HIP; break; }
+        if ((st = read_scalars()) != RS_OK) break;
+        if (h[B_TT] == 0.0) { stop_early = first; break; }   // x += alpha p^ was applied
+        const double rnn = sqrt(h[B_RN]);
+        est = rnn;
+        rho = h[B_RHO];
+        first = false;
+        if (!isfinite(rnn)) break;
+        if (rnn <= o.rtol * bnorm || h[B_OMEGA] == 0.0) break;
+      }
+      if (st != RS_OK) break;
+      if (stop_early) {
+        if ((st = residual()) != RS_OK) break;
+        relres = sqrt(h[B_RN]) / bnorm;
+        st = relres <= o.rtol ? RS_OK : RS_NOT_CONVERGED;
+        break;
+      }
+    }
+    est = bnorm > 0.0 ? est / bnorm : 0.0;
+  } while (0);
+  if (st == RS_OK || st == RS_NOT_CONVERGED) {
+    rs_status e = rs_dilu_check(M, s);
+    if (e != RS_OK) st = e;
+  }
+  float ms = 0.f;
+  (void)hipEventRecord(e1, s);
+  (void)hipEventSynchronize(e1);
+  (void)hipEventElapsedTime(&ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (info) {
+    info->iters = iters;
+    info->cycles = cycles;
+    info->status = st;
+    info->relres = relres;
+    info->est_relres = est;
+    info->ms = ms;
+  }
+  return st;
+}
+
+extern "C" rs_status rs_bicgstab_solve(rs_bsr A, rs_cpr M, const double *d_b, double *d_x,
+                                       const rs_bicgstab_opts *o, rs_solve_info *info, void *stream) {
+  if (info) memset(info, 0, sizeof(*info));
+  if (!A || !M || !d_b || !d_x || d_b == d_x || M->A != A) return RS_E_ARG;
+  rs_bicgstab_opts opts;
+  if (o) opts = *o; else rs_bicgstab_opts_default(&opts);
+  if (opts.maxit < 0 || !(opts.rtol >= 0.0)) return RS_E_ARG;
+  hipStream_t s = rs_stream(stream);
+  return M->prec == 64 ? bicgstab_t<double>(A, M, d_b, d_x, opts, info, s)
+                       : bicgstab_t<float>(A, M, d_b, d_x, opts, info, s);
+}

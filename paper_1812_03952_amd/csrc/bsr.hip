@@ -104,34 +104,63 @@ template <> struct vec4_of<float> {
 // for each of the 7 slots it loads 32 contiguous bytes of A (the 4 entries of
 // row r) and the 4 unknowns of the neighbour (shared by the 4 lanes, served
 // by the L1/L2).  FP64 accumulation; x may be FP64 or FP32.
-template <class TX, bool RES>
+// ND > 0 adds dot products of the result as an epilogue, one deterministic
+// partial per workgroup in part[d * gridDim.x + blockIdx.x]:
+//   ND = 1:  d0 = y . u   (u == nullptr: y . y)
+//   ND = 2:  d0 = y . u,  d1 = y . y
+// so a Krylov step gets (r^, v) or (t, s) and (t, t) without re-reading y.
+template <class TX, bool RES, int ND>
 __global__ __launch_bounds__(256) void k_spmv7(int64_t n, int64_t nx, int64_t nxy,
                                                 const double *__restrict__ a7,
                                                 const TX *__restrict__ x,
                                                 const double *__restrict__ b,
-                                                double *__restrict__ y) {
+                                                double *__restrict__ y,
+                                                const double *__restrict__ u,
+                                                double *__restrict__ part) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= 4 * n) return;
-  int64_t c = t >> 2;
-  int r = (int)(t & 3);
-  double acc = 0.0;
+  const bool valid = t < 4 * n;
+  double yv = 0.0;
+  if (valid) {
+    int64_t c = t >> 2;
+    int r = (int)(t & 3);
+    double acc = 0.0;
 #pragma unroll
-  for (int s = 0; s < 7; ++s) {
-    int64_t q = slot_nbr(c, s, nx, nxy);
-    q = (q < 0 || q >= n) ? c : q;           // off-grid blocks are zero
-    const v2d *ap = (const v2d *)(a7 + ((int64_t)s * n + c) * 16 + 4 * r);
-    // plain loads: the non-temporal hint measured about 8 points of HBM
-    // bandwidth slower here
-    v2d a01 = ap[0];
-    v2d a23 = ap[1];
-    double xv[4];
-    vec4_of<TX>::load(x + 4 * q, xv);
-    acc = fma(a01.x, xv[0], acc);
-    acc = fma(a01.y, xv[1], acc);
-    acc = fma(a23.x, xv[2], acc);
-    acc = fma(a23.y, xv[3], acc);
+    for (int s = 0; s < 7; ++s) {
+      int64_t q = slot_nbr(c, s, nx, nxy);
+      q = (q < 0 || q >= n) ? c : q;           // off-grid blocks are zero
+      const v2d *ap = (const v2d *)(a7 + ((int64_t)s * n + c) * 16 + 4 * r);
+      // plain loads: the non-temporal hint measured about 8 points of HBM
+      // bandwidth slower here
+      v2d a01 = ap[0];
+      v2d a23 = ap[1];
+      double xv[4];
+      vec4_of<TX>::load(x + 4 * q, xv);
+      acc = fma(a01.x, xv[0], acc);
+      acc = fma(a01.y, xv[1], acc);
+      acc = fma(a23.x, xv[2], acc);
+      acc = fma(a23.y, xv[3], acc);
+    }
+    yv = RES ? b[t] - acc : acc;
+    y[t] = yv;
   }
-  y[t] = RES ? b[t] - acc : acc;
+  if (ND > 0) {
+    __shared__ double sh[2][4];
+    double d[2];
+    d[0] = valid ? yv * (u ? u[t] : yv) : 0.0;
+    d[1] = yv * yv;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < ND; ++k) {
+      double v = d[k];
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+      if (lane == 0) sh[k][wv] = v;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < ND)
+      part[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] =
+          ((sh[threadIdx.x][0] + sh[threadIdx.x][1]) + sh[threadIdx.x][2]) + sh[threadIdx.x][3];
+  }
 }
 
 // A^T in the 7-slot layout: slot s of cell c holds the transpose of the
@@ -274,19 +303,42 @@ extern "C" void rs_bsr_destroy(rs_bsr A) { delete A; }
 
 rs_status rs_spmv_any(const rs_bsr_s *A, const void *x, int xprec, double *y, const double *b_minus,
                       hipStream_t s) {
+  return rs_spmv_dots(A, x, xprec, y, b_minus, 0, nullptr, nullptr, s);
+}
+
+unsigned rs_spmv_blocks(const rs_bsr_s *A) { return rs_grid(4 * A->g.n); }
+
+rs_status rs_spmv_dots(const rs_bsr_s *A, const void *x, int xprec, double *y, const double *b_minus,
+                       int nd, const double *u, double *part, hipStream_t s) {
   int64_t n = A->g.n;
   unsigned grid = rs_grid(4 * n);
+  const double *a7 = A->a7.as<double>();
+  const int64_t nx = A->g.nx, nxy = A->g.nxy;
+#define RS_SPMV(TX, RES, ND) \
+  k_spmv7<TX, RES, ND><<<grid, RS_BLOCK, 0, s>>>(n, nx, nxy, a7, (const TX *)x, b_minus, y, u, part)
+  if (nd < 0 || nd > 2 || (nd > 0 && !part)) return RS_E_ARG;
   if (xprec == 64) {
-    if (b_minus)
-      k_spmv7<double, true><<<grid, RS_BLOCK, 0, s>>>(n, A->g.nx, A->g.nxy, A->a7.as<double>(), (const double *)x, b_minus, y);
-    else
-      k_spmv7<double, false><<<grid, RS_BLOCK, 0, s>>>(n, A->g.nx, A->g.nxy, A->a7.as<double>(), (const double *)x, nullptr, y);
+    if (b_minus) {
+      if (nd == 0) RS_SPMV(double, true, 0);
+      else if (nd == 1) RS_SPMV(double, true, 1);
+      else RS_SPMV(double, true, 2);
+    } else {
+      if (nd == 0) RS_SPMV(double, false, 0);
+      else if (nd == 1) RS_SPMV(double, false, 1);
+      else RS_SPMV(double, false, 2);
+    }
   } else {
-    if (b_minus)
-      k_spmv7<float, true><<<grid, RS_BLOCK, 0, s>>>(n, A->g.nx, A->g.nxy, A->a7.as<double>(), (const float *)x, b_minus, y);
-    else
-      k_spmv7<float, false><<<grid, RS_BLOCK, 0, s>>>(n, A->g.nx, A->g.nxy, A->a7.as<double>(), (const float *)x, nullptr, y);
+    if (b_minus) {
+      if (nd == 0) RS_SPMV(float, true, 0);
+      else if (nd == 1) RS_SPMV(float, true, 1);
+      else RS_SPMV(float, true, 2);
+    } else {
+      if (nd == 0) RS_SPMV(float, false, 0);
+      else if (nd == 1) RS_SPMV(float, false, 1);
+      else RS_SPMV(float, false, 2);
+    }
   }
+#undef RS_SPMV
   RS_HIP(hipGetLastError());
   return RS_OK;
 }

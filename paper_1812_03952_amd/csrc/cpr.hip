@@ -159,6 +159,7 @@ extern "C" void rs_cpr_opts_default(rs_cpr_opts *o) {
 rs_cpr_s::~rs_cpr_s() {
   for (amg_level *L : lev) delete L;
   if (hpin) (void)hipHostFree(hpin);
+  if (bpin) (void)hipHostFree(bpin);
 }
 
 extern "C" void rs_cpr_destroy(rs_cpr M) { delete M; }

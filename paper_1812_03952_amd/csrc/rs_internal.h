@@ -131,12 +131,22 @@ struct rs_cpr_s {
   int m = 0;
   dbuf V, Z, w, part, scal;
   double *hpin = nullptr;     // pinned host status word
+  // BiCGSTAB work vectors (r, r^, p, v, t in FP64; p^, s^ in the
+  // preconditioner's precision), partials and scalars
+  dbuf bvec, bpart, bscal;
+  int bprec = 0;
+  double *bpin = nullptr;     // pinned host copy of the scalar block
   ~rs_cpr_s();
 };
 
 // ---- internal entry points shared between translation units ---------------
 rs_status rs_spmv_any(const rs_bsr_s *A, const void *x, int xprec, double *y,
                       const double *b_minus, hipStream_t s);
+// The SpMV with ND epilogue dots (see k_spmv7): partials in
+// part[d * rs_spmv_blocks(A) + block].
+rs_status rs_spmv_dots(const rs_bsr_s *A, const void *x, int xprec, double *y, const double *b_minus,
+                       int nd, const double *u, double *part, hipStream_t s);
+unsigned rs_spmv_blocks(const rs_bsr_s *A);
 rs_status rs_cpr_apply_any(rs_cpr_s *M, const double *r, void *z, int zprec,
                            hipStream_t s);
 rs_status rs_vcycle_run(rs_cpr_s *M, hipStream_t s);

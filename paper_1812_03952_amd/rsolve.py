@@ -37,6 +37,10 @@ class GmresOpts(C.Structure):
     _fields_ = [("restart", C.c_int), ("rtol", C.c_double), ("maxit", C.c_int)]
 
 
+class BicgstabOpts(C.Structure):
+    _fields_ = [("rtol", C.c_double), ("maxit", C.c_int)]
+
+
 class SolveInfo(C.Structure):
     _fields_ = [("iters", C.c_int), ("cycles", C.c_int), ("status", C.c_int),
                 ("relres", C.c_double), ("est_relres", C.c_double), ("ms", C.c_double)]
@@ -59,12 +63,14 @@ def lib():
         sig = {
             "rs_cpr_opts_default": (None, [C.POINTER(CprOpts)]),
             "rs_gmres_opts_default": (None, [C.POINTER(GmresOpts)]),
+            "rs_bicgstab_opts_default": (None, [C.POINTER(BicgstabOpts)]),
             "rs_status_string": (C.c_char_p, [_i]),
             "rs_bsr_create": (_i, [_i, _i, _i, _i, _i64, _vp, _vp, _vp, _vp, C.POINTER(_vp)]),
             "rs_bsr_update": (_i, [_vp, _vp, _vp]),
             "rs_decouple": (_i, [_vp, _i, _i, _vp, C.POINTER(_vp)]),
             "rs_cpr_setup": (_i, [_vp, _vp, C.POINTER(CprOpts), _vp, C.POINTER(_vp)]),
             "rs_gmres_solve": (_i, [_vp, _vp, _vp, _vp, C.POINTER(GmresOpts), C.POINTER(SolveInfo), _vp]),
+            "rs_bicgstab_solve": (_i, [_vp, _vp, _vp, _vp, C.POINTER(BicgstabOpts), C.POINTER(SolveInfo), _vp]),
             "rs_adjoint_solve": (_i, [_vp, _i, _i, C.POINTER(CprOpts), _vp, _vp, C.POINTER(GmresOpts),
                                       C.POINTER(SolveInfo), _vp]),
             "rs_bsr_destroy": (None, [_vp]),
@@ -142,6 +148,14 @@ def cpr_opts(**kw) -> CprOpts:
 def gmres_opts(**kw) -> GmresOpts:
     o = GmresOpts()
     lib().rs_gmres_opts_default(C.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def bicgstab_opts(**kw) -> BicgstabOpts:
+    o = BicgstabOpts()
+    lib().rs_bicgstab_opts_default(C.byref(o))
     for k, v in kw.items():
         setattr(o, k, v)
     return o
@@ -227,6 +241,18 @@ def gmres_solve(A: Bsr, M: Cpr, b, x, opts: GmresOpts | None = None, stream=None
                               None if opts is None else C.byref(opts), C.byref(info), _stream(stream))
     if check:
         _check(st, "rs_gmres_solve", ok=(RS_OK, RS_NOT_CONVERGED))
+    d = info.as_dict()
+    d["return"] = st
+    return d
+
+
+def bicgstab_solve(A: Bsr, M: Cpr, b, x, opts: BicgstabOpts | None = None, stream=None, check=True) -> dict:
+    info = SolveInfo()
+    N = 4 * A.n
+    st = lib().rs_bicgstab_solve(A.h, M.h, _ptr(b, torch.float64, N), _ptr(x, torch.float64, N),
+                                 None if opts is None else C.byref(opts), C.byref(info), _stream(stream))
+    if check:
+        _check(st, "rs_bicgstab_solve", ok=(RS_OK, RS_NOT_CONVERGED))
     d = info.as_dict()
     d["return"] = st
     return d

@@ -75,3 +75,30 @@ def test_full_size_spmv_sampled_rows(cfg):
         for q in range(rp[c], rp[c + 1]):
             acc += vals[q] @ xh[4 * ci[q]:4 * ci[q] + 4]
         assert np.allclose(yh[4 * c:4 * c + 4], acc, rtol=1e-13, atol=1e-13 * np.abs(acc).max())
+
+
+@pytest.mark.parametrize("cfg", [1, 2])
+def test_full_size_bicgstab_against_oracle(cfg):
+    """The same path with BiCGSTAB as the outer solver."""
+    p = synth.config(cfg)
+    dp = rs.DeviceProblem(p)
+    Ao = oracle.assemble(p).with_values(dp.vals.cpu().numpy().reshape(-1, 4, 4))
+    xo, io = oracle.bicgstab(Ao, p.b, oracle.CPR(Ao, smoother=oracle.SM_RAS), rtol=1e-8)
+    assert io["status"] == 0
+    nb = np.linalg.norm(p.b)
+    A = dp.bsr()
+    for prec in (64, 32):
+        rs.bsr_update(A, dp.vals)
+        M = rs.cpr_setup(A, rs.decouple(A, rs.ABF, prec), rs.cpr_opts(smoother=rs.SM_RAS))
+        x = torch.zeros_like(dp.b)
+        info = rs.bicgstab_solve(A, M, dp.b, x, rs.bicgstab_opts(rtol=1e-8))
+        xg = x.cpu().numpy()
+        true = np.linalg.norm(p.b - oracle.spmv(Ao, xg)) / nb
+        err = relerr(xg, xo)
+        print(f"cfg {cfg} prec {prec}: iters {info['iters']} (oracle {io['iters']}), true relres {true:.2e}, "
+              f"|x - x_oracle|/|x_oracle| {err:.2e}")
+        assert info["return"] == 0 and true <= 1e-8 and abs(true - info["relres"]) <= 1e-10
+        if prec == 64:
+            assert info["iters"] == io["iters"] and err <= 1e-9
+        else:
+            assert err <= 1e-5

@@ -22,7 +22,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
 _SRC = ["bsr.c", "decouple.c", "amg.c", "cpr.c"]
 
-ABF, QIMPES = 0, 1
+ABF, QIMPES, FRS, FRS_ABF = 0, 1, 2, 3
 SM_BJ, SM_DILU, SM_RAS = 0, 1, 2
 
 
@@ -90,7 +90,7 @@ def lib():
         L.or_amg_vcycle.restype = None
         L.or_amg_free.argtypes = [C.c_void_p]
         L.or_amg_free.restype = None
-        L.or_cpr_setup.argtypes = [C.c_int, _i32p, _i32p, _f64p, C.c_int, C.c_int, C.c_int64,
+        L.or_cpr_setup.argtypes = [C.c_int, _i32p, _i32p, _f64p, C.c_int, C.c_int, C.c_int64, C.c_int,
                                    C.POINTER(AmgOpts), C.POINTER(C.c_int)]
         L.or_ras_restrict.argtypes = [C.c_int, C.c_int64, _i32p, _i32p, _f64p] + [C.c_void_p] * 3
         L.or_free.argtypes = [C.c_void_p]
@@ -311,16 +311,17 @@ class AMG:
 
 
 class CPR:
-    """Two-stage CPR preconditioner on a block matrix."""
+    """CPR preconditioner on a block matrix: pressure then full (stages=2)
+    or the three-stage CPR-FPF (stages=3)."""
 
-    def __init__(self, A: BSR, method=ABF, smoother=SM_DILU, sub=None, **amg_kw):
+    def __init__(self, A: BSR, method=ABF, smoother=SM_DILU, sub=None, stages=2, **amg_kw):
         """sub: cells per RAS subdomain (SM_RAS only); default nx*ny, the xy-layers."""
         L = lib()
         self.A = A
         self._o = amg_opts(**amg_kw)
         st = C.c_int(0)
         sub = A.nx * A.ny if sub is None else int(sub)
-        self._h = L.or_cpr_setup(A.n, A.rp, A.ci, A.v.reshape(-1), method, smoother, sub,
+        self._h = L.or_cpr_setup(A.n, A.rp, A.ci, A.v.reshape(-1), method, smoother, sub, int(stages),
                                  C.byref(self._o), C.byref(st))
         if st.value != 0:
             L.or_cpr_free(self._h)

@@ -8,7 +8,7 @@
 #include "oracle.h"
 
 struct or_cpr {
-  int n, smoother;
+  int n, smoother, stages;
   int64_t nnzb;
   const int *rp, *ci;      /* borrowed pattern */
   int *rpc, *cic;          /* own copy of the pattern */
@@ -21,26 +21,33 @@ struct or_cpr {
   or_amg *amg;
 };
 
-/* Two-stage CPR of pressure-then-full type.  The paper describes its
- * three-stage CPR-FPF (Section "Preconditioners", Algorithm pc-fpf) as a
- * Schwarz/ILU stage, a pressure stage "y = y + Pi_p AMG(A_PP)^{-1} Pi_r r"
- * and a second Schwarz/ILU stage, with residual updates in between; the
- * printed algorithm repeats its first step as its third.  Here the two-stage
- * form keeps the pressure stage and one full-system stage:
- *    r~  = D^{-1} r                          (decoupling, Eq. decoupled-eq)
- *    x_p = Vcycle(A_p, Pi_r r~)              (Pi_r: unknown 0 of each cell)
- *    r~2 = r~ - A~ Pi_p x_p                  (Pi_p: inject into unknown 0)
- *    z   = M2^{-1} r~2 + Pi_p x_p            (M2: block-Jacobi, DILU, or
- *                                             zero-overlap RAS with DILU in
- *                                             each subdomain, on A~)
- * Pinned by the dense composition [C + M2^{-1}(I - A~ C)] D^{-1} with
- * C = Pi_p A_p^{-1} Pi_r when the AMG is a single exact level. */
+/* CPR of pressure-then-full type (stages = 2) or the three-stage CPR-FPF
+ * (stages = 3) of Section "Preconditioners" (Algorithm pc-fpf).  The printed
+ * algorithm repeats its first step as its third; the text around it gives
+ * five steps, which are what stages = 3 computes, on the decoupled system:
+ *    f   = D^{-1} r                          (decoupling, Eq. decoupled-eq)
+ *    1.  y = M2^{-1} f                       (full-system stage)
+ *    2.  q = f - A~ y
+ *    3.  y = y + Pi_p Vcycle(A_p, Pi_r q)    (pressure stage)
+ *    4.  q = f - A~ y
+ *    5.  y = y + M2^{-1} q                   (full-system stage)
+ * M2 is block Jacobi, DILU, or zero-overlap RAS with DILU in each
+ * subdomain, on A~; Pi_r takes unknown 0, Pi_p injects into unknown 0.
+ * stages = 2 keeps steps 3-5 with y = 0:
+ *    x_p = Vcycle(A_p, Pi_r f),  z = M2^{-1}(f - A~ Pi_p x_p) + Pi_p x_p.
+ * Pinned by the dense compositions, with S = M2^{-1} and
+ * C = Pi_p A_p^{-1} Pi_r when the AMG is a single exact level:
+ *    two-stage    [C + S(I - A~ C)] D^{-1}
+ *    three-stage  [S + (C + S(I - A~ C))(I - A~ S)] D^{-1},
+ * the latter also through its error propagation
+ *    I - A~ M^{-1} D = (I - A~ S)(I - A~ C)(I - A~ S). */
 or_cpr *or_cpr_setup(int n, const int *rp, const int *ci, const double *v,
-                     int method, int smoother, int64_t sub, const or_amg_opts *ao,
-                     int *status) {
+                     int method, int smoother, int64_t sub, int stages,
+                     const or_amg_opts *ao, int *status) {
   or_cpr *M = (or_cpr *)calloc(1, sizeof(or_cpr));
   int64_t nnzb = rp[n];
-  M->n = n; M->smoother = smoother; M->nnzb = nnzb;
+  M->n = n; M->smoother = smoother; M->nnzb = nnzb; M->stages = stages;
+  if (stages != 2 && stages != 3) { *status = OR_E_ARG; return M; }
   M->rpc = (int *)malloc(sizeof(int) * ((size_t)n + 1));
   M->cic = (int *)malloc(sizeof(int) * (size_t)nnzb);
   memcpy(M->rpc, rp, sizeof(int) * ((size_t)n + 1));
@@ -65,29 +72,50 @@ or_cpr *or_cpr_setup(int n, const int *rp, const int *ci, const double *v,
   return M;
 }
 
+static void m2_apply(const or_cpr *M, const double *r, double *z) {
+  int n = M->n;
+  if (M->smoother == OR_SM_DILU) or_dilu_apply(n, M->rp, M->ci, M->vt, M->dinv2, r, z);
+  else if (M->smoother == OR_SM_RAS) or_dilu_apply(n, M->rp2, M->ci2, M->vt2, M->dinv2, r, z);
+  else or_bj_apply(n, M->dinv2, r, z);
+}
+
 void or_cpr_apply(const or_cpr *M, const double *r, double *z) {
   int n = M->n;
-  double *rt = (double *)malloc(sizeof(double) * 4 * (size_t)n);
+  int64_t N = 4 * (int64_t)n;
+  double *f = (double *)malloc(sizeof(double) * (size_t)N);
+  double *q = (double *)malloc(sizeof(double) * (size_t)N);
+  double *w = (double *)malloc(sizeof(double) * (size_t)N);
   double *bp = (double *)malloc(sizeof(double) * (size_t)n);
   double *xp = (double *)malloc(sizeof(double) * (size_t)n);
   for (int64_t i = 0; i < n; ++i)
     for (int a = 0; a < 4; ++a) {
       double s = 0.0;
       for (int c = 0; c < 4; ++c) s = s + M->dinv[16 * i + 4 * a + c] * r[4 * i + c];
-      rt[4 * i + a] = s;
+      f[4 * i + a] = s;
     }
-  for (int64_t i = 0; i < n; ++i) bp[i] = rt[4 * i];
-  or_amg_vcycle(M->amg, bp, xp);
-  for (int64_t i = 0; i < n; ++i)
-    for (int64_t p = M->rp[i]; p < M->rp[i + 1]; ++p) {
-      double xj = xp[M->ci[p]];
-      for (int a = 0; a < 4; ++a) rt[4 * i + a] = rt[4 * i + a] - M->vt[16 * p + 4 * a] * xj;
-    }
-  if (M->smoother == OR_SM_DILU) or_dilu_apply(n, M->rp, M->ci, M->vt, M->dinv2, rt, z);
-  else if (M->smoother == OR_SM_RAS) or_dilu_apply(n, M->rp2, M->ci2, M->vt2, M->dinv2, rt, z);
-  else or_bj_apply(n, M->dinv2, rt, z);
-  for (int64_t i = 0; i < n; ++i) z[4 * i] = z[4 * i] + xp[i];
-  free(rt); free(bp); free(xp);
+  if (M->stages == 2) {
+    for (int64_t i = 0; i < n; ++i) bp[i] = f[4 * i];
+    or_amg_vcycle(M->amg, bp, xp);
+    for (int64_t i = 0; i < n; ++i)
+      for (int64_t p = M->rp[i]; p < M->rp[i + 1]; ++p) {
+        double xj = xp[M->ci[p]];
+        for (int a = 0; a < 4; ++a) f[4 * i + a] = f[4 * i + a] - M->vt[16 * p + 4 * a] * xj;
+      }
+    m2_apply(M, f, z);
+    for (int64_t i = 0; i < n; ++i) z[4 * i] = z[4 * i] + xp[i];
+  } else {
+    m2_apply(M, f, z);                                            /* 1 */
+    or_spmv(n, M->rp, M->ci, M->vt, z, q);                        /* 2 */
+    for (int64_t t = 0; t < N; ++t) q[t] = f[t] - q[t];
+    for (int64_t i = 0; i < n; ++i) bp[i] = q[4 * i];             /* 3 */
+    or_amg_vcycle(M->amg, bp, xp);
+    for (int64_t i = 0; i < n; ++i) z[4 * i] = z[4 * i] + xp[i];
+    or_spmv(n, M->rp, M->ci, M->vt, z, q);                        /* 4 */
+    for (int64_t t = 0; t < N; ++t) q[t] = f[t] - q[t];
+    m2_apply(M, q, w);                                            /* 5 */
+    for (int64_t t = 0; t < N; ++t) z[t] = z[t] + w[t];
+  }
+  free(f); free(q); free(w); free(bp); free(xp);
 }
 
 const double *or_cpr_decoupled(const or_cpr *M) { return M->vt; }

@@ -68,10 +68,19 @@ static int inv4(const double *a, double *out) {
  *  Quasi-IMPES (named in the paper only): w_i solves A_ii^T w_i = e_0 (GJE
  *    on [A_ii^T | e_0]); row 0 of every block in row i becomes w_i^T A_ij,
  *    rows 1-3 are unchanged; D_i^{-1} = [w_i^T; e_1^T; e_2^T; e_3^T].
+ *  FRS (Eq. decoupled-frs): D_i^{-1} = F, the 4x4 matrix with ones in row
+ *    0 and on the diagonal, zeros elsewhere: row 0 of every block (and of
+ *    the right-hand side) becomes the sum of its four rows, summed in row
+ *    order; rows 1-3 are unchanged.
+ *  FRS+ABF (the two-stage decoupling of the same section): FRS first, then
+ *    ABF on the result, i.e. GJE on [F A_ii | F A_i,j | F]:
+ *    A~_ij = (F A_ii)^{-1} F A_ij, D_i^{-1} = (F A_ii)^{-1} F.  In exact
+ *    arithmetic this equals ABF alone, since (F A_ii)^{-1} F = A_ii^{-1}.
  * vt receives the decoupled blocks (same pattern), dinv the 4x4 D_i^{-1}.
  * Pinned by the dense product blockdiag(A)^{-1} A, by A~_ii = I, by the
- * quasi-IMPES pressure row equalling the ABF one, and by D^{-1}A x = D^{-1}b
- * sharing the solution of A x = b. */
+ * quasi-IMPES pressure row equalling the ABF one, by D^{-1}A x = D^{-1}b
+ * sharing the solution of A x = b, by FRS equalling blockdiag(F) A, and by
+ * FRS+ABF equalling ABF to rounding. */
 int or_decouple(int n, const int *rp, const int *ci, const double *v, int method,
                 double *vt, double *dinv) {
   int maxw = 0;
@@ -87,14 +96,18 @@ int or_decouple(int n, const int *rp, const int *ci, const double *v, int method
     if (pd < 0) { status = OR_E_ARG; break; }
     const double *Aii = &v[16 * pd];
     int nb = rp[i + 1] - rp[i];
-    if (method == OR_ABF) {
-      int w = 4 * nb + 4;     /* every block of the row, then I */
+    if (method == OR_ABF || method == OR_FRS_ABF) {
+      int w = 4 * nb + 4;     /* every block of the row, then I (F for FRS+ABF) */
       double L[4][4];
       for (int r = 0; r < 4; ++r) {
         for (int c = 0; c < 4; ++c) L[r][c] = Aii[4 * r + c];
         for (int b = 0; b < nb; ++b)
           for (int c = 0; c < 4; ++c) R[r * w + 4 * b + c] = v[16 * (rp[i] + b) + 4 * r + c];
         for (int c = 0; c < 4; ++c) R[r * w + 4 * nb + c] = (r == c) ? 1.0 : 0.0;
+      }
+      if (method == OR_FRS_ABF) {
+        for (int c = 0; c < 4; ++c) L[0][c] = ((L[0][c] + L[1][c]) + L[2][c]) + L[3][c];
+        for (int c = 0; c < w; ++c) R[c] = ((R[c] + R[w + c]) + R[2 * w + c]) + R[3 * w + c];
       }
       status = gje4(L, R, w);
       if (status != OR_OK) break;
@@ -129,6 +142,15 @@ int or_decouple(int n, const int *rp, const int *ci, const double *v, int method
       for (int e = 0; e < 16; ++e) d[e] = 0.0;
       for (int c = 0; c < 4; ++c) d[c] = e0[c];
       d[5] = d[10] = d[15] = 1.0;
+    } else if (method == OR_FRS) {
+      for (int b = 0; b < nb; ++b) {
+        const double *a = &v[16 * (rp[i] + b)];
+        double *o = &vt[16 * (rp[i] + b)];
+        for (int c = 0; c < 4; ++c) o[c] = ((a[c] + a[4 + c]) + a[8 + c]) + a[12 + c];
+        for (int e = 4; e < 16; ++e) o[e] = a[e];
+      }
+      double *d = &dinv[16 * i];
+      for (int e = 0; e < 16; ++e) d[e] = (e < 4 || e % 5 == 0) ? 1.0 : 0.0;
     } else {
       status = OR_E_ARG;
     }

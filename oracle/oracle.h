@@ -45,6 +45,8 @@ int or_transpose(int n, const int *rp, const int *ci, const double *v, double *v
 /* ---- decoupling (Section "Decoupling Methods", Eqs. decoupled-eq, decoupled-abf) */
 #define OR_ABF 0
 #define OR_QIMPES 1
+#define OR_FRS 2        /* full row sum, Eq. decoupled-frs */
+#define OR_FRS_ABF 3    /* two-stage: FRS, then ABF */
 int or_decouple(int n, const int *rp, const int *ci, const double *v, int method,
                 double *vt, double *dinv);
 void or_extract_pressure(int64_t nnzb, const double *vt, double *ap);
@@ -87,8 +89,8 @@ void or_amg_free(or_amg *h);
 #define OR_SM_RAS 2     /* zero-overlap RAS, DILU in each subdomain of sub cells */
 typedef struct or_cpr or_cpr;
 or_cpr *or_cpr_setup(int n, const int *rp, const int *ci, const double *v,
-                     int method, int smoother, int64_t sub, const or_amg_opts *ao,
-                     int *status);
+                     int method, int smoother, int64_t sub, int stages,
+                     const or_amg_opts *ao, int *status);
 void or_cpr_apply(const or_cpr *M, const double *r, double *z);
 const double *or_cpr_decoupled(const or_cpr *M);
 const double *or_cpr_dinv(const or_cpr *M);

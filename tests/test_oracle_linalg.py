@@ -47,7 +47,7 @@ def test_transpose_dense(prob):
     assert np.array_equal(oracle.transpose(A).dense(), A.dense().T)
 
 
-@pytest.mark.parametrize("method", [oracle.ABF, oracle.QIMPES])
+@pytest.mark.parametrize("method", [oracle.ABF, oracle.QIMPES, oracle.FRS, oracle.FRS_ABF])
 def test_decouple_dense_and_solution_invariant(prob, method):
     p, A = prob
     At, dinv = oracle.decouple(A, method)
@@ -60,6 +60,35 @@ def test_decouple_dense_and_solution_invariant(prob, method):
         # D_abf = diag(A_11..A_nn): D^{-1} is the inverse of each diagonal block, A~_ii = I
         assert np.allclose(dinv, np.linalg.inv(_diag_blocks(A)), rtol=1e-10, atol=1e-12)
         assert np.array_equal(_diag_blocks(At), np.broadcast_to(np.eye(4), (A.n, 4, 4)))
+
+
+def test_frs_is_row_sum(prob):
+    """FRS (Eq. decoupled-frs): D^{-1} = F, ones in row 0 and on the diagonal;
+    row 0 of every block becomes the column sums, rows 1-3 are unchanged."""
+    _, A = prob
+    At, d = oracle.decouple(A, oracle.FRS)
+    F = np.eye(4); F[0, :] = 1.0
+    assert np.array_equal(d, np.broadcast_to(F, (A.n, 4, 4)))
+    assert np.allclose(At.v[:, 0, :], A.v.sum(axis=1), rtol=1e-15, atol=1e-15 * np.abs(A.v).max())
+    assert np.array_equal(At.v[:, 1:, :], A.v[:, 1:, :])
+    # the pressure matrix of FRS holds the column-0 sums of each block
+    assert np.allclose(oracle.extract_pressure(At), A.v[:, :, 0].sum(axis=1), rtol=1e-15,
+                       atol=1e-15 * np.abs(A.v).max())
+
+
+def test_frs_then_abf_equals_abf(prob):
+    """Two-stage FRS+ABF: (F A_ii)^{-1} F A_ij = A_ii^{-1} A_ij in exact
+    arithmetic, so it matches ABF to rounding, with A~_ii = I."""
+    _, A = prob
+    Aa, da = oracle.decouple(A, oracle.ABF)
+    Af, df = oracle.decouple(A, oracle.FRS_ABF)
+    scale = np.abs(Aa.v).max()
+    assert np.allclose(Af.v, Aa.v, rtol=1e-11, atol=1e-12 * scale)
+    assert np.allclose(df, da, rtol=1e-11, atol=1e-12 * np.abs(da).max())
+    assert np.array_equal(_diag_blocks(Af), np.broadcast_to(np.eye(4), (A.n, 4, 4)))
+    F = np.eye(4); F[0, :] = 1.0
+    assert np.allclose(df, np.linalg.inv(_diag_blocks(A) * 0 + F @ _diag_blocks(A)) @ F, rtol=1e-10,
+                       atol=1e-12 * np.abs(df).max())
 
 
 def test_quasi_impes_row_equals_abf_row(prob):

@@ -17,14 +17,19 @@ def _blockdiag(blocks):
     return D
 
 
+@pytest.mark.parametrize("stages", [2, 3])
 @pytest.mark.parametrize("smoother", [oracle.SM_BJ, oracle.SM_DILU, oracle.SM_RAS])
-@pytest.mark.parametrize("method", [oracle.ABF, oracle.QIMPES])
-def test_cpr_dense_composition(method, smoother):
-    """With a single-level (exact) pressure solve:
-       M^{-1} = [C + M2^{-1}(I - A~ C)] D^{-1},  C = Pi_p A_p^{-1} Pi_r."""
+@pytest.mark.parametrize("method", [oracle.ABF, oracle.QIMPES, oracle.FRS])
+def test_cpr_dense_composition(method, smoother, stages):
+    """With a single-level (exact) pressure solve, S = M2^{-1} and
+    C = Pi_p A_p^{-1} Pi_r:
+       two-stage    M^{-1} = [C + S(I - A~ C)] D^{-1}
+       three-stage  M^{-1} = [S + (C + S(I - A~ C))(I - A~ S)] D^{-1}
+    and for the three-stage form its error propagation
+       I - A~ M^{-1} D = (I - A~ S)(I - A~ C)(I - A~ S)."""
     p = synth.small(4, 3, 2, seed=29)
     A = oracle.assemble(p)
-    M = oracle.CPR(A, method=method, smoother=smoother)
+    M = oracle.CPR(A, method=method, smoother=smoother, stages=stages)
     assert M.amg().nlevels == 1
     n = A.n; N = 4 * n
     At = M.decoupled()
@@ -48,9 +53,17 @@ def test_cpr_dense_composition(method, smoother):
                 if j > i: upper[4*i:4*i+4, 4*j:4*j+4] = Dt[4*i:4*i+4, 4*j:4*j+4]
         Dblk = _blockdiag(np.linalg.inv(d2))
         M2inv = np.linalg.inv((Dblk + lower) @ _blockdiag(d2) @ (Dblk + upper))
-    ref = (Cm + M2inv @ (np.eye(N) - Dt @ Cm)) @ Dinv
+    I = np.eye(N)
+    if stages == 2:
+        ref = (Cm + M2inv @ (I - Dt @ Cm)) @ Dinv
+    else:
+        ref = (M2inv + (Cm + M2inv @ (I - Dt @ Cm)) @ (I - Dt @ M2inv)) @ Dinv
     got = np.stack([M.apply(e) for e in np.eye(N)], 1)
     assert np.allclose(got, ref, rtol=1e-8, atol=1e-9 * np.abs(ref).max())
+    if stages == 3:
+        E = I - Dt @ got @ np.linalg.inv(Dinv)
+        Ef = (I - Dt @ M2inv) @ (I - Dt @ Cm) @ (I - Dt @ M2inv)
+        assert np.allclose(E, Ef, rtol=1e-7, atol=1e-8 * max(1.0, np.abs(Ef).max()))
 
 
 def test_gmres_exact_in_n_steps():
@@ -68,9 +81,10 @@ def test_cpr_gmres_vs_dense_lu(dims, sigma):
                    wells=synth.wells_vertical_pair(*dims, (0, 0), (dims[0] - 1, dims[1] - 1)))
     A = oracle.assemble(p)
     xref = np.linalg.solve(A.dense(), p.b)
-    for method, smoother in ((oracle.ABF, oracle.SM_DILU), (oracle.QIMPES, oracle.SM_DILU),
-                             (oracle.ABF, oracle.SM_RAS)):
-        M = oracle.CPR(A, method=method, smoother=smoother, coarse_n=20)
+    for method, smoother, stages in ((oracle.ABF, oracle.SM_DILU, 2), (oracle.QIMPES, oracle.SM_DILU, 2),
+                                     (oracle.ABF, oracle.SM_RAS, 2), (oracle.FRS, oracle.SM_RAS, 3),
+                                     (oracle.FRS_ABF, oracle.SM_BJ, 3)):
+        M = oracle.CPR(A, method=method, smoother=smoother, stages=stages, coarse_n=20)
         x, info = oracle.gmres(A, p.b, M, rtol=1e-12, maxit=200)
         assert info["status"] == 0 and info["relres"] <= 1e-12
         r = p.b - A.dense() @ x

@@ -24,6 +24,7 @@ HBM_PEAK_GBS = 8000.0
 # second stage: zero-overlap RAS over xy-layers with DILU inside (default),
 # DILU of the whole matrix, or block Jacobi
 SMOOTHERS = {"bj": 0, "dilu": 1, "ras": 2}
+DECOUPLINGS = {"abf": 0, "qi": 1, "frs": 2, "frs_abf": 3}
 SMOOTHER_NAMES = {"bj": "block Jacobi", "dilu": "DILU", "ras": "RAS(0, xy-layers) + DILU"}
 
 
@@ -87,16 +88,16 @@ def calibration_copy():
     del src, dst
 
 
-def run_variant(rs, dp, A, prec, steps, warmup, tag, smoother, solver="gmres"):
+def run_variant(rs, dp, A, prec, steps, warmup, tag, smoother, solver="gmres", method=0, stages=2):
     import torch
     times, infos, phases = [], [], []
     for it in range(warmup + steps):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         rs.bsr_update(A, dp.vals)
-        D = rs.decouple(A, rs.ABF, prec)
+        D = rs.decouple(A, method, prec)
         t1 = time.perf_counter()
-        M = rs.cpr_setup(A, D, rs.cpr_opts(smoother=smoother))
+        M = rs.cpr_setup(A, D, rs.cpr_opts(smoother=smoother, stages=stages))
         t2 = time.perf_counter()
         x = torch.zeros_like(dp.b)
         if solver == "gmres":
@@ -138,6 +139,9 @@ def main():
                     help="comma list of outer solvers, each run with the FP32 preconditioner; the first is the "
                          "headline (the FP64 variant runs with GMRES when gmres is listed)")
     ap.add_argument("--smoother", choices=list(SMOOTHERS), default="ras")
+    ap.add_argument("--decouple", choices=list(DECOUPLINGS), default="abf")
+    ap.add_argument("--stages", type=int, choices=[2, 3], default=2,
+                    help="CPR stages: 2 = pressure then full, 3 = CPR-FPF")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 1 GiB copy kernel (for counter calibration under rocprofv3 --pmc)")
     args = ap.parse_args()
@@ -174,7 +178,7 @@ def main():
             variants.append(("fp64", 64, "gmres"))
     for tag, prec, solver in variants:
         times, infos, phases = run_variant(rs, dp, A, prec, args.steps, args.warmup, tag, SMOOTHERS[args.smoother],
-                                           solver)
+                                           solver, DECOUPLINGS[args.decouple], args.stages)
         tmax = max(times)
         tmed = float(np.median(times))
         ph = np.median(np.array(phases), axis=0)
@@ -200,9 +204,11 @@ def main():
         "dtype": "fp32-preconditioner/fp64-gmres",
         "data": "synthetic",
         "config": {"workload": f"{prob.name}: 4x4-block 7-point Jacobian, {n} cells, {4 * n} unknowns, "
-                               f"nnzb {A.nnzb}; ABF + CPR(AMG V-cycle, {SMOOTHER_NAMES[args.smoother]}) + FGMRES(30), rtol 1e-8",
+                               f"nnzb {A.nnzb}; {args.decouple.upper()} + {'CPR-FPF' if args.stages == 3 else 'CPR'}(AMG V-cycle, "
+                               f"{SMOOTHER_NAMES[args.smoother]}) + {'FGMRES(30)' if solvers[0] == 'gmres' else 'BiCGSTAB'}, rtol 1e-8",
                    "cells": n, "unknowns": 4 * n, "nnzb": A.nnzb, "restart": 30, "rtol": 1e-8,
-                   "smoother": args.smoother, "headline_solver": solvers[0]},
+                   "smoother": args.smoother, "headline_solver": solvers[0], "decouple": args.decouple,
+                   "cpr_stages": args.stages},
         "fp32_precond": res.get("fp32"),
         "fp64": res.get("fp64"),
         "bicgstab_fp32_precond": res.get("bicgstab_fp32"),

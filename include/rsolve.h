@@ -58,6 +58,10 @@ typedef enum {
 
 #define RS_ABF 0        /* alternate block factorisation, Eq. decoupled-abf */
 #define RS_QIMPES 1     /* quasi-IMPES: pressure row of A_ii^{-1} only      */
+#define RS_FRS 2        /* full row sum, Eq. decoupled-frs: row 0 of each block
+                           becomes the sum of its four rows                 */
+#define RS_FRS_ABF 3    /* two-stage FRS then ABF (same section); equals ABF
+                           in exact arithmetic                               */
 #define RS_SM_BJ 0      /* second stage: block Jacobi over cells (RAS, overlap 0, one cell each) */
 #define RS_SM_DILU 1    /* second stage: block ILU(0) of the whole matrix, natural order        */
 #define RS_SM_RAS 2     /* second stage: RAS, overlap 0, one xy-layer per subdomain, block
@@ -72,6 +76,8 @@ typedef struct {
   int max_levels;      /* AMG depth limit (default 20)                           */
   int lu_max;          /* largest coarsest level inverted densely (default 2048) */
   int coarse_sweeps;   /* l1-Jacobi sweeps if the coarsest is larger (default 4) */
+  int stages;          /* 2: pressure then full (default); 3: CPR-FPF, full,
+                          pressure, full (Algorithm pc-fpf)                       */
 } rs_cpr_opts;
 
 typedef struct {
@@ -123,17 +129,22 @@ rs_status rs_bsr_update(rs_bsr A, const double *d_vals, void *stream);
 /* Decoupling (D^{-1} A) x = D^{-1} b, Eq. decoupled-eq, computed block row by
  * block row with Gauss-Jordan elimination and row pivoting (Section
  * "Decoupling Methods").  method: RS_ABF (D = diag(A_11..A_nn), Eq.
- * decoupled-abf) or RS_QIMPES (only the pressure row is replaced, by row 0
- * of A_ii^{-1} A_ij).  prec: 64 or 32, the storage and arithmetic precision
+ * decoupled-abf), RS_QIMPES (only the pressure row is replaced, by row 0
+ * of A_ii^{-1} A_ij), RS_FRS (Eq. decoupled-frs: D^{-1} = F, ones in row 0
+ * and on the diagonal, so row 0 becomes the sum of the four rows), or
+ * RS_FRS_ABF (FRS, then ABF on the result).  prec: 64 or 32, the storage and arithmetic precision
  * of the decoupled blocks used by the preconditioner; the pressure matrix
  * used by the AMG setup is always kept in FP64.  A singular diagonal block
  * (pivot <= 1e-300 or <= 1e-14 max|A_ii|) gives RS_E_SINGULAR. */
 rs_status rs_decouple(rs_bsr A, int method, int prec, void *stream, rs_dcpl *out);
 
-/* Two-stage CPR setup (Section "Preconditioners"): pressure sub-matrix
+/* CPR setup (Section "Preconditioners"): pressure sub-matrix
  * A_p[i][j] = A~_ij[0][0] ("getting sub-matrix (for CPR)", Section "Linear
  * Solver"), aggregation-AMG hierarchy on A_p built on the device, and the
  * second stage (block Jacobi or block ILU(0)) on the decoupled matrix.
+ * With o->stages == 3 the apply is CPR-FPF (Algorithm pc-fpf, read as its
+ * five described steps): y = M2^{-1} f, the pressure correction of the
+ * residual f - A~ y, then M2^{-1} of the new residual added to y.
  * o == NULL takes the defaults.  The handle keeps references to A and D:
  * destroy it before them. */
 rs_status rs_cpr_setup(rs_bsr A, rs_dcpl D, const rs_cpr_opts *o, void *stream,

@@ -75,6 +75,25 @@ __global__ __launch_bounds__(1024) void k_bcg_reduce(int nparts, int stride, con
   if (threadIdx.x == 0) out[k] = sh[0];
 }
 
+// First stage for long partial lists (one per SpMV workgroup): block
+// (c, k) sums part[k * stride + b] over its contiguous chunk of b in a fixed
+// order, into mid[k * gridDim.x + c].
+__global__ __launch_bounds__(256) void k_bcg_reduce_chunks(int nparts, int stride, const double *__restrict__ part,
+                                                           double *__restrict__ mid) {
+  __shared__ double sh[256];
+  const int k = blockIdx.y, nc = gridDim.x, c = blockIdx.x;
+  const int chunk = (nparts + nc - 1) / nc, b0 = c * chunk, b1 = min(nparts, b0 + chunk);
+  double s = 0.0;
+  for (int b = b0 + threadIdx.x; b < b1; b += blockDim.x) s += part[(int64_t)k * stride + b];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) mid[k * nc + c] = sh[0];
+}
+
 // partial ||b||^2
 __global__ __launch_bounds__(256) void k_bcg_norm2(int64_t N, const double *__restrict__ b, double *__restrict__ part) {
   double acc = 0.0;
@@ -167,6 +186,19 @@ extern "C" void rs_bicgstab_opts_default(rs_bicgstab_opts *o) {
   o->maxit = 300;
 }
 
+// out[k] = sum over b < nparts of part[k * stride + b], k < K, deterministic:
+// one workgroup per dot for short lists, two stages (64 chunks) for the
+// SpMV's one-partial-per-workgroup lists.
+constexpr int RED_CHUNKS = 64;
+static void bcg_reduce(int K, int nparts, int stride, const double *part, double *mid, double *out, hipStream_t s) {
+  if (nparts <= 4096) {
+    k_bcg_reduce<<<K, 1024, 0, s>>>(nparts, stride, part, out);
+  } else {
+    k_bcg_reduce_chunks<<<dim3(RED_CHUNKS, K), 256, 0, s>>>(nparts, stride, part, mid);
+    k_bcg_reduce<<<K, 1024, 0, s>>>(RED_CHUNKS, RED_CHUNKS, mid, out);
+  }
+}
+
 static rs_status bcg_read(double *h, const double *d, int cnt, hipStream_t s) {
   RS_HIP(hipMemcpyAsync(h, d, sizeof(double) * cnt, hipMemcpyDeviceToHost, s));
   RS_HIP(hipStreamSynchronize(s));
@@ -181,13 +213,14 @@ static rs_status bicgstab_t(rs_bsr_s *A, rs_cpr_s *M, const double *b, double *x
   const int zp = sizeof(TZ) == 8 ? 64 : 32;
   if (M->bprec != zp || !M->bvec.p) {
     RS_TRY(M->bvec.alloc(sizeof(double) * N * 5 + sizeof(TZ) * N * 2));
-    RS_TRY(M->bpart.alloc(sizeof(double) * 2 * ((size_t)nsp > NBLK ? nsp : NBLK)));
+    RS_TRY(M->bpart.alloc(sizeof(double) * (2 * ((size_t)nsp > NBLK ? nsp : NBLK) + 2 * RED_CHUNKS)));
     RS_TRY(M->bscal.alloc(sizeof(double) * (B_TOTAL + 4)));
     M->bprec = zp;
   }
   double *r = M->bvec.as<double>(), *rh = r + N, *p = rh + N, *v = p + N, *tv = v + N;
   TZ *ph = (TZ *)(tv + N), *shv = ph + N;
   double *part = M->bpart.as<double>(), *S = M->bscal.as<double>(), *D = S + B_TOTAL;
+  double *mid = part + 2 * ((size_t)nsp > NBLK ? nsp : NBLK);
   if (!M->bpin) RS_HIP(hipHostMalloc((void **)&M->bpin, sizeof(double) * B_TOTAL, hipHostMallocDefault));
   double *hp = M->bpin;
   hipEvent_t e0, e1;
@@ -204,13 +237,13 @@ static rs_status bicgstab_t(rs_bsr_s *A, rs_cpr_s *M, const double *b, double *x
   // r = b - A x and ||r||^2 into S[B_RN]
   auto residual = [&]() -> rs_status {
     RS_TRY(rs_spmv_dots(A, x, 64, r, b, 1, nullptr, part, s));
-    k_bcg_reduce<<<1, 1024, 0, s>>>(nsp, nsp, part, S + B_RN);
+    bcg_reduce(1, nsp, nsp, part, mid, S + B_RN, s);
     RS_HIP(hipGetLastError());
     return read_scalars();
   };
   do {
     k_bcg_norm2<<<NBLK, 256, 0, s>>>(N, b, part);
-    k_bcg_reduce<<<1, 1024, 0, s>>>(NBLK, NBLK, part, D);
+    bcg_reduce(1, NBLK, NBLK, part, mid, D, s);
     if ((st = bcg_read(h, D, 1, s)) != RS_OK) break;
     const double bnorm = sqrt(h[0]);
     if (!isfinite(bnorm)) { st = RS_E_NONFINITE; break; }
@@ -236,9 +269,9 @@ static rs_status bicgstab_t(rs_bsr_s *A, rs_cpr_s *M, const double *b, double *x
         k_bcg_p<<<NBLK, 256, 0, s>>>(N, r, v, p, S);
         if ((st = rs_cpr_apply_any(M, p, ph, zp, s)) != RS_OK) break;
         if ((st = rs_spmv_dots(A, ph, zp, v, nullptr, 1, rh, part, s)) != RS_OK) break;
-        k_bcg_reduce<<<1, 1024, 0, s>>>(nsp, nsp, part, S + B_RV);
+        bcg_reduce(1, nsp, nsp, part, mid, S + B_RV, s);
         k_bcg_s<<<NBLK, 256, 0, s>>>(N, r, v, S, part);
-        k_bcg_reduce<<<1, 1024, 0, s>>>(NBLK, NBLK, part, S + B_SN);
+        bcg_reduce(1, NBLK, NBLK, part, mid, S + B_SN, s);
         if ((st = read_scalars()) != RS_OK) break;
         if (h[B_RV] == 0.0) { stop_early = first; break; }   // r now holds garbage; x is untouched
         ++iters;
@@ -251,9 +284,9 @@ static rs_status bicgstab_t(rs_bsr_s *A, rs_cpr_s *M, const double *b, double *x
         }
         if ((st = rs_cpr_apply_any(M, r, shv, zp, s)) != RS_OK) break;
         if ((st = rs_spmv_dots(A, shv, zp, tv, nullptr, 2, r, part, s)) != RS_OK) break;
-        k_bcg_reduce<<<2, 1024, 0, s>>>(nsp, nsp, part, S + B_TS);
+        bcg_reduce(2, nsp, nsp, part, mid, S + B_TS, s);
         k_bcg_xr<TZ><<<NBLK, 256, 0, s>>>(N, ph, shv, tv, rh, r, x, S, part);
-        k_bcg_reduce<<<2, 1024, 0, s>>>(NBLK, NBLK, part, D);
+        bcg_reduce(2, NBLK, NBLK, part, mid, D, s);
         k_bcg_next<<<1, 64, 0, s>>>(S, D);
         if (hipGetLastError() != hipSuccess) { st = RS_E_HIP; break; }
         if ((st = read_scalars()) != RS_OK) break;

@@ -1,5 +1,6 @@
-// cpr.hip -- two-stage CPR preconditioner (pressure stage, then full-system
-// stage) and its second stage: block Jacobi or block ILU(0).
+// cpr.hip -- CPR preconditioner: two-stage (pressure stage, then
+// full-system stage) or three-stage CPR-FPF, and the full-system stage:
+// block Jacobi or block ILU(0).
 //
 // Apply, for a residual r (FP64):
 //   r~  = D^{-1} r                       decoupling (Eq. decoupled-eq)
@@ -7,9 +8,15 @@
 //   r~2 = r~ - A~[:,0] x_p               residual update (column 0 of A~)
 //   z   = M2^{-1} r~2 + Pi_p x_p          second stage, then prolong x_p
 // The paper's CPR-FPF (Section "Preconditioners", Algorithm pc-fpf) wraps
-// the pressure stage between two Schwarz/ILU stages; this is the two-stage
-// pressure-then-full form.  In prec 32 every vector and stored operator of
-// the preconditioner is FP32 except the coarsest AMG solve (FP64).
+// the pressure stage between two full-system stages; its five steps, with
+// f = r~:
+//   y   = M2^{-1} f                       (the second stage with x_p = 0)
+//   r~1 = f - A~ y                        k_fpf_resid, also b_p = r~1[:,0]
+//   x_p = Vcycle(A_p, b_p)
+//   z   = y + M2^{-1}(r~1 - A~[:,0] x_p) + Pi_p x_p
+// where r~1 - A~[:,0] x_p is the residual of y + Pi_p x_p (step 4).
+// In prec 32 every vector and stored operator of the preconditioner is FP32
+// except the coarsest AMG solve (FP64).
 //
 // Block ILU(0) on the 7-point block pattern only modifies the diagonal
 // blocks (no fill position lies on the pattern): D_i = A~_ii - sum over the
@@ -134,6 +141,40 @@ __global__ __launch_bounds__(256) void k_bj_apply(int64_t n, int64_t nx, int64_t
   if (ok) z[t] = o;
 }
 
+// CPR-FPF step 2: r~1 = r~ - A~ y in place of r~, and b_p = r~1[:,0].  Four
+// lanes per cell, lane `row` owns block row `row` of the 7 decoupled blocks.
+template <class T>
+__global__ __launch_bounds__(256) void k_fpf_resid(int64_t n, int64_t nx, int64_t nxy, const T *__restrict__ t7,
+                                                    const T *__restrict__ y, T *__restrict__ rt, T *__restrict__ bp) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 4 * n) return;
+  const int64_t c = t >> 2;
+  const int row = (int)(t & 3);
+  T v = rt[t];
+#pragma unroll
+  for (int s = 0; s < 7; ++s) {
+    int64_t q = nbr_of(c, s, nx, nxy);
+    q = (q < 0 || q >= n) ? c : q;           // off-grid blocks are zero
+    const T *a = t7 + ((int64_t)s * n + c) * 16 + 4 * row;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) v = v - a[m] * y[4 * q + m];
+  }
+  rt[t] = v;
+  if (row == 0) bp[c] = v;
+}
+
+template <class T>
+__global__ void k_fpf_add(int64_t m, const T *__restrict__ y, T *__restrict__ z) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < m) z[t] = z[t] + y[t];
+}
+
+template <class T>
+__global__ void k_fill0(int64_t m, T *__restrict__ a) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < m) a[t] = (T)0;
+}
+
 template <class T>
 __global__ void k_vec_to_f64(int64_t m, const T *__restrict__ a, double *__restrict__ b) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -154,6 +195,7 @@ extern "C" void rs_cpr_opts_default(rs_cpr_opts *o) {
   o->max_levels = 20;
   o->lu_max = 2048;
   o->coarse_sweeps = 4;
+  o->stages = 2;
 }
 
 rs_cpr_s::~rs_cpr_s() {
@@ -171,7 +213,8 @@ extern "C" rs_status rs_cpr_setup(rs_bsr A, rs_dcpl D, const rs_cpr_opts *o, voi
   if (o) opts = *o; else rs_cpr_opts_default(&opts);
   if ((opts.smoother != RS_SM_BJ && opts.smoother != RS_SM_DILU && opts.smoother != RS_SM_RAS) ||
       (opts.smoother == RS_SM_RAS && rs_ras_check_shape(A->g, D->prec) != RS_OK) || opts.coarse_n < 1 ||
-      opts.max_levels < 1 || opts.lu_max < 1 || opts.lu_max > 8192 || opts.coarse_sweeps < 1)
+      opts.max_levels < 1 || opts.lu_max < 1 || opts.lu_max > 8192 || opts.coarse_sweeps < 1 ||
+      (opts.stages != 2 && opts.stages != 3))
     return RS_E_ARG;
   hipStream_t s = rs_stream(stream);
   rs_cpr_s *M = new rs_cpr_s();
@@ -186,6 +229,13 @@ extern "C" rs_status rs_cpr_setup(rs_bsr A, rs_dcpl D, const rs_cpr_opts *o, voi
     if ((st = M->rt.alloc(es * 4 * n)) != RS_OK) break;
     if ((st = M->yv.alloc(es * 4 * n)) != RS_OK) break;
     if ((st = M->zt.alloc(es * 4 * n)) != RS_OK) break;
+    if (opts.stages == 3) {
+      const int64_t nz0 = n + 2 * A->g.nxy;     // x_p = 0 with the guards the second stage reads
+      if ((st = M->fy.alloc(es * 4 * n)) != RS_OK) break;
+      if ((st = M->fzero.alloc(es * nz0)) != RS_OK) break;
+      if (M->prec == 64) k_fill0<double><<<rs_grid(nz0), RS_BLOCK, 0, s>>>(nz0, M->fzero.as<double>());
+      else k_fill0<float><<<rs_grid(nz0), RS_BLOCK, 0, s>>>(nz0, M->fzero.as<float>());
+    }
     dbuf flag;
     if ((st = flag.alloc(sizeof(int))) != RS_OK) break;
     if (hipMemsetAsync(flag.p, 0, sizeof(int), s) != hipSuccess) { st = RS_E_HIP; break; }
@@ -212,16 +262,11 @@ extern "C" rs_status rs_cpr_setup(rs_bsr A, rs_dcpl D, const rs_cpr_opts *o, voi
   return RS_OK;
 }
 
+// z = M2^{-1}(r~ - A~[:,0] x_p) + Pi_p x_p with r~ in M->rt (not modified)
 template <class T>
-static rs_status cpr_apply_t(rs_cpr_s *M, const double *r, T *z, hipStream_t s) {
-  const rs_bsr_s *A = M->A;
-  const grid3 &g = A->g;
-  int64_t n = g.n;
-  amg_level *L0 = M->lev[0];
-  k_cpr_in<T><<<rs_grid(4 * n), RS_BLOCK, 0, s>>>(n, M->D->dinv.as<T>(), r, M->rt.as<T>(), L0->b.as<T>());
-  RS_HIP(hipGetLastError());
-  RS_TRY(rs_vcycle_run(M, s));
-  const T *xp = L0->xp<T>();
+static rs_status second_stage(rs_cpr_s *M, const T *xp, T *z, hipStream_t s) {
+  const grid3 &g = M->A->g;
+  const int64_t n = g.n;
   if (M->o.smoother == RS_SM_BJ) {
     k_bj_apply<T><<<rs_grid(4 * n), RS_BLOCK, 0, s>>>(n, g.nx, g.nxy, M->rt.as<T>(), M->D->col0.as<T>(), xp,
                                                      M->dinv2.as<T>(), z);
@@ -231,6 +276,30 @@ static rs_status cpr_apply_t(rs_cpr_s *M, const double *r, T *z, hipStream_t s) 
     RS_TRY(rs_dilu_apply_run<T>(M, xp, z, s));
   }
   RS_HIP(hipGetLastError());
+  return RS_OK;
+}
+
+template <class T>
+static rs_status cpr_apply_t(rs_cpr_s *M, const double *r, T *z, hipStream_t s) {
+  const rs_bsr_s *A = M->A;
+  const grid3 &g = A->g;
+  int64_t n = g.n;
+  amg_level *L0 = M->lev[0];
+  k_cpr_in<T><<<rs_grid(4 * n), RS_BLOCK, 0, s>>>(n, M->D->dinv.as<T>(), r, M->rt.as<T>(), L0->b.as<T>());
+  RS_HIP(hipGetLastError());
+  if (M->o.stages == 3) {
+    T *y = M->fy.as<T>();
+    RS_TRY(second_stage<T>(M, M->fzero.as<T>() + g.nxy, y, s));
+    k_fpf_resid<T><<<rs_grid(4 * n), RS_BLOCK, 0, s>>>(n, g.nx, g.nxy, M->D->t7.as<T>(), y, M->rt.as<T>(),
+                                                      L0->b.as<T>());
+    RS_HIP(hipGetLastError());
+  }
+  RS_TRY(rs_vcycle_run(M, s));
+  RS_TRY(second_stage<T>(M, L0->xp<T>(), z, s));
+  if (M->o.stages == 3) {
+    k_fpf_add<T><<<rs_grid(4 * n), RS_BLOCK, 0, s>>>(4 * n, M->fy.as<T>(), z);
+    RS_HIP(hipGetLastError());
+  }
   return RS_OK;
 }
 

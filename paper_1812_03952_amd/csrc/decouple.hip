@@ -1,4 +1,5 @@
-// decouple.hip -- ABF / quasi-IMPES decoupling and pressure-matrix extraction.
+// decouple.hip -- ABF / quasi-IMPES / FRS / FRS+ABF decoupling and
+// pressure-matrix extraction.
 //
 // Decoupling is a left scaling (D^{-1} A) x = D^{-1} b (Eq. decoupled-eq)
 // applied block row by block row with Gauss-Jordan elimination and row
@@ -57,7 +58,10 @@ __device__ __forceinline__ void store_col0(T *__restrict__ col0, int64_t n, int6
   }
 }
 
-template <class T>
+// ABF, and the two-stage FRS+ABF when FRS is set: row 0 of A_ii and of every
+// block the lane carries (the identity too, which becomes F) is first
+// replaced by the sum of the four rows, in row order.
+template <class T, bool FRS>
 __global__ __launch_bounds__(256) void k_decouple_abf(int64_t n, const double *__restrict__ a7,
                                                        T *__restrict__ t7, T *__restrict__ dinv,
                                                        double *__restrict__ ap7, T *__restrict__ col0,
@@ -75,6 +79,13 @@ __global__ __launch_bounds__(256) void k_decouple_abf(int64_t n, const double *_
     for (int r = 0; r < 4; ++r)
 #pragma unroll
       for (int q = 0; q < 4; ++q) R[r][q] = (r == q) ? 1.0 : 0.0;
+  }
+  if (FRS) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      L[0][q] = ((L[0][q] + L[1][q]) + L[2][q]) + L[3][q];
+      R[0][q] = ((R[0][q] + R[1][q]) + R[2][q]) + R[3][q];
+    }
   }
   int f = gje4<4>(L, R);
   if (valid && lane == 0 && f) atomicOr(flag, f);
@@ -158,10 +169,46 @@ __global__ __launch_bounds__(256) void k_decouple_qi(int64_t n, const double *__
   store_col0<T>(col0, n, ((int64_t)blockIdx.x * blockDim.x) >> 3, valid, lane, R);
 }
 
+// FRS (Eq. decoupled-frs): D_i^{-1} = F (ones in row 0 and on the
+// diagonal): row 0 of every block becomes the sum of its four rows, in row
+// order; rows 1-3 stay.
+template <class T>
+__global__ __launch_bounds__(256) void k_decouple_frs(int64_t n, const double *__restrict__ a7,
+                                                       T *__restrict__ t7, T *__restrict__ dinv,
+                                                       double *__restrict__ ap7, T *__restrict__ col0) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = t < 8 * n;                 // all threads stay for the block-wide col0 store
+  const int64_t c = valid ? t >> 3 : n - 1;
+  const int lane = (int)(t & 7);
+  double R[4][4];
+  if (lane < 7) {
+    load16(a7 + ((int64_t)lane * n + c) * 16, R);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) R[0][q] = ((R[0][q] + R[1][q]) + R[2][q]) + R[3][q];
+  } else {
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) R[r][q] = (r == 0 || r == q) ? 1.0 : 0.0;
+  }
+  if (valid) {
+    if (lane == 7) {
+      T *o = dinv + c * 16;
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) o[4 * r + q] = (T)R[r][q];
+    } else {
+      store_block<T>(t7, ap7, lane, n, c, R);
+    }
+  }
+  store_col0<T>(col0, n, ((int64_t)blockIdx.x * blockDim.x) >> 3, valid, lane, R);
+}
+
 }  // namespace
 
 extern "C" rs_status rs_decouple(rs_bsr A, int method, int prec, void *stream, rs_dcpl *out) {
-  if (!A || !out || (method != RS_ABF && method != RS_QIMPES) || (prec != 32 && prec != 64))
+  if (!A || !out || method < RS_ABF || method > RS_FRS_ABF || (prec != 32 && prec != 64))
     return RS_E_ARG;
   *out = nullptr;
   hipStream_t s = rs_stream(stream);
@@ -180,21 +227,24 @@ extern "C" rs_status rs_decouple(rs_bsr A, int method, int prec, void *stream, r
     if ((st = flag.alloc(sizeof(int))) != RS_OK) break;
     if (hipMemsetAsync(flag.p, 0, sizeof(int), s) != hipSuccess) { st = RS_E_HIP; break; }
     unsigned grid = rs_grid(8 * n);
+    const double *a7 = A->a7.as<double>();
+    double *ap7 = D->ap7.as<double>();
+    int *fl = flag.as<int>();
+#define RS_DC(KERN, T, ...) KERN<<<grid, RS_BLOCK, 0, s>>>(n, a7, D->t7.as<T>(), D->dinv.as<T>(), ap7, D->col0.as<T>(), ##__VA_ARGS__)
     if (method == RS_ABF) {
-      if (prec == 64)
-        k_decouple_abf<double><<<grid, RS_BLOCK, 0, s>>>(n, A->a7.as<double>(), D->t7.as<double>(), D->dinv.as<double>(),
-                                                         D->ap7.as<double>(), D->col0.as<double>(), flag.as<int>());
-      else
-        k_decouple_abf<float><<<grid, RS_BLOCK, 0, s>>>(n, A->a7.as<double>(), D->t7.as<float>(), D->dinv.as<float>(),
-                                                        D->ap7.as<double>(), D->col0.as<float>(), flag.as<int>());
+      if (prec == 64) RS_DC((k_decouple_abf<double, false>), double, fl);
+      else RS_DC((k_decouple_abf<float, false>), float, fl);
+    } else if (method == RS_FRS_ABF) {
+      if (prec == 64) RS_DC((k_decouple_abf<double, true>), double, fl);
+      else RS_DC((k_decouple_abf<float, true>), float, fl);
+    } else if (method == RS_QIMPES) {
+      if (prec == 64) RS_DC(k_decouple_qi<double>, double, fl);
+      else RS_DC(k_decouple_qi<float>, float, fl);
     } else {
-      if (prec == 64)
-        k_decouple_qi<double><<<grid, RS_BLOCK, 0, s>>>(n, A->a7.as<double>(), D->t7.as<double>(), D->dinv.as<double>(),
-                                                        D->ap7.as<double>(), D->col0.as<double>(), flag.as<int>());
-      else
-        k_decouple_qi<float><<<grid, RS_BLOCK, 0, s>>>(n, A->a7.as<double>(), D->t7.as<float>(), D->dinv.as<float>(),
-                                                       D->ap7.as<double>(), D->col0.as<float>(), flag.as<int>());
+      if (prec == 64) RS_DC(k_decouple_frs<double>, double);
+      else RS_DC(k_decouple_frs<float>, float);
     }
+#undef RS_DC
     if (hipGetLastError() != hipSuccess ||
         hipMemcpyAsync(&h, flag.p, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess) { st = RS_E_HIP; break; }

@@ -127,6 +127,7 @@ struct rs_cpr_s {
   uint32_t repoch = 0;
   // CPR work
   dbuf rt, bp, xp, yv, zt;   // prec vectors
+  dbuf fy, fzero;             // CPR-FPF: first-stage result, zero x_p with guards
   // GMRES work (allocated on first solve)
   int m = 0;
   dbuf V, Z, w, part, scal;

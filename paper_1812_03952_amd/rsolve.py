@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librsolve.so")
 
 RS_OK, RS_NOT_CONVERGED = 0, 1
-ABF, QIMPES = 0, 1
+ABF, QIMPES, FRS, FRS_ABF = 0, 1, 2, 3
 SM_BJ, SM_DILU, SM_RAS = 0, 1, 2
 
 
@@ -30,7 +30,7 @@ class RsError(RuntimeError):
 class CprOpts(C.Structure):
     _fields_ = [("smoother", C.c_int), ("theta", C.c_double), ("max_row_sum", C.c_double),
                 ("coarse_n", C.c_int), ("max_levels", C.c_int), ("lu_max", C.c_int),
-                ("coarse_sweeps", C.c_int)]
+                ("coarse_sweeps", C.c_int), ("stages", C.c_int)]
 
 
 class GmresOpts(C.Structure):

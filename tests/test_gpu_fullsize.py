@@ -102,3 +102,29 @@ def test_full_size_bicgstab_against_oracle(cfg):
             assert info["iters"] == io["iters"] and err <= 1e-9
         else:
             assert err <= 1e-5
+
+
+def test_full_size_fpf_frs_against_oracle():
+    """100x100x50 with FRS decoupling and CPR-FPF (RAS full-system stages),
+    GMRES, FP64 and FP32 preconditioner, against the oracle."""
+    p = synth.config(1)
+    dp = rs.DeviceProblem(p)
+    Ao = oracle.assemble(p).with_values(dp.vals.cpu().numpy().reshape(-1, 4, 4))
+    xo, io = oracle.gmres(Ao, p.b, oracle.CPR(Ao, method=oracle.FRS, smoother=oracle.SM_RAS, stages=3), rtol=1e-8)
+    assert io["status"] == 0
+    nb = np.linalg.norm(p.b)
+    A = dp.bsr()
+    for prec in (64, 32):
+        M = rs.cpr_setup(A, rs.decouple(A, rs.FRS, prec), rs.cpr_opts(smoother=rs.SM_RAS, stages=3))
+        x = torch.zeros_like(dp.b)
+        info = rs.gmres_solve(A, M, dp.b, x, rs.gmres_opts(rtol=1e-8))
+        xg = x.cpu().numpy()
+        true = np.linalg.norm(p.b - oracle.spmv(Ao, xg)) / nb
+        err = relerr(xg, xo)
+        print(f"FRS + CPR-FPF prec {prec}: iters {info['iters']} (oracle {io['iters']}), true relres {true:.2e}, "
+              f"|x - x_oracle|/|x_oracle| {err:.2e}")
+        assert info["return"] == 0 and true <= 1e-8
+        if prec == 64:
+            assert info["iters"] == io["iters"] and err <= 1e-9
+        else:
+            assert err <= 1e-5

@@ -52,7 +52,7 @@ def test_spmv(dims):
     assert np.abs(y.cpu().numpy() - ref).max() <= bound
 
 
-@pytest.mark.parametrize("method", [rs.ABF, rs.QIMPES])
+@pytest.mark.parametrize("method", [rs.ABF, rs.QIMPES, rs.FRS, rs.FRS_ABF])
 @pytest.mark.parametrize("dims", [(5, 3, 4), (20, 20, 10), (1, 1, 7)])
 def test_decouple_fp64_bitwise(method, dims):
     p = _prob(dims, sigma=1.5)
@@ -143,7 +143,7 @@ def test_vcycle(coarse_n, max_levels):
 
 
 @pytest.mark.parametrize("smoother", [rs.SM_BJ, rs.SM_DILU, rs.SM_RAS])
-@pytest.mark.parametrize("method", [rs.ABF, rs.QIMPES])
+@pytest.mark.parametrize("method", [rs.ABF, rs.QIMPES, rs.FRS])
 @pytest.mark.parametrize("dims", [(20, 20, 10), (7, 1, 5), (1, 1, 1)])
 def test_cpr_apply(method, smoother, dims):
     p = _prob(dims, sigma=1.5)
@@ -183,6 +183,55 @@ def test_ras_layer_limit():
         B = upload(A)
         with pytest.raises(rs.RsError):
             rs.cpr_setup(B, rs.decouple(B, rs.ABF, prec), rs.cpr_opts(smoother=rs.SM_RAS))
+
+
+@pytest.mark.parametrize("smoother", [rs.SM_BJ, rs.SM_DILU, rs.SM_RAS])
+@pytest.mark.parametrize("method", [rs.ABF, rs.FRS, rs.FRS_ABF])
+@pytest.mark.parametrize("dims", [(20, 20, 10), (7, 1, 5), (1, 1, 1)])
+def test_cpr_apply_fpf(method, smoother, dims):
+    """Three-stage CPR-FPF against the oracle's five steps (the device
+    updates the step-4 residual through column 0 of A~ instead of
+    recomputing it: equal in exact arithmetic)."""
+    p = _prob(dims, sigma=1.5)
+    A = oracle.assemble(p)
+    Mo = oracle.CPR(A, method=method, smoother=smoother, stages=3)
+    B = upload(A)
+    Mg = rs.cpr_setup(B, rs.decouple(B, method, 64), rs.cpr_opts(smoother=smoother, stages=3))
+    r = np.random.default_rng(7).standard_normal(4 * A.n)
+    z = torch.empty(4 * A.n, dtype=torch.float64, device="cuda")
+    rs.cpr_apply(Mg, dev(r), z)
+    assert relerr(z.cpu().numpy(), Mo.apply(r)) <= 1e-10
+    Mg32 = rs.cpr_setup(B, rs.decouple(B, method, 32), rs.cpr_opts(smoother=smoother, stages=3))
+    rs.cpr_apply(Mg32, dev(r), z)
+    assert relerr(z.cpu().numpy(), Mo.apply(r)) <= 1e-4
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+@pytest.mark.parametrize("method,smoother", [(rs.FRS, rs.SM_RAS), (rs.FRS_ABF, rs.SM_DILU), (rs.ABF, rs.SM_BJ)])
+def test_fpf_solves(method, smoother, prec):
+    """GMRES and BiCGSTAB with CPR-FPF on the 20x20x10 workload: true residual
+    1e-8, solution against the oracle's, iteration counts equal in FP64."""
+    p = synth.config(0)
+    A = oracle.assemble(p)
+    Mo = oracle.CPR(A, method=method, smoother=smoother, stages=3)
+    B = upload(A)
+    M = rs.cpr_setup(B, rs.decouple(B, method, prec), rs.cpr_opts(smoother=smoother, stages=3))
+    nb = np.linalg.norm(p.b)
+    for solver in ("gmres", "bicgstab"):
+        if solver == "gmres":
+            xo, io = oracle.gmres(A, p.b, Mo, rtol=1e-8)
+            x = torch.zeros(4 * A.n, dtype=torch.float64, device="cuda")
+            info = rs.gmres_solve(B, M, dev(p.b), x, rs.gmres_opts(rtol=1e-8))
+        else:
+            xo, io = oracle.bicgstab(A, p.b, Mo, rtol=1e-8)
+            x = torch.zeros(4 * A.n, dtype=torch.float64, device="cuda")
+            info = rs.bicgstab_solve(B, M, dev(p.b), x, rs.bicgstab_opts(rtol=1e-8))
+        xg = x.cpu().numpy()
+        true = np.linalg.norm(p.b - oracle.spmv(A, xg)) / nb
+        assert info["return"] == 0 and true <= 1e-8, solver
+        assert relerr(xg, xo) <= 1e-5, solver
+        if prec == 64:
+            assert info["iters"] == io["iters"], solver
 
 
 def test_cpr_apply_fp32_close_to_fp64():

@@ -26,6 +26,7 @@
 // sweep, so r~2 and the corrected z are never stored separately.
 #include "rs_internal.h"
 #include <math.h>
+#include <mutex>
 
 namespace {
 #pragma clang fp contract(off)
@@ -206,6 +207,25 @@ rs_cpr_s::~rs_cpr_s() {
 
 extern "C" void rs_cpr_destroy(rs_cpr M) { delete M; }
 
+// One non-blocking stream per device, at the default priority, for set-up
+// work that does not depend on the AMG set-up (block Jacobi, layer RAS).
+// nullptr if it cannot be created (the work then stays on the caller's stream).
+static hipStream_t side_stream() {
+  static std::mutex mu;
+  static hipStream_t ss[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+  std::lock_guard<std::mutex> lk(mu);
+  if (!ss[dev] && hipStreamCreateWithFlags(&ss[dev], hipStreamNonBlocking) != hipSuccess) ss[dev] = nullptr;
+  return ss[dev];
+}
+
+// The second-stage set-up (block Jacobi or layer RAS) reads only the
+// decoupled blocks, the AMG set-up only the pressure matrix: the former runs
+// on a side stream while the latter (many small launches and host reads)
+// runs on the caller's stream.  The global DILU set-up stays on the
+// caller's stream (its workgroups wait on each other).  Both streams are
+// idle again when this returns, on every path.
 extern "C" rs_status rs_cpr_setup(rs_bsr A, rs_dcpl D, const rs_cpr_opts *o, void *stream, rs_cpr *out) {
   if (!A || !D || !out || D->A != A) return RS_E_ARG;
   *out = nullptr;
@@ -217,14 +237,19 @@ extern "C" rs_status rs_cpr_setup(rs_bsr A, rs_dcpl D, const rs_cpr_opts *o, voi
       (opts.stages != 2 && opts.stages != 3))
     return RS_E_ARG;
   hipStream_t s = rs_stream(stream);
+  hipStream_t ss = opts.smoother == RS_SM_DILU ? nullptr : side_stream();
+  hipEvent_t ev = nullptr;
+  if (ss && hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) { ev = nullptr; ss = nullptr; }
+  if (!ss) ss = s;
+  const bool split = ss != s;
   rs_cpr_s *M = new rs_cpr_s();
   M->A = A; M->D = D; M->o = opts; M->prec = D->prec;
   int64_t n = A->g.n;
   size_t es = M->prec == 64 ? sizeof(double) : sizeof(float);
   rs_status st = RS_OK;
+  dbuf flag;
+  bool launched = false;
   do {
-    if ((st = rs_amg_level0(M, s)) != RS_OK) break;
-    if ((st = rs_amg_build(M, s)) != RS_OK) break;
     if ((st = M->dinv2.alloc(es * 16 * n)) != RS_OK) break;
     if ((st = M->rt.alloc(es * 4 * n)) != RS_OK) break;
     if ((st = M->yv.alloc(es * 4 * n)) != RS_OK) break;
@@ -236,33 +261,51 @@ extern "C" rs_status rs_cpr_setup(rs_bsr A, rs_dcpl D, const rs_cpr_opts *o, voi
       if (M->prec == 64) k_fill0<double><<<rs_grid(nz0), RS_BLOCK, 0, s>>>(nz0, M->fzero.as<double>());
       else k_fill0<float><<<rs_grid(nz0), RS_BLOCK, 0, s>>>(nz0, M->fzero.as<float>());
     }
-    dbuf flag;
     if ((st = flag.alloc(sizeof(int))) != RS_OK) break;
     if (hipMemsetAsync(flag.p, 0, sizeof(int), s) != hipSuccess) { st = RS_E_HIP; break; }
-    const grid3 &g = A->g;
+    if (split) {
+      if (hipEventRecord(ev, s) != hipSuccess || hipStreamWaitEvent(ss, ev, 0) != hipSuccess) { st = RS_E_HIP; break; }
+    }
+    launched = true;
     if (opts.smoother == RS_SM_BJ) {
-      if (M->prec == 64) k_bj_setup<double><<<rs_grid(n), RS_BLOCK, 0, s>>>(n, D->t7.as<double>(), M->dinv2.as<double>(), flag.as<int>());
-      else k_bj_setup<float><<<rs_grid(n), RS_BLOCK, 0, s>>>(n, D->t7.as<float>(), M->dinv2.as<float>(), flag.as<int>());
+      if (M->prec == 64) k_bj_setup<double><<<rs_grid(n), RS_BLOCK, 0, ss>>>(n, D->t7.as<double>(), M->dinv2.as<double>(), flag.as<int>());
+      else k_bj_setup<float><<<rs_grid(n), RS_BLOCK, 0, ss>>>(n, D->t7.as<float>(), M->dinv2.as<float>(), flag.as<int>());
+      if (hipGetLastError() != hipSuccess) { st = RS_E_HIP; break; }
     } else if (opts.smoother == RS_SM_RAS) {
-      if ((st = rs_ras_setup_run(M, flag.as<int>(), s)) != RS_OK) break;
-    } else {
+      if ((st = rs_ras_setup_run(M, flag.as<int>(), ss)) != RS_OK) break;
+    }
+    if ((st = rs_amg_level0(M, s)) != RS_OK) break;
+    if ((st = rs_amg_build(M, s)) != RS_OK) break;
+    if (opts.smoother == RS_SM_DILU) {
       if ((st = rs_dilu_prepare(M)) != RS_OK) break;
       if ((st = rs_dilu_setup_run(M, flag.as<int>(), s)) != RS_OK) break;
     }
+  } while (0);
+  if (split && launched) {
+    // join: the caller's stream waits for the side stream, and the side
+    // stream is drained before any buffer can go back to the pool
+    if (hipEventRecord(ev, ss) != hipSuccess || hipStreamWaitEvent(s, ev, 0) != hipSuccess ||
+        hipStreamSynchronize(ss) != hipSuccess) {
+      if (st == RS_OK) st = RS_E_HIP;
+    }
+  }
+  if (ev) (void)hipEventDestroy(ev);
+  if (st == RS_OK) {
     int h = 0;
     if (hipGetLastError() != hipSuccess ||
         hipMemcpyAsync(&h, flag.p, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess) { st = RS_E_HIP; break; }
-    if (h & RSF_NONFINITE) st = RS_E_NONFINITE;
+        hipStreamSynchronize(s) != hipSuccess) st = RS_E_HIP;
+    else if (h & RSF_NONFINITE) st = RS_E_NONFINITE;
     else if (h & RSF_SINGULAR) st = RS_E_SINGULAR;
     else st = rs_dilu_check(M, s);
-  } while (0);
+  } else {
+    (void)hipStreamSynchronize(s);
+  }
   if (st != RS_OK) { delete M; return st; }
   *out = M;
   return RS_OK;
 }
 
-// z = M2^{-1}(r~ - A~[:,0] x_p) + Pi_p x_p with r~ in M->rt (not modified)
 template <class T>
 static rs_status second_stage(rs_cpr_s *M, const T *xp, T *z, hipStream_t s) {
   const grid3 &g = M->A->g;

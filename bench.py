@@ -100,10 +100,11 @@ def run_variant(rs, dp, A, prec, steps, warmup, tag, smoother, solver="gmres", m
         M = rs.cpr_setup(A, D, rs.cpr_opts(smoother=smoother, stages=stages))
         t2 = time.perf_counter()
         x = torch.zeros_like(dp.b)
+        # x0 = 0: the solvers take r0 = b without a product with A
         if solver == "gmres":
-            info = rs.gmres_solve(A, M, dp.b, x)
+            info = rs.gmres_solve(A, M, dp.b, x, rs.gmres_opts(zero_guess=1))
         else:
-            info = rs.bicgstab_solve(A, M, dp.b, x)
+            info = rs.bicgstab_solve(A, M, dp.b, x, rs.bicgstab_opts(zero_guess=1))
         torch.cuda.synchronize()
         t3 = time.perf_counter()
         del M, D

@@ -84,12 +84,15 @@ typedef struct {
   int restart;         /* Krylov dimension per cycle (default 30, max 32)        */
   double rtol;         /* stop at ||b - A x|| <= rtol ||b|| (default 1e-8)       */
   int maxit;           /* Arnoldi steps in total (default 300)                   */
+  int zero_guess;      /* 1: start from x0 = 0 whatever d_x holds (r0 = b, no
+                          product with A); 0: d_x is the initial guess (default) */
 } rs_gmres_opts;
 
 typedef struct {
   double rtol;         /* stop at ||b - A x|| <= rtol ||b|| (default 1e-8)       */
   int maxit;           /* iterations in total (default 300); each applies A and
                           M twice (once if it stops half-way)                    */
+  int zero_guess;      /* as in rs_gmres_opts                                    */
 } rs_bicgstab_opts;
 
 typedef struct {

@@ -184,6 +184,7 @@ extern "C" void rs_bicgstab_opts_default(rs_bicgstab_opts *o) {
   if (!o) return;
   o->rtol = 1e-8;
   o->maxit = 300;
+  o->zero_guess = 0;
 }
 
 // out[k] = sum over b < nparts of part[k * stride + b], k < K, deterministic:
@@ -252,15 +253,31 @@ static rs_status bicgstab_t(rs_bsr_s *A, rs_cpr_s *M, const double *b, double *x
       relres = 0.0;
       break;
     }
+    bool zero_start = o.zero_guess != 0;
     for (;;) {
-      if ((st = residual()) != RS_OK) break;
+      if (zero_start) {
+        // x0 = 0: r = b and ||r||^2 = ||b||^2 (already reduced into D[0])
+        k_bcg_zero<<<gN, RS_BLOCK, 0, s>>>(N, x);
+        if (hipMemcpyAsync(r, b, sizeof(double) * N, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+            hipMemcpyAsync(S + B_RN, D, sizeof(double), hipMemcpyDeviceToDevice, s) != hipSuccess) {
+          st = RS_E_HIP;
+          break;
+        }
+        if ((st = read_scalars()) != RS_OK) break;
+        zero_start = false;
+      } else if ((st = residual()) != RS_OK) {
+        break;
+      }
       const double rn = sqrt(h[B_RN]);
       relres = rn / bnorm;
       if (!isfinite(rn)) { st = RS_E_NONFINITE; break; }
       if (rn <= o.rtol * bnorm) { st = RS_OK; break; }
       if (iters >= o.maxit) { st = RS_NOT_CONVERGED; break; }
       ++cycles;
-      RS_HIP(hipMemcpyAsync(rh, r, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+      if (hipMemcpyAsync(rh, r, sizeof(double) * N, hipMemcpyDeviceToDevice, s) != hipSuccess) {
+        st = RS_E_HIP;
+        break;
+      }
       k_bcg_start<<<gN, RS_BLOCK, 0, s>>>(N, p, v, S);
       double rho = h[B_RN];                  // (r^, r) with r^ = r
       bool first = true, stop_early = false;

@@ -174,6 +174,11 @@ __global__ void k_scale(int64_t N, const double *w, const double *__restrict__ S
   v[t] = w[t] / d;
 }
 
+__global__ void k_zero(int64_t N, double *__restrict__ x) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < N) x[t] = 0.0;
+}
+
 template <class TZ>
 __global__ void k_update_x(int64_t N, int k, const TZ *__restrict__ Z, const double *__restrict__ S,
                            double *__restrict__ x) {
@@ -192,6 +197,7 @@ extern "C" void rs_gmres_opts_default(rs_gmres_opts *o) {
   o->restart = 30;
   o->rtol = 1e-8;
   o->maxit = 300;
+  o->zero_guess = 0;
 }
 
 extern "C" const char *rs_status_string(int st) {
@@ -272,17 +278,26 @@ static rs_status gmres_t(rs_bsr_s *A, rs_cpr_s *M, const double *b, double *x, c
       relres = 0.0;
       break;
     }
+    bool zero_start = o.zero_guess != 0;
     for (;;) {
-      // r = b - A x into V_0
-      if ((st = rs_spmv_any(A, x, 64, V, b, s)) != RS_OK) break;
-      if ((st = run_dots(N, 0, V, V, part, S, S_NRM, s)) != RS_OK) break;
-      if ((st = read_host(hb.p, S + S_NRM, 1, s)) != RS_OK) break;
-      double beta = sqrt(hb.p[0]);
+      double beta;
+      if (zero_start) {
+        // x0 = 0: r0 = b, ||r0|| = ||b||, V_0 = b / ||b|| (the k_scale below)
+        k_zero<<<gN, RS_BLOCK, 0, s>>>(N, x);
+        beta = bnorm;
+      } else {
+        // r = b - A x into V_0
+        if ((st = rs_spmv_any(A, x, 64, V, b, s)) != RS_OK) break;
+        if ((st = run_dots(N, 0, V, V, part, S, S_NRM, s)) != RS_OK) break;
+        if ((st = read_host(hb.p, S + S_NRM, 1, s)) != RS_OK) break;
+        beta = sqrt(hb.p[0]);
+      }
       relres = beta / bnorm;
       if (!isfinite(beta)) { st = RS_E_NONFINITE; break; }
       if (beta <= o.rtol * bnorm) { st = RS_OK; break; }
       if (iters >= o.maxit) { st = RS_NOT_CONVERGED; break; }
-      k_scale<<<gN, RS_BLOCK, 0, s>>>(N, V, S, -1, beta, V);
+      k_scale<<<gN, RS_BLOCK, 0, s>>>(N, zero_start ? b : V, S, -1, beta, V);
+      zero_start = false;
       k_init_cycle<<<1, 128, 0, s>>>(S, beta);
       ++cycles;
       int k = 0;

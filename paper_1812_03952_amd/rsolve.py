@@ -34,11 +34,11 @@ class CprOpts(C.Structure):
 
 
 class GmresOpts(C.Structure):
-    _fields_ = [("restart", C.c_int), ("rtol", C.c_double), ("maxit", C.c_int)]
+    _fields_ = [("restart", C.c_int), ("rtol", C.c_double), ("maxit", C.c_int), ("zero_guess", C.c_int)]
 
 
 class BicgstabOpts(C.Structure):
-    _fields_ = [("rtol", C.c_double), ("maxit", C.c_int)]
+    _fields_ = [("rtol", C.c_double), ("maxit", C.c_int), ("zero_guess", C.c_int)]
 
 
 class SolveInfo(C.Structure):

@@ -266,6 +266,25 @@ def test_gmres_solution(cfg, prec, smoother):
         assert info["iters"] == io8["iters"]
 
 
+@pytest.mark.parametrize("solver", ["gmres", "bicgstab"])
+def test_zero_guess_ignores_x(solver):
+    """zero_guess = 1 starts from x0 = 0 without a product with A, whatever
+    d_x holds: bitwise the solve from a zero d_x with zero_guess = 0."""
+    p = synth.config(0)
+    A = oracle.assemble(p)
+    B = upload(A)
+    M = rs.cpr_setup(B, rs.decouple(B, rs.ABF, 32), rs.cpr_opts(smoother=rs.SM_RAS))
+    b = dev(p.b)
+    solve = rs.gmres_solve if solver == "gmres" else rs.bicgstab_solve
+    opts = rs.gmres_opts if solver == "gmres" else rs.bicgstab_opts
+    x0 = torch.zeros_like(b)
+    i0 = solve(B, M, b, x0, opts(zero_guess=0))
+    x1 = torch.full_like(b, float("nan"))
+    i1 = solve(B, M, b, x1, opts(zero_guess=1))
+    assert i0["return"] == 0 and i1["return"] == 0 and i0["iters"] == i1["iters"]
+    assert torch.equal(x0, x1) and i0["relres"] == i1["relres"]
+
+
 def test_gmres_deterministic_and_status():
     p = synth.config(0)
     A = oracle.assemble(p)

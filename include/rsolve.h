@@ -129,6 +129,14 @@ rs_status rs_bsr_create(int nx, int ny, int nz, int bs, int64_t nnzb,
  * updated (rebuild them). */
 rs_status rs_bsr_update(rs_bsr A, const double *d_vals, void *stream);
 
+/* rs_bsr_update followed by rs_decouple, in one pass over the values: the
+ * new values (caller layout, 16-byte aligned) are read once, stored into A
+ * and decoupled; the results equal those of the two calls.  For the Newton
+ * loop, where every step brings a new Jacobian to decouple.  Errors as for
+ * the two calls; after RS_E_SINGULAR A holds the new values. */
+rs_status rs_bsr_update_decouple(rs_bsr A, const double *d_vals, int method, int prec, void *stream,
+                                 rs_dcpl *out);
+
 /* Decoupling (D^{-1} A) x = D^{-1} b, Eq. decoupled-eq, computed block row by
  * block row with Gauss-Jordan elimination and row pivoting (Section
  * "Decoupling Methods").  method: RS_ABF (D = diag(A_11..A_nn), Eq.
@@ -156,8 +164,9 @@ rs_status rs_cpr_setup(rs_bsr A, rs_dcpl D, const rs_cpr_opts *o, void *stream,
 /* Solve A x = b with restarted flexible GMRES right-preconditioned by M
  * (Section "Linear Solver").  d_x holds the initial guess on entry and the
  * iterate on exit.  o == NULL takes the defaults.  info (host, may be NULL)
- * receives iterations, cycles and the true FP64 relative residual.  Returns
- * RS_OK when the true residual meets rtol, RS_NOT_CONVERGED at maxit. */
+ * receives iterations, cycles and the true FP64 relative residual.  d_b and
+ * d_x must be 16-byte aligned (RS_E_ARG otherwise).  Returns RS_OK when the
+ * true residual meets rtol, RS_NOT_CONVERGED at maxit. */
 rs_status rs_gmres_solve(rs_bsr A, rs_cpr M, const double *d_b, double *d_x,
                          const rs_gmres_opts *o, rs_solve_info *info, void *stream);
 
@@ -169,15 +178,17 @@ rs_status rs_gmres_solve(rs_bsr A, rs_cpr M, const double *d_b, double *d_x,
  * r^ = r) if that misses rtol.  A breakdown ((r^, r), (r^, v) or (t, t)
  * zero) restarts likewise, and ends the solve when it comes in the first
  * iteration after a start.  d_x holds the initial guess on entry.  o == NULL
- * takes the defaults.  The work vectors (7 of 4n entries) live in M.  Returns
- * RS_OK when the true residual meets rtol, RS_NOT_CONVERGED otherwise. */
+ * takes the defaults.  The work vectors (7 of 4n entries) live in M.  d_b and
+ * d_x must be 16-byte aligned (RS_E_ARG otherwise).  Returns RS_OK when the
+ * true residual meets rtol, RS_NOT_CONVERGED otherwise. */
 rs_status rs_bicgstab_solve(rs_bsr A, rs_cpr M, const double *d_b, double *d_x,
                             const rs_bicgstab_opts *o, rs_solve_info *info, void *stream);
 
 /* Adjoint solve A^T lambda = w (not in the paper; gives dJ/dA = -lambda x^T
  * for J = w^T x).  Builds on first use and caches, inside A, the block
  * transpose, its decoupling (method, prec) and its CPR (co); the cache is
- * dropped by rs_bsr_update.  d_lambda holds the initial guess on entry. */
+ * dropped by rs_bsr_update.  d_lambda holds the initial guess on entry;
+ * d_w and d_lambda must be 16-byte aligned (RS_E_ARG otherwise). */
 rs_status rs_adjoint_solve(rs_bsr A, int method, int prec, const rs_cpr_opts *co,
                            const double *d_w, double *d_lambda,
                            const rs_gmres_opts *o, rs_solve_info *info, void *stream);
@@ -188,7 +199,7 @@ void rs_cpr_destroy(rs_cpr M);
 
 /* ---- building blocks of the path, exposed for tests and measurement ----- */
 
-/* y = A x (Fig. fig-mv).  d_x, d_y: 4n doubles, must not alias. */
+/* y = A x (Fig. fig-mv).  d_x, d_y: 4n doubles, 16-byte aligned, must not alias. */
 rs_status rs_spmv(rs_bsr A, const double *d_x, double *d_y, void *stream);
 
 /* One application of the CPR preconditioner, z = M^{-1} r (FP64 in/out). */

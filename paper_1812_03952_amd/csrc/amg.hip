@@ -82,8 +82,11 @@ __global__ void k_scan_add(int32_t *__restrict__ out, const int32_t *__restrict_
   if (t < n) out[t] += boff[t / 1024];
 }
 
-// out = exclusive scan of in (n entries); *total = sum.  in may equal out.
-rs_status scan_i32(const int32_t *in, int32_t *out, int64_t n, int64_t *total, hipStream_t s) {
+// out = exclusive scan of in (n entries); in may equal out.  The sum goes to
+// *total (host: the stream is synchronised) and/or *dtotal (device, stream
+// ordered); either may be null.
+rs_status scan_i32(const int32_t *in, int32_t *out, int64_t n, int64_t *total, hipStream_t s,
+                   int32_t *dtotal) {
   int64_t nb = (n + 1023) / 1024;
   if (nb < 1) nb = 1;
   dbuf bs, bo;
@@ -91,14 +94,17 @@ rs_status scan_i32(const int32_t *in, int32_t *out, int64_t n, int64_t *total, h
   k_scan_block<<<(unsigned)nb, 256, 0, s>>>(in, out, bs.as<int32_t>(), n);
   RS_HIP(hipGetLastError());
   if (nb == 1) {
-    int32_t t = 0;
-    RS_HIP(hipMemcpyAsync(&t, bs.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    RS_HIP(hipStreamSynchronize(s));
-    *total = t;
+    if (dtotal) RS_HIP(hipMemcpyAsync(dtotal, bs.p, sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    if (total) {
+      int32_t t = 0;
+      RS_HIP(hipMemcpyAsync(&t, bs.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+      RS_HIP(hipStreamSynchronize(s));
+      *total = t;
+    }
     return RS_OK;
   }
   RS_TRY(bo.alloc(sizeof(int32_t) * nb));
-  RS_TRY(scan_i32(bs.as<int32_t>(), bo.as<int32_t>(), nb, total, s));
+  RS_TRY(scan_i32(bs.as<int32_t>(), bo.as<int32_t>(), nb, total, s, dtotal));
   k_scan_add<<<rs_grid(n), RS_BLOCK, 0, s>>>(out, bo.as<int32_t>(), n);
   RS_HIP(hipGetLastError());
   return RS_OK;
@@ -170,15 +176,39 @@ __global__ void k_strength_sym(int n, const int32_t *__restrict__ rp, const int3
   state[i] = deg ? ST_UND : ST_ISO;
 }
 
+// A fine-level cell's in-grid flags and neighbours by slot.
+struct cell7 {
+  int64_t c;
+  bool in[7];
+  int64_t nb[7];
+};
+__device__ __forceinline__ cell7 cell7_of(int64_t c, int nx, int ny, int nz) {
+  const int64_t nxy = (int64_t)nx * ny;
+  const int i = (int)(c % nx), j = (int)((c / nx) % ny), k = (int)(c / nxy);
+  cell7 e;
+  e.c = c;
+  e.in[0] = k > 0; e.in[1] = j > 0; e.in[2] = i > 0; e.in[3] = true;
+  e.in[4] = i < nx - 1; e.in[5] = j < ny - 1; e.in[6] = k < nz - 1;
+  e.nb[0] = c - nxy; e.nb[1] = c - nx; e.nb[2] = c - 1; e.nb[3] = c;
+  e.nb[4] = c + 1; e.nb[5] = c + nx; e.nb[6] = c + nxy;
+  return e;
+}
+
+constexpr int MIS_BATCH = 4;   // MIS rounds per host read
+
 __device__ __forceinline__ uint64_t keyof(uint8_t st, int v, int level) {
   return st == ST_ROOT ? ~0ull : (st == ST_UND ? prio(v, level) : 0ull);
 }
 
+// Rounds run in batches without a host read in between; a round whose
+// predecessor left no vertex undecided (*prev == 0) has nothing to change
+// and returns at once.  prev == nullptr: the predecessor is known to have
+// left some.
 __global__ void k_mis_m1(int n, int level, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
                          const uint8_t *__restrict__ strong, const uint8_t *__restrict__ state,
-                         uint64_t *__restrict__ m1) {
+                         uint64_t *__restrict__ m1, const int *__restrict__ prev) {
   int u = blockIdx.x * blockDim.x + threadIdx.x;
-  if (u >= n) return;
+  if (u >= n || (prev && *prev == 0)) return;
   uint64_t m = keyof(state[u], u, level);
   for (int p = rp[u]; p < rp[u + 1]; ++p)
     if (strong[p]) {
@@ -191,9 +221,9 @@ __global__ void k_mis_m1(int n, int level, const int32_t *__restrict__ rp, const
 
 __global__ void k_mis_m2(int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
                          const uint8_t *__restrict__ strong, const uint64_t *__restrict__ m1,
-                         uint64_t *__restrict__ m2) {
+                         uint64_t *__restrict__ m2, const int *__restrict__ prev) {
   int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= n) return;
+  if (v >= n || (prev && *prev == 0)) return;
   uint64_t m = m1[v];
   for (int p = rp[v]; p < rp[v + 1]; ++p)
     if (strong[p]) {
@@ -204,7 +234,8 @@ __global__ void k_mis_m2(int n, const int32_t *__restrict__ rp, const int32_t *_
 }
 
 __global__ void k_mis_decide(int n, int level, const uint64_t *__restrict__ m2, uint8_t *__restrict__ state,
-                             int *__restrict__ undecided) {
+                             int *__restrict__ undecided, const int *__restrict__ prev) {
+  if (prev && *prev == 0) return;             // *undecided stays 0
   int v = blockIdx.x * blockDim.x + threadIdx.x;
   int left = 0;
   if (v < n && state[v] == ST_UND) {
@@ -295,27 +326,57 @@ __global__ void k_cand(int nc, const int32_t *__restrict__ mptr, const int32_t *
 
 // Coarse row I: accumulate members' rows into a first-seen list, then sort
 // the list by column (insertion sort on the short list).  The list lives in
-// LDS (one column per thread: entry s of thread t at [s][t]) when the row's
-// candidate count fits GAL_CAP, in the global scratch otherwise; the
-// additions happen in the same order either way.
+// LDS (one column per thread: entry s of thread t at [s][t]) while it holds
+// at most GAL_CAP distinct coarse columns; a row that needs more starts
+// again with the list in the global scratch (sized by the candidate count).
+// The additions happen in the same order either way.
 constexpr int GAL_BLOCK = 128, GAL_CAP = 32;
 
-template <class K, class V>
-__device__ __forceinline__ void gal_row(int I, const int32_t *__restrict__ mptr, const int32_t *__restrict__ mem,
-                                        const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
-                                        const double *__restrict__ a, const int32_t *__restrict__ agg, K key,
-                                        V val, int &m) {
+// Row sources: each(i, f) calls f(col, a) for the entries of fine row i in
+// column order and stops when f returns false.
+struct rows_csr {
+  const int32_t *rp, *ci;
+  const double *a;
+  template <class F> __device__ __forceinline__ bool each(int i, F &&f) const {
+    for (int p = rp[i]; p < rp[i + 1]; ++p)
+      if (!f(ci[p], a[p])) return false;
+    return true;
+  }
+};
+struct rows_7 {
+  int nx, ny, nz;
+  const double *ap7;
+  template <class F> __device__ __forceinline__ bool each(int i, F &&f) const {
+    const int64_t n = (int64_t)nx * ny * nz;
+    const cell7 e = cell7_of(i, nx, ny, nz);
+    for (int sl = 0; sl < 7; ++sl)
+      if (e.in[sl] && !f((int)e.nb[sl], ap7[sl * n + i])) return false;
+    return true;
+  }
+};
+
+// false when the list would exceed cap entries
+template <class R, class K, class V>
+__device__ __forceinline__ bool gal_row(int I, const int32_t *__restrict__ mptr, const int32_t *__restrict__ mem,
+                                        const R &rows, const int32_t *__restrict__ agg, K key, V val, int cap,
+                                        int &m) {
   m = 0;
   for (int x = mptr[I]; x < mptr[I + 1]; ++x) {
-    int i = mem[x];
-    for (int p = rp[i]; p < rp[i + 1]; ++p) {
-      int J = agg[ci[p]];
-      if (J < 0) continue;
+    const bool ok = rows.each(mem[x], [&](int col, double a) -> bool {
+      const int J = agg[col];
+      if (J < 0) return true;
       int s = 0;
       while (s < m && key(s) != J) ++s;
-      if (s == m) { key(m) = J; val(m) = 0.0; ++m; }
-      val(s) = val(s) + a[p];
-    }
+      if (s == m) {
+        if (m == cap) return false;
+        key(m) = J;
+        val(m) = 0.0;
+        ++m;
+      }
+      val(s) = val(s) + a;
+      return true;
+    });
+    if (!ok) return false;
   }
   for (int x = 1; x < m; ++x) {
     int k = key(x);
@@ -325,12 +386,13 @@ __device__ __forceinline__ void gal_row(int I, const int32_t *__restrict__ mptr,
     key(y + 1) = k;
     val(y + 1) = v;
   }
+  return true;
 }
 
+template <class R>
 __global__ __launch_bounds__(GAL_BLOCK) void k_galerkin(int nc, const int32_t *__restrict__ mptr,
-                                                        const int32_t *__restrict__ mem,
-                                                        const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
-                                                        const double *__restrict__ a, const int32_t *__restrict__ agg,
+                                                        const int32_t *__restrict__ mem, R rows,
+                                                        const int32_t *__restrict__ agg,
                                                         const int32_t *__restrict__ off, int32_t *__restrict__ skey,
                                                         double *__restrict__ sval, int32_t *__restrict__ cnt) {
   __shared__ int32_t lk[GAL_CAP][GAL_BLOCK];
@@ -340,13 +402,12 @@ __global__ __launch_bounds__(GAL_BLOCK) void k_galerkin(int nc, const int32_t *_
   if (I >= nc) return;
   const int base = off[I], ncand = cnt[I];       // candidate count from k_cand
   int m = 0;
-  if (ncand <= GAL_CAP) {
-    gal_row(I, mptr, mem, rp, ci, a, agg, [&](int s) -> int32_t & { return lk[s][t]; },
-            [&](int s) -> double & { return lv[s][t]; }, m);
+  if (gal_row(I, mptr, mem, rows, agg, [&](int s) -> int32_t & { return lk[s][t]; },
+              [&](int s) -> double & { return lv[s][t]; }, GAL_CAP, m)) {
     for (int s = 0; s < m; ++s) { skey[base + s] = lk[s][t]; sval[base + s] = lv[s][t]; }
   } else {
-    gal_row(I, mptr, mem, rp, ci, a, agg, [&](int s) -> int32_t & { return skey[base + s]; },
-            [&](int s) -> double & { return sval[base + s]; }, m);
+    gal_row(I, mptr, mem, rows, agg, [&](int s) -> int32_t & { return skey[base + s]; },
+            [&](int s) -> double & { return sval[base + s]; }, ncand, m);
   }
   cnt[I] = m;
 }
@@ -360,7 +421,7 @@ __global__ void k_galerkin_copy(int nc, const int32_t *__restrict__ off, const i
   for (int s = 0; s < m; ++s) { cci[o + s] = skey[b + s]; ca[o + s] = sval[b + s]; }
 }
 
-__global__ void k_set_last(int32_t *__restrict__ p, int64_t idx, int32_t v) { p[idx] = v; }
+__global__ void k_set_last(int32_t *__restrict__ p, int64_t idx, const int32_t *__restrict__ v) { p[idx] = *v; }
 
 template <class T>
 __global__ void k_l1diag(int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
@@ -816,6 +877,147 @@ __global__ void k_from_f64(int n, const double *__restrict__ a, T *__restrict__ 
   if (i < n) b[i] = (T)a[i];
 }
 
+// ---- structured fine level ---------------------------------------------------
+// The fine level is the 7-point grid with its entries by slot (ap7[s][c],
+// slots -z -y -x self +x +y +z in ascending column order).  These kernels
+// take the CSR kernels' operations in the same order, reading a cell's
+// entries from the slot planes: a row's CSR entries are exactly its in-grid
+// slots, in slot order.  Strong couplings are a 7-bit mask per cell.
+template <class T>
+__global__ void k_l1diag7(int nx, int ny, int nz, const double *__restrict__ ap7, T *__restrict__ d) {
+  const int64_t n = (int64_t)nx * ny * nz, c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  const cell7 e = cell7_of(c, nx, ny, nz);
+  double sum = 0.0;
+#pragma unroll
+  for (int sl = 0; sl < 7; ++sl)
+    if (e.in[sl]) sum = sum + fabs(ap7[sl * n + c]);
+  const double aii = ap7[3 * n + c];
+  if (sum == 0.0) sum = 1.0;
+  d[c] = (T)(aii < 0.0 ? -sum : sum);
+}
+
+// dmask bit s: j = nbr(c, s) influences c (k_strength_dir's test)
+__global__ void k_strength7_dir(int nx, int ny, int nz, const double *__restrict__ ap7, double theta, double mrs,
+                                uint8_t *__restrict__ dmask) {
+  const int64_t n = (int64_t)nx * ny * nz, c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  const cell7 e = cell7_of(c, nx, ny, nz);
+  double v[7];
+  double aii = 0.0, nm = 0.0, sum = 0.0;
+#pragma unroll
+  for (int sl = 0; sl < 7; ++sl) {
+    v[sl] = e.in[sl] ? ap7[sl * n + c] : 0.0;
+    if (!e.in[sl]) continue;
+    sum = sum + v[sl];
+    if (sl == 3) aii = v[sl];
+    else if (-v[sl] > nm) nm = -v[sl];
+  }
+  const bool weak = fabs(sum) > mrs * fabs(aii) || !(nm > 0.0);
+  const double thr = theta * nm;
+  uint8_t m = 0;
+#pragma unroll
+  for (int sl = 0; sl < 7; ++sl)
+    if (e.in[sl] && sl != 3 && !weak && -v[sl] >= thr) m |= (uint8_t)(1u << sl);
+  dmask[c] = m;
+}
+
+// symmetrised: smask bit s = dmask(c) bit s | dmask(nbr) bit 6-s
+__global__ void k_strength7_sym(int nx, int ny, int nz, const uint8_t *__restrict__ dmask,
+                                uint8_t *__restrict__ smask, uint8_t *__restrict__ state) {
+  const int64_t n = (int64_t)nx * ny * nz, c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  const cell7 e = cell7_of(c, nx, ny, nz);
+  const uint8_t own = dmask[c];
+  uint8_t m = 0;
+#pragma unroll
+  for (int sl = 0; sl < 7; ++sl)
+    if (e.in[sl] && sl != 3 && (((own >> sl) & 1u) || ((dmask[e.nb[sl]] >> (6 - sl)) & 1u))) m |= (uint8_t)(1u << sl);
+  smask[c] = m;
+  state[c] = m ? ST_UND : ST_ISO;
+}
+
+__global__ void k_mis7_m1(int nx, int ny, int nz, int level, const uint8_t *__restrict__ smask,
+                          const uint8_t *__restrict__ state, uint64_t *__restrict__ m1, const int *__restrict__ prev) {
+  const int64_t n = (int64_t)nx * ny * nz, c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n || (prev && *prev == 0)) return;
+  const cell7 e = cell7_of(c, nx, ny, nz);
+  const uint8_t sm = smask[c];
+  uint64_t m = keyof(state[c], (int)c, level);
+#pragma unroll
+  for (int sl = 0; sl < 7; ++sl)
+    if ((sm >> sl) & 1u) {
+      const uint64_t kk = keyof(state[e.nb[sl]], (int)e.nb[sl], level);
+      m = kk > m ? kk : m;
+    }
+  m1[c] = m;
+}
+
+__global__ void k_mis7_m2(int nx, int ny, int nz, const uint8_t *__restrict__ smask, const uint64_t *__restrict__ m1,
+                          uint64_t *__restrict__ m2, const int *__restrict__ prev) {
+  const int64_t n = (int64_t)nx * ny * nz, c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n || (prev && *prev == 0)) return;
+  const cell7 e = cell7_of(c, nx, ny, nz);
+  const uint8_t sm = smask[c];
+  uint64_t m = m1[c];
+#pragma unroll
+  for (int sl = 0; sl < 7; ++sl)
+    if ((sm >> sl) & 1u) {
+      const uint64_t kk = m1[e.nb[sl]];
+      m = kk > m ? kk : m;
+    }
+  m2[c] = m;
+}
+
+__global__ void k_agg1_7(int nx, int ny, int nz, const uint8_t *__restrict__ smask, const uint8_t *__restrict__ state,
+                         const int32_t *__restrict__ id, int32_t *__restrict__ agg1) {
+  const int64_t n = (int64_t)nx * ny * nz, c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  const cell7 e = cell7_of(c, nx, ny, nz);
+  int g = -1;
+  const uint8_t st = state[c], sm = smask[c];
+  if (st == ST_ROOT) g = id[c];
+  else if (st != ST_ISO)
+    for (int sl = 0; sl < 7; ++sl)
+      if (((sm >> sl) & 1u) && state[e.nb[sl]] == ST_ROOT) { g = id[e.nb[sl]]; break; }
+  agg1[c] = g;
+}
+
+__global__ void k_agg2_7(int nx, int ny, int nz, const uint8_t *__restrict__ smask, const double *__restrict__ ap7,
+                         const uint8_t *__restrict__ state, const int32_t *__restrict__ agg1,
+                         int32_t *__restrict__ agg, int *__restrict__ bad) {
+  const int64_t n = (int64_t)nx * ny * nz, c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  const cell7 e = cell7_of(c, nx, ny, nz);
+  int g = agg1[c];
+  if (g < 0 && state[c] != ST_ISO) {
+    const uint8_t sm = smask[c];
+    double bw = -1.0;
+    for (int sl = 0; sl < 7; ++sl) {
+      if (!((sm >> sl) & 1u)) continue;
+      const int ag = agg1[e.nb[sl]];
+      if (ag < 0) continue;
+      const double w = fabs(ap7[sl * n + c]);
+      if (w > bw || (w == bw && ag < g)) { bw = w; g = ag; }
+    }
+    if (g < 0) atomicOr(bad, 1);     // cannot happen for a maximal distance-2 set
+  }
+  agg[c] = g;
+}
+
+__global__ void k_cand7(int nc, int nx, int ny, int nz, const int32_t *__restrict__ mptr, const int32_t *__restrict__ mem,
+                        int32_t *__restrict__ cand) {
+  const int I = blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= nc) return;
+  int cnt = 0;
+  for (int x = mptr[I]; x < mptr[I + 1]; ++x) {
+    const cell7 e = cell7_of(mem[x], nx, ny, nz);
+#pragma unroll
+    for (int sl = 0; sl < 7; ++sl) cnt += e.in[sl] ? 1 : 0;
+  }
+  cand[I] = cnt;
+}
+
 // x = Cinv b, one wave per row.
 template <class T>
 __global__ void k_dense_mv(int n, const double *__restrict__ Ci, const T *__restrict__ b, T *__restrict__ x) {
@@ -832,7 +1034,9 @@ __global__ void k_dense_mv(int n, const double *__restrict__ Ci, const T *__rest
 }  // namespace
 
 // ---------------------------------------------------------------------------
-static rs_status level_alloc_work(amg_level *L, int prec, int64_t guard, hipStream_t s) {
+rs_status rs_amg_level0_csr(rs_cpr_s *M, hipStream_t s);
+
+static rs_status level_alloc_work(amg_level *L, int prec, int64_t guard, bool csr_values, hipStream_t s) {
   size_t es = prec == 64 ? sizeof(double) : sizeof(float);
   RS_TRY(L->b.alloc(es * (L->n + 1)));
   // the fine level's iterate is read at every stencil neighbour of every cell
@@ -842,22 +1046,28 @@ static rs_status level_alloc_work(amg_level *L, int prec, int64_t guard, hipStre
   if (guard) RS_HIP(hipMemsetAsync(L->x.p, 0, es * (L->n + 1 + 2 * guard), s));
   RS_TRY(L->r.alloc(es * (L->n + 1)));
   RS_TRY(L->dl1.alloc(es * (L->n + 1)));
-  if (prec == 32) {
+  if (prec == 32 && csr_values) {
     RS_TRY(L->ap.alloc(sizeof(float) * (L->nnz + 1)));
   }
   return RS_OK;
 }
 
-// Build the whole hierarchy; M->lev[0] must hold n, nnz, rp, ci, a (FP64).
+// Build the whole hierarchy; M->lev[0] must hold n and nnz.  The fine level
+// is set up by the structured kernels from the pressure entries by slot; its
+// CSR arrays are built only when it is also the coarsest level (or when it is
+// inspected).
 rs_status rs_amg_build(rs_cpr_s *M, hipStream_t s) {
   const rs_cpr_opts &o = M->o;
   int prec = M->prec;
-  dbuf flag;
-  RS_TRY(flag.alloc(sizeof(int)));
+  dbuf flag;                            // [0] error flag, [1] coarse nnz of the level
+  RS_TRY(flag.alloc(sizeof(int) * 2));
   for (int l = 0;; ++l) {
     amg_level *L = M->lev[l];
     int n = L->n;
-    RS_TRY(level_alloc_work(L, prec, l == 0 ? M->A->g.nxy : 0, s));
+    const bool last = n <= o.coarse_n || (int)M->lev.size() >= o.max_levels;
+    const bool st7 = l == 0 && !last;       // structured set-up of the fine level
+    if (l == 0 && last) RS_TRY(rs_amg_level0_csr(M, s));
+    RS_TRY(level_alloc_work(L, prec, l == 0 ? M->A->g.nxy : 0, !st7, s));
     if (l == 0) {
       size_t es = prec == 64 ? sizeof(double) : sizeof(float);
       RS_TRY(L->s7.alloc(es * 7 * (size_t)n));
@@ -867,34 +1077,58 @@ rs_status rs_amg_build(rs_cpr_s *M, hipStream_t s) {
       RS_HIP(hipGetLastError());
     }
     RS_TRY(L->agg.alloc(sizeof(int32_t) * (n + 1)));
-    if (prec == 64) k_l1diag<double><<<rs_grid(n), RS_BLOCK, 0, s>>>(n, L->rp.as<int32_t>(), L->ci.as<int32_t>(), L->a.as<double>(), L->dl1.as<double>());
-    else k_l1diag<float><<<rs_grid(n), RS_BLOCK, 0, s>>>(n, L->rp.as<int32_t>(), L->ci.as<int32_t>(), L->a.as<double>(), L->dl1.as<float>());
-    RS_HIP(hipGetLastError());
-    if (prec == 32) {
-      k_cast_f32<<<rs_grid(L->nnz), RS_BLOCK, 0, s>>>(L->nnz, L->a.as<double>(), L->ap.as<float>());
-      RS_HIP(hipGetLastError());
+    const grid3 &g = M->A->g;
+    const double *ap7 = M->D->ap7.as<double>();
+    if (st7) {
+      if (prec == 64) k_l1diag7<double><<<rs_grid(n), RS_BLOCK, 0, s>>>(g.nx, g.ny, g.nz, ap7, L->dl1.as<double>());
+      else k_l1diag7<float><<<rs_grid(n), RS_BLOCK, 0, s>>>(g.nx, g.ny, g.nz, ap7, L->dl1.as<float>());
+    } else {
+      if (prec == 64) k_l1diag<double><<<rs_grid(n), RS_BLOCK, 0, s>>>(n, L->rp.as<int32_t>(), L->ci.as<int32_t>(), L->a.as<double>(), L->dl1.as<double>());
+      else k_l1diag<float><<<rs_grid(n), RS_BLOCK, 0, s>>>(n, L->rp.as<int32_t>(), L->ci.as<int32_t>(), L->a.as<double>(), L->dl1.as<float>());
+      if (prec == 32) k_cast_f32<<<rs_grid(L->nnz), RS_BLOCK, 0, s>>>(L->nnz, L->a.as<double>(), L->ap.as<float>());
     }
-    RS_HIP(hipMemsetAsync(L->agg.p, 0xff, sizeof(int32_t) * (n + 1), s));
-    if (n <= o.coarse_n || (int)M->lev.size() >= o.max_levels) break;
-    // strength
-    dbuf dir, strong, state, m1, m2, und;
-    RS_TRY(dir.alloc(L->nnz)); RS_TRY(strong.alloc(L->nnz)); RS_TRY(state.alloc(n));
-    RS_TRY(m1.alloc(sizeof(uint64_t) * n)); RS_TRY(m2.alloc(sizeof(uint64_t) * n));
-    RS_TRY(und.alloc(sizeof(int)));
-    const int32_t *rp = L->rp.as<int32_t>(), *ci = L->ci.as<int32_t>();
-    k_strength_dir<<<rs_grid(n), RS_BLOCK, 0, s>>>(n, rp, ci, L->a.as<double>(), o.theta, o.max_row_sum, dir.as<uint8_t>());
-    k_strength_sym<<<rs_grid(n), RS_BLOCK, 0, s>>>(n, rp, ci, dir.as<uint8_t>(), strong.as<uint8_t>(), state.as<uint8_t>());
     RS_HIP(hipGetLastError());
-    // distance-2 MIS rounds
-    for (int round = 0;; ++round) {
+    RS_HIP(hipMemsetAsync(L->agg.p, 0xff, sizeof(int32_t) * (n + 1), s));
+    if (last) break;
+    // strength: per CSR entry, or a 7-bit mask per cell on the fine level
+    dbuf dir, strong, state, m1, m2, und;
+    RS_TRY(dir.alloc(st7 ? n : L->nnz)); RS_TRY(strong.alloc(st7 ? n : L->nnz)); RS_TRY(state.alloc(n));
+    RS_TRY(m1.alloc(sizeof(uint64_t) * n)); RS_TRY(m2.alloc(sizeof(uint64_t) * n));
+    RS_TRY(und.alloc(sizeof(int) * MIS_BATCH));
+    const int32_t *rp = L->rp.as<int32_t>(), *ci = L->ci.as<int32_t>();
+    if (st7) {
+      k_strength7_dir<<<rs_grid(n), RS_BLOCK, 0, s>>>(g.nx, g.ny, g.nz, ap7, o.theta, o.max_row_sum, dir.as<uint8_t>());
+      k_strength7_sym<<<rs_grid(n), RS_BLOCK, 0, s>>>(g.nx, g.ny, g.nz, dir.as<uint8_t>(), strong.as<uint8_t>(),
+                                                      state.as<uint8_t>());
+    } else {
+      k_strength_dir<<<rs_grid(n), RS_BLOCK, 0, s>>>(n, rp, ci, L->a.as<double>(), o.theta, o.max_row_sum, dir.as<uint8_t>());
+      k_strength_sym<<<rs_grid(n), RS_BLOCK, 0, s>>>(n, rp, ci, dir.as<uint8_t>(), strong.as<uint8_t>(), state.as<uint8_t>());
+    }
+    RS_HIP(hipGetLastError());
+    // distance-2 MIS rounds, MIS_BATCH per host read; und[b] = 1 when round b
+    // of the batch left undecided vertices
+    for (int round = 0;; round += MIS_BATCH) {
       if (round > n + 2) return RS_E_HIP;     // progress is guaranteed; guard anyway
-      RS_HIP(hipMemsetAsync(und.p, 0, sizeof(int), s));
-      k_mis_m1<<<rs_grid(n), RS_BLOCK, 0, s>>>(n, l, rp, ci, strong.as<uint8_t>(), state.as<uint8_t>(), m1.as<uint64_t>());
-      k_mis_m2<<<rs_grid(n), RS_BLOCK, 0, s>>>(n, rp, ci, strong.as<uint8_t>(), m1.as<uint64_t>(), m2.as<uint64_t>());
-      k_mis_decide<<<rs_grid(n), RS_BLOCK, 0, s>>>(n, l, m2.as<uint64_t>(), state.as<uint8_t>(), und.as<int>());
+      RS_HIP(hipMemsetAsync(und.p, 0, sizeof(int) * MIS_BATCH, s));
+      for (int b = 0; b < MIS_BATCH; ++b) {
+        const int *prev = b ? und.as<int>() + b - 1 : nullptr;
+        if (st7) {
+          k_mis7_m1<<<rs_grid(n), RS_BLOCK, 0, s>>>(g.nx, g.ny, g.nz, l, strong.as<uint8_t>(), state.as<uint8_t>(),
+                                                    m1.as<uint64_t>(), prev);
+          k_mis7_m2<<<rs_grid(n), RS_BLOCK, 0, s>>>(g.nx, g.ny, g.nz, strong.as<uint8_t>(), m1.as<uint64_t>(),
+                                                    m2.as<uint64_t>(), prev);
+        } else {
+          k_mis_m1<<<rs_grid(n), RS_BLOCK, 0, s>>>(n, l, rp, ci, strong.as<uint8_t>(), state.as<uint8_t>(),
+                                                   m1.as<uint64_t>(), prev);
+          k_mis_m2<<<rs_grid(n), RS_BLOCK, 0, s>>>(n, rp, ci, strong.as<uint8_t>(), m1.as<uint64_t>(),
+                                                   m2.as<uint64_t>(), prev);
+        }
+        k_mis_decide<<<rs_grid(n), RS_BLOCK, 0, s>>>(n, l, m2.as<uint64_t>(), state.as<uint8_t>(),
+                                                     und.as<int>() + b, prev);
+      }
       RS_HIP(hipGetLastError());
       int h = 0;
-      RS_HIP(hipMemcpyAsync(&h, und.p, sizeof(int), hipMemcpyDeviceToHost, s));
+      RS_HIP(hipMemcpyAsync(&h, und.as<int>() + MIS_BATCH - 1, sizeof(int), hipMemcpyDeviceToHost, s));
       RS_HIP(hipStreamSynchronize(s));
       if (h == 0) break;
     }
@@ -904,13 +1138,20 @@ rs_status rs_amg_build(rs_cpr_s *M, hipStream_t s) {
     k_root_flag<<<rs_grid(n), RS_BLOCK, 0, s>>>(n, state.as<uint8_t>(), id.as<int32_t>());
     RS_HIP(hipGetLastError());
     int64_t nc64 = 0;
-    RS_TRY(scan_i32(id.as<int32_t>(), id.as<int32_t>(), n, &nc64, s));
+    RS_TRY(scan_i32(id.as<int32_t>(), id.as<int32_t>(), n, &nc64, s, nullptr));
     int nc = (int)nc64;
     if (nc == 0 || nc >= n) break;   // no coarsening possible: this level is the coarsest
     RS_HIP(hipMemsetAsync(flag.p, 0, sizeof(int), s));
-    k_agg1<<<rs_grid(n), RS_BLOCK, 0, s>>>(n, rp, ci, strong.as<uint8_t>(), state.as<uint8_t>(), id.as<int32_t>(), agg1.as<int32_t>());
-    k_agg2<<<rs_grid(n), RS_BLOCK, 0, s>>>(n, rp, ci, strong.as<uint8_t>(), L->a.as<double>(), state.as<uint8_t>(),
-                                           agg1.as<int32_t>(), L->agg.as<int32_t>(), flag.as<int>());
+    if (st7) {
+      k_agg1_7<<<rs_grid(n), RS_BLOCK, 0, s>>>(g.nx, g.ny, g.nz, strong.as<uint8_t>(), state.as<uint8_t>(),
+                                               id.as<int32_t>(), agg1.as<int32_t>());
+      k_agg2_7<<<rs_grid(n), RS_BLOCK, 0, s>>>(g.nx, g.ny, g.nz, strong.as<uint8_t>(), ap7, state.as<uint8_t>(),
+                                               agg1.as<int32_t>(), L->agg.as<int32_t>(), flag.as<int>());
+    } else {
+      k_agg1<<<rs_grid(n), RS_BLOCK, 0, s>>>(n, rp, ci, strong.as<uint8_t>(), state.as<uint8_t>(), id.as<int32_t>(), agg1.as<int32_t>());
+      k_agg2<<<rs_grid(n), RS_BLOCK, 0, s>>>(n, rp, ci, strong.as<uint8_t>(), L->a.as<double>(), state.as<uint8_t>(),
+                                             agg1.as<int32_t>(), L->agg.as<int32_t>(), flag.as<int>());
+    }
     RS_HIP(hipGetLastError());
     L->nc = nc;
     // members of each aggregate, ascending
@@ -920,9 +1161,9 @@ rs_status rs_amg_build(rs_cpr_s *M, hipStream_t s) {
     RS_HIP(hipMemsetAsync(cnt.p, 0, sizeof(int32_t) * (nc + 1), s));
     k_count_members<<<rs_grid(n), RS_BLOCK, 0, s>>>(n, L->agg.as<int32_t>(), cnt.as<int32_t>());
     RS_HIP(hipGetLastError());
-    int64_t nmem = 0;
-    RS_TRY(scan_i32(cnt.as<int32_t>(), L->mptr.as<int32_t>(), nc + 1, &nmem, s));
-    RS_TRY(L->mem.alloc(sizeof(int32_t) * (nmem + 1)));
+    // members: at most n (no host read of the exact count)
+    RS_TRY(scan_i32(cnt.as<int32_t>(), L->mptr.as<int32_t>(), nc + 1, nullptr, s, nullptr));
+    RS_TRY(L->mem.alloc(sizeof(int32_t) * ((size_t)n + 1)));
     RS_HIP(hipMemsetAsync(cnt.p, 0, sizeof(int32_t) * (nc + 1), s));
     k_fill_members<<<rs_grid(n), RS_BLOCK, 0, s>>>(n, L->agg.as<int32_t>(), L->mptr.as<int32_t>(), cnt.as<int32_t>(), L->mem.as<int32_t>());
     k_sort_members<<<rs_grid(nc), RS_BLOCK, 0, s>>>(nc, L->mptr.as<int32_t>(), L->mem.as<int32_t>());
@@ -930,33 +1171,41 @@ rs_status rs_amg_build(rs_cpr_s *M, hipStream_t s) {
     // Galerkin product
     dbuf off, skey, sval;
     RS_TRY(off.alloc(sizeof(int32_t) * (nc + 1)));
-    k_cand<<<rs_grid(nc), RS_BLOCK, 0, s>>>(nc, L->mptr.as<int32_t>(), L->mem.as<int32_t>(), rp, cnt.as<int32_t>());
+    if (st7) k_cand7<<<rs_grid(nc), RS_BLOCK, 0, s>>>(nc, g.nx, g.ny, g.nz, L->mptr.as<int32_t>(), L->mem.as<int32_t>(), cnt.as<int32_t>());
+    else k_cand<<<rs_grid(nc), RS_BLOCK, 0, s>>>(nc, L->mptr.as<int32_t>(), L->mem.as<int32_t>(), rp, cnt.as<int32_t>());
     RS_HIP(hipGetLastError());
-    int64_t ncand = 0;
-    RS_TRY(scan_i32(cnt.as<int32_t>(), off.as<int32_t>(), nc, &ncand, s));
+    // candidates: the members' row entries, at most this level's nnz
+    RS_TRY(scan_i32(cnt.as<int32_t>(), off.as<int32_t>(), nc, nullptr, s, nullptr));
+    const int64_t ncand = L->nnz;
     RS_TRY(skey.alloc(sizeof(int32_t) * (ncand + 1)));
     RS_TRY(sval.alloc(sizeof(double) * (ncand + 1)));
-    k_galerkin<<<rs_grid(nc, GAL_BLOCK), GAL_BLOCK, 0, s>>>(nc, L->mptr.as<int32_t>(), L->mem.as<int32_t>(), rp, ci, L->a.as<double>(),
-                                                 L->agg.as<int32_t>(), off.as<int32_t>(), skey.as<int32_t>(),
-                                                 sval.as<double>(), cnt.as<int32_t>());
+    if (st7)
+      k_galerkin<rows_7><<<rs_grid(nc, GAL_BLOCK), GAL_BLOCK, 0, s>>>(
+          nc, L->mptr.as<int32_t>(), L->mem.as<int32_t>(), rows_7{g.nx, g.ny, g.nz, ap7}, L->agg.as<int32_t>(),
+          off.as<int32_t>(), skey.as<int32_t>(), sval.as<double>(), cnt.as<int32_t>());
+    else
+      k_galerkin<rows_csr><<<rs_grid(nc, GAL_BLOCK), GAL_BLOCK, 0, s>>>(
+          nc, L->mptr.as<int32_t>(), L->mem.as<int32_t>(), rows_csr{rp, ci, L->a.as<double>()}, L->agg.as<int32_t>(),
+          off.as<int32_t>(), skey.as<int32_t>(), sval.as<double>(), cnt.as<int32_t>());
     RS_HIP(hipGetLastError());
     amg_level *C = new amg_level();
     M->lev.push_back(C);
     C->n = nc;
     RS_TRY(C->rp.alloc(sizeof(int32_t) * (nc + 1)));
-    int64_t cnnz = 0;
-    RS_TRY(scan_i32(cnt.as<int32_t>(), C->rp.as<int32_t>(), nc, &cnnz, s));
-    k_set_last<<<1, 1, 0, s>>>(C->rp.as<int32_t>(), nc, (int32_t)cnnz);
-    C->nnz = cnnz;
-    RS_TRY(C->ci.alloc(sizeof(int32_t) * (cnnz + 1)));
-    RS_TRY(C->a.alloc(sizeof(double) * (cnnz + 1)));
+    // coarse nnz: on the device for rp[nc], read with the error flag below;
+    // ci and a sized by the candidate bound
+    RS_TRY(scan_i32(cnt.as<int32_t>(), C->rp.as<int32_t>(), nc, nullptr, s, flag.as<int32_t>() + 1));
+    k_set_last<<<1, 1, 0, s>>>(C->rp.as<int32_t>(), nc, flag.as<int32_t>() + 1);
+    RS_TRY(C->ci.alloc(sizeof(int32_t) * (ncand + 1)));
+    RS_TRY(C->a.alloc(sizeof(double) * (ncand + 1)));
     k_galerkin_copy<<<rs_grid(nc), RS_BLOCK, 0, s>>>(nc, off.as<int32_t>(), skey.as<int32_t>(), sval.as<double>(),
                                                       C->rp.as<int32_t>(), C->ci.as<int32_t>(), C->a.as<double>());
     RS_HIP(hipGetLastError());
-    int h = 0;
-    RS_HIP(hipMemcpyAsync(&h, flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    int h[2] = {0, 0};
+    RS_HIP(hipMemcpyAsync(h, flag.p, sizeof(int) * 2, hipMemcpyDeviceToHost, s));
     RS_HIP(hipStreamSynchronize(s));
-    if (h) return RS_E_HIP;
+    if (h[0]) return RS_E_HIP;
+    C->nnz = h[1];
   }
   M->nlev = (int)M->lev.size();
   // coarsest level
@@ -1045,6 +1294,10 @@ extern "C" rs_status rs_cpr_level(rs_cpr M, int l, int *h_n, int64_t *h_nnz, int
   if (!M || l < 0 || l >= M->nlev) return RS_E_ARG;
   RS_HIP(hipDeviceSynchronize());
   amg_level *L = M->lev[l];
+  if (l == 0 && (h_rp || h_ci || h_a) && !L->a.p) {   // the fine level's CSR on demand
+    RS_TRY(rs_amg_level0_csr(M, nullptr));
+    RS_HIP(hipDeviceSynchronize());
+  }
   if (h_n) *h_n = L->n;
   if (h_nnz) *h_nnz = L->nnz;
   if (h_rp) RS_HIP(hipMemcpy(h_rp, L->rp.p, sizeof(int32_t) * (L->n + 1), hipMemcpyDeviceToHost));
@@ -1097,11 +1350,22 @@ extern "C" rs_status rs_cpr_vcycle(rs_cpr M, const double *d_b, double *d_x, voi
 }
 
 rs_status rs_amg_level0(rs_cpr_s *M, hipStream_t s) {
+  (void)s;
   rs_bsr_s *A = M->A;
   amg_level *L = new amg_level();
   M->lev.push_back(L);
   L->n = (int)A->g.n;
   L->nnz = A->nnzb;
+  return RS_OK;
+}
+
+// CSR arrays of the fine level (the validated 7-point pattern, values from
+// the pressure entries by slot), for when it is the coarsest level or is
+// inspected.
+rs_status rs_amg_level0_csr(rs_cpr_s *M, hipStream_t s) {
+  rs_bsr_s *A = M->A;
+  amg_level *L = M->lev[0];
+  if (L->a.p) return RS_OK;
   RS_TRY(L->rp.alloc(sizeof(int32_t) * (L->n + 1)));
   RS_TRY(L->ci.alloc(sizeof(int32_t) * L->nnz));
   RS_TRY(L->a.alloc(sizeof(double) * L->nnz));

@@ -350,6 +350,7 @@ extern "C" rs_status rs_bicgstab_solve(rs_bsr A, rs_cpr M, const double *d_b, do
                                        const rs_bicgstab_opts *o, rs_solve_info *info, void *stream) {
   if (info) memset(info, 0, sizeof(*info));
   if (!A || !M || !d_b || !d_x || d_b == d_x || M->A != A) return RS_E_ARG;
+  if (((uintptr_t)d_b | (uintptr_t)d_x) & 15) return RS_E_ARG;     // read 16 bytes at a time
   rs_bicgstab_opts opts;
   if (o) opts = *o; else rs_bicgstab_opts_default(&opts);
   if (opts.maxit < 0 || !(opts.rtol >= 0.0)) return RS_E_ARG;

@@ -291,11 +291,16 @@ extern "C" rs_status rs_bsr_create(int nx, int ny, int nz, int bs, int64_t nnzb,
   return RS_OK;
 }
 
-extern "C" rs_status rs_bsr_update(rs_bsr A, const double *d_vals, void *stream) {
-  if (!A || !d_vals) return RS_E_ARG;
+// New values make the cached transpose, its decoupling and CPR stale.
+void rs_bsr_drop_adjoint(rs_bsr_s *A) {
   if (A->at_m) { rs_cpr_destroy(A->at_m); A->at_m = nullptr; }
   if (A->at_d) { rs_dcpl_destroy(A->at_d); A->at_d = nullptr; }
   if (A->at) { delete A->at; A->at = nullptr; }
+}
+
+extern "C" rs_status rs_bsr_update(rs_bsr A, const double *d_vals, void *stream) {
+  if (!A || !d_vals) return RS_E_ARG;
+  rs_bsr_drop_adjoint(A);
   return load_values(A, d_vals, rs_stream(stream));
 }
 
@@ -344,7 +349,7 @@ rs_status rs_spmv_dots(const rs_bsr_s *A, const void *x, int xprec, double *y, c
 }
 
 extern "C" rs_status rs_spmv(rs_bsr A, const double *d_x, double *d_y, void *stream) {
-  if (!A || !d_x || !d_y || d_x == d_y) return RS_E_ARG;
+  if (!A || !d_x || !d_y || d_x == d_y || (((uintptr_t)d_x | (uintptr_t)d_y) & 15)) return RS_E_ARG;
   return rs_spmv_any(A, d_x, 64, d_y, nullptr, rs_stream(stream));
 }
 

@@ -20,6 +20,66 @@
 namespace {
 #include "block4.h"
 
+// Where a decoupling kernel reads block (s, c) of A from.
+//   src7:  the library's 7-slot copy a7 (after rs_bsr_create/rs_bsr_update);
+//   srcu:  the caller's row-major blocks in CSR order through the slot map
+//          pos7 (-1 off the grid: a zero block), for rs_bsr_update_decouple:
+//          the lane that owns slot s also stores the block into a7 and flags
+//          non-finite entries, so the update and the decoupling are one pass.
+struct src7 {
+  const double *a7;
+  int64_t n;
+  __device__ __forceinline__ void diag(int64_t c, double (&M)[4][4]) const { load16(a7 + (3 * n + c) * 16, M); }
+  __device__ __forceinline__ void block(int s, int64_t c, bool, double (&M)[4][4], int &) const {
+    load16(a7 + ((int64_t)s * n + c) * 16, M);
+  }
+  __device__ __forceinline__ void commit(int64_t) const {}
+};
+// The 32 cells of a workgroup (8 lanes each) stage their blocks in LDS;
+// commit() then writes each of the 7 slot planes as one contiguous 4 KB run
+// (one 16-byte store per thread) instead of 16-byte pieces 128 bytes apart.
+// Every thread of the workgroup must call commit().
+struct srcu {
+  const double *vals;
+  const int64_t *pos7;
+  double *a7;
+  int64_t n;
+  __device__ static double (&stage())[7][32][16] {
+    __shared__ double sa[7][32][16];
+    return sa;
+  }
+  __device__ __forceinline__ void diag(int64_t c, double (&M)[4][4]) const { load16(vals + 16 * pos7[3 * n + c], M); }
+  __device__ __forceinline__ void block(int s, int64_t c, bool store, double (&M)[4][4], int &f) const {
+    const int64_t p = pos7[(int64_t)s * n + c];
+    if (p >= 0) {
+      load16(vals + 16 * p, M);
+    } else {
+#pragma unroll
+      for (int e = 0; e < 16; ++e) M[e >> 2][e & 3] = 0.0;
+    }
+    if (store) {
+      double(&sa)[7][32][16] = stage();
+      const int cl = threadIdx.x >> 3;
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        sa[s][cl][e] = M[e >> 2][e & 3];
+        if (!isfinite(M[e >> 2][e & 3])) f |= RSF_NONFINITE;
+      }
+    }
+  }
+  __device__ __forceinline__ void commit(int64_t c0) const {
+    __syncthreads();
+    double(&sa)[7][32][16] = stage();
+    const int cl = threadIdx.x >> 3, part = threadIdx.x & 7;   // 32 cells x 8 double2 per plane
+    if (c0 + cl < n) {
+#pragma unroll
+      for (int s = 0; s < 7; ++s)
+        *(double2 *)(a7 + ((int64_t)s * n + c0 + cl) * 16 + 2 * part) =
+            make_double2(sa[s][cl][2 * part], sa[s][cl][2 * part + 1]);
+    }
+  }
+};
+
 template <class T>
 __device__ __forceinline__ void store_block(T *__restrict__ t7, double *__restrict__ ap7, int s, int64_t n,
                                             int64_t c, const double (&R)[4][4]) {
@@ -61,8 +121,8 @@ __device__ __forceinline__ void store_col0(T *__restrict__ col0, int64_t n, int6
 // ABF, and the two-stage FRS+ABF when FRS is set: row 0 of A_ii and of every
 // block the lane carries (the identity too, which becomes F) is first
 // replaced by the sum of the four rows, in row order.
-template <class T, bool FRS>
-__global__ __launch_bounds__(256) void k_decouple_abf(int64_t n, const double *__restrict__ a7,
+template <class T, bool FRS, class SRC>
+__global__ __launch_bounds__(256) void k_decouple_abf(int64_t n, SRC src,
                                                        T *__restrict__ t7, T *__restrict__ dinv,
                                                        double *__restrict__ ap7, T *__restrict__ col0,
                                                        int *__restrict__ flag) {
@@ -71,9 +131,10 @@ __global__ __launch_bounds__(256) void k_decouple_abf(int64_t n, const double *_
   const int64_t c = valid ? t >> 3 : n - 1;
   const int lane = (int)(t & 7);
   double L[4][4], R[4][4];
-  load16(a7 + (3 * n + c) * 16, L);
+  int fsrc = 0;
+  src.diag(c, L);
   if (lane < 7) {
-    load16(a7 + ((int64_t)lane * n + c) * 16, R);
+    src.block(lane, c, valid, R, fsrc);
   } else {
 #pragma unroll
     for (int r = 0; r < 4; ++r)
@@ -89,6 +150,7 @@ __global__ __launch_bounds__(256) void k_decouple_abf(int64_t n, const double *_
   }
   int f = gje4<4>(L, R);
   if (valid && lane == 0 && f) atomicOr(flag, f);
+  if (fsrc) atomicOr(flag, fsrc);
   if (lane == 3) {      // A~_ii = I exactly
 #pragma unroll
     for (int r = 0; r < 4; ++r)
@@ -106,13 +168,14 @@ __global__ __launch_bounds__(256) void k_decouple_abf(int64_t n, const double *_
       store_block<T>(t7, ap7, lane, n, c, R);
     }
   }
+  src.commit(((int64_t)blockIdx.x * blockDim.x) >> 3);
   store_col0<T>(col0, n, ((int64_t)blockIdx.x * blockDim.x) >> 3, valid, lane, R);
 }
 
 // Quasi-IMPES: w_i solves A_ii^T w_i = e_0; row 0 of each block in row i
 // becomes w_i^T A_ij; rows 1-3 stay; D_i^{-1} = [w_i^T; e_1^T; e_2^T; e_3^T].
-template <class T>
-__global__ __launch_bounds__(256) void k_decouple_qi(int64_t n, const double *__restrict__ a7,
+template <class T, class SRC>
+__global__ __launch_bounds__(256) void k_decouple_qi(int64_t n, SRC src,
                                                       T *__restrict__ t7, T *__restrict__ dinv,
                                                       double *__restrict__ ap7, T *__restrict__ col0,
                                                       int *__restrict__ flag) {
@@ -121,9 +184,10 @@ __global__ __launch_bounds__(256) void k_decouple_qi(int64_t n, const double *__
   const int64_t c = valid ? t >> 3 : n - 1;
   const int lane = (int)(t & 7);
   double L[4][4], w[4][1];
+  int fsrc = 0;
   {
     double Aii[4][4];
-    load16(a7 + (3 * n + c) * 16, Aii);
+    src.diag(c, Aii);
 #pragma unroll
     for (int r = 0; r < 4; ++r)
 #pragma unroll
@@ -132,11 +196,12 @@ __global__ __launch_bounds__(256) void k_decouple_qi(int64_t n, const double *__
 #pragma unroll
   for (int r = 0; r < 4; ++r) w[r][0] = (r == 0) ? 1.0 : 0.0;
   int f = gje4<1>(L, w);
-  if (valid && lane == 0 && f) atomicOr(flag, f);
   double R[4][4];
+  if (valid && lane == 0 && f) atomicOr(flag, f);
   if (lane < 7) {
     double A[4][4];
-    load16(a7 + ((int64_t)lane * n + c) * 16, A);
+    src.block(lane, c, valid, A, fsrc);
+    if (fsrc) atomicOr(flag, fsrc);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       double s = 0.0;
@@ -166,23 +231,27 @@ __global__ __launch_bounds__(256) void k_decouple_qi(int64_t n, const double *__
       store_block<T>(t7, ap7, lane, n, c, R);
     }
   }
+  src.commit(((int64_t)blockIdx.x * blockDim.x) >> 3);
   store_col0<T>(col0, n, ((int64_t)blockIdx.x * blockDim.x) >> 3, valid, lane, R);
 }
 
 // FRS (Eq. decoupled-frs): D_i^{-1} = F (ones in row 0 and on the
 // diagonal): row 0 of every block becomes the sum of its four rows, in row
 // order; rows 1-3 stay.
-template <class T>
-__global__ __launch_bounds__(256) void k_decouple_frs(int64_t n, const double *__restrict__ a7,
+template <class T, class SRC>
+__global__ __launch_bounds__(256) void k_decouple_frs(int64_t n, SRC src,
                                                        T *__restrict__ t7, T *__restrict__ dinv,
-                                                       double *__restrict__ ap7, T *__restrict__ col0) {
+                                                       double *__restrict__ ap7, T *__restrict__ col0,
+                                                       int *__restrict__ flag) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool valid = t < 8 * n;                 // all threads stay for the block-wide col0 store
   const int64_t c = valid ? t >> 3 : n - 1;
   const int lane = (int)(t & 7);
   double R[4][4];
   if (lane < 7) {
-    load16(a7 + ((int64_t)lane * n + c) * 16, R);
+    int fsrc = 0;
+    src.block(lane, c, valid, R, fsrc);
+    if (fsrc) atomicOr(flag, fsrc);
 #pragma unroll
     for (int q = 0; q < 4; ++q) R[0][q] = ((R[0][q] + R[1][q]) + R[2][q]) + R[3][q];
   } else {
@@ -202,16 +271,40 @@ __global__ __launch_bounds__(256) void k_decouple_frs(int64_t n, const double *_
       store_block<T>(t7, ap7, lane, n, c, R);
     }
   }
+  src.commit(((int64_t)blockIdx.x * blockDim.x) >> 3);
   store_col0<T>(col0, n, ((int64_t)blockIdx.x * blockDim.x) >> 3, valid, lane, R);
 }
 
 }  // namespace
 
-extern "C" rs_status rs_decouple(rs_bsr A, int method, int prec, void *stream, rs_dcpl *out) {
+template <class SRC>
+static void launch_decouple(int method, int prec, int64_t n, SRC src, rs_dcpl_s *D, int *fl, hipStream_t s) {
+  const unsigned grid = rs_grid(8 * n);
+  double *ap7 = D->ap7.as<double>();
+#define RS_DC(KERN, T) KERN<<<grid, RS_BLOCK, 0, s>>>(n, src, D->t7.as<T>(), D->dinv.as<T>(), ap7, D->col0.as<T>(), fl)
+  if (method == RS_ABF) {
+    if (prec == 64) RS_DC((k_decouple_abf<double, false, SRC>), double);
+    else RS_DC((k_decouple_abf<float, false, SRC>), float);
+  } else if (method == RS_FRS_ABF) {
+    if (prec == 64) RS_DC((k_decouple_abf<double, true, SRC>), double);
+    else RS_DC((k_decouple_abf<float, true, SRC>), float);
+  } else if (method == RS_QIMPES) {
+    if (prec == 64) RS_DC((k_decouple_qi<double, SRC>), double);
+    else RS_DC((k_decouple_qi<float, SRC>), float);
+  } else {
+    if (prec == 64) RS_DC((k_decouple_frs<double, SRC>), double);
+    else RS_DC((k_decouple_frs<float, SRC>), float);
+  }
+#undef RS_DC
+}
+
+// vals == nullptr: decouple A's current values; else store vals (caller
+// layout) into A and decouple them in the same pass.
+static rs_status decouple_impl(rs_bsr_s *A, const double *vals, int method, int prec, hipStream_t s, rs_dcpl *out) {
   if (!A || !out || method < RS_ABF || method > RS_FRS_ABF || (prec != 32 && prec != 64))
     return RS_E_ARG;
+  if (vals && ((uintptr_t)vals & 15)) return RS_E_ARG;     // block rows are read 16 bytes at a time
   *out = nullptr;
-  hipStream_t s = rs_stream(stream);
   int64_t n = A->g.n;
   size_t es = prec == 64 ? sizeof(double) : sizeof(float);
   rs_dcpl_s *D = new rs_dcpl_s();
@@ -226,25 +319,8 @@ extern "C" rs_status rs_decouple(rs_bsr A, int method, int prec, void *stream, r
     dbuf flag;
     if ((st = flag.alloc(sizeof(int))) != RS_OK) break;
     if (hipMemsetAsync(flag.p, 0, sizeof(int), s) != hipSuccess) { st = RS_E_HIP; break; }
-    unsigned grid = rs_grid(8 * n);
-    const double *a7 = A->a7.as<double>();
-    double *ap7 = D->ap7.as<double>();
-    int *fl = flag.as<int>();
-#define RS_DC(KERN, T, ...) KERN<<<grid, RS_BLOCK, 0, s>>>(n, a7, D->t7.as<T>(), D->dinv.as<T>(), ap7, D->col0.as<T>(), ##__VA_ARGS__)
-    if (method == RS_ABF) {
-      if (prec == 64) RS_DC((k_decouple_abf<double, false>), double, fl);
-      else RS_DC((k_decouple_abf<float, false>), float, fl);
-    } else if (method == RS_FRS_ABF) {
-      if (prec == 64) RS_DC((k_decouple_abf<double, true>), double, fl);
-      else RS_DC((k_decouple_abf<float, true>), float, fl);
-    } else if (method == RS_QIMPES) {
-      if (prec == 64) RS_DC(k_decouple_qi<double>, double, fl);
-      else RS_DC(k_decouple_qi<float>, float, fl);
-    } else {
-      if (prec == 64) RS_DC(k_decouple_frs<double>, double);
-      else RS_DC(k_decouple_frs<float>, float);
-    }
-#undef RS_DC
+    if (vals) launch_decouple(method, prec, n, srcu{vals, A->pos7.as<int64_t>(), A->a7.as<double>(), n}, D, flag.as<int>(), s);
+    else launch_decouple(method, prec, n, src7{A->a7.as<double>(), n}, D, flag.as<int>(), s);
     if (hipGetLastError() != hipSuccess ||
         hipMemcpyAsync(&h, flag.p, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess) { st = RS_E_HIP; break; }
@@ -254,6 +330,17 @@ extern "C" rs_status rs_decouple(rs_bsr A, int method, int prec, void *stream, r
   if (st != RS_OK) { delete D; return st; }
   *out = D;
   return RS_OK;
+}
+
+extern "C" rs_status rs_decouple(rs_bsr A, int method, int prec, void *stream, rs_dcpl *out) {
+  return decouple_impl(A, nullptr, method, prec, rs_stream(stream), out);
+}
+
+extern "C" rs_status rs_bsr_update_decouple(rs_bsr A, const double *d_vals, int method, int prec, void *stream,
+                                            rs_dcpl *out) {
+  if (!A || !d_vals || !out) return RS_E_ARG;
+  rs_bsr_drop_adjoint(A);
+  return decouple_impl(A, d_vals, method, prec, rs_stream(stream), out);
 }
 
 extern "C" void rs_dcpl_destroy(rs_dcpl D) { delete D; }

@@ -76,6 +76,53 @@ __global__ __launch_bounds__(256) void k_ras_in(int nx, int ny, int64_t n, const
   if (row == 0) xpw[p] = xp[c];
 }
 
+// The same per tile of RI x RJ cells of a layer (4 lanes per cell, one
+// workgroup of 4*RI*RJ threads): the results are staged in LDS in the tile's
+// own wavefront order, in which the cells of one anti-diagonal of the tile
+// are consecutive in the layer's wavefront order too, and written back as
+// runs of up to min(RI, RJ) cells instead of one scattered cell per quad.
+constexpr int RI = 16, RJ = 16;
+template <class T>
+__global__ __launch_bounds__(4 * RI * RJ) void k_ras_in_tile(int nx, int ny, int64_t n, const T *__restrict__ rt,
+                                                             const T *__restrict__ col0, const T *__restrict__ xp,
+                                                             const T *__restrict__ dinv2, T *__restrict__ rh,
+                                                             T *__restrict__ xpw) {
+  __shared__ T so[RI * RJ][4];
+  __shared__ T sx[RI * RJ];
+  __shared__ int sab[RI * RJ];
+  const int tx = (nx + RI - 1) / RI, ty = (ny + RJ - 1) / RJ;
+  const int layer = blockIdx.x / (tx * ty), tt = blockIdx.x - layer * (tx * ty);
+  const int i0 = (tt % tx) * RI, j0 = (tt / tx) * RJ;
+  const int ni = min(RI, nx - i0), nj = min(RJ, ny - j0);      // this tile's extent
+  const int64_t nxy = (int64_t)nx * ny;
+  const int tid = threadIdx.x, row = tid & 3, q = tid >> 2;
+  const int a = q % RI, b = q / RI;
+  if (a < ni && b < nj) {
+    const int64_t c = layer * nxy + (int64_t)(j0 + b) * nx + (i0 + a);
+    const int64_t off[7] = {-nxy, -(int64_t)nx, -1, 0, 1, (int64_t)nx, nxy};
+    T col[8], dv[4];
+    ld8v(col0 + c * 32 + 8 * row, col);
+    ld4v(dinv2 + c * 16 + 4 * row, dv);
+    T v = rt[4 * c + row];
+#pragma unroll
+    for (int sl = 0; sl < 7; ++sl) v = v - col[sl] * xp[c + off[sl]];
+    const T o = quad_mv<T>(dv, v);
+    const int w = (int)wf_pos(a, b, ni, nj);                   // tile-local wavefront index
+    so[w][row] = o;
+    if (row == 0) {
+      sx[w] = xp[c];
+      sab[w] = a | (b << 16);
+    }
+  }
+  __syncthreads();
+  if (q < ni * nj) {
+    const int ab = sab[q], aa = ab & 0xffff, bb = ab >> 16;
+    const int64_t p = layer * nxy + wf_pos(i0 + aa, j0 + bb, nx, ny);
+    rh[4 * p + row] = so[q][row];
+    if (row == 0) xpw[p] = sx[q];
+  }
+}
+
 // ---- scaled blocks for the sweeps, per (cell, block row) ---------------------
 // blk[b][p] = D_c^{-1} A~_{c, nb(b)} for b = 0..3: -y, -x, +x, +y (slots 1, 2,
 // 4, 5), at the cell's wavefront position p; FP64 products rounded once.
@@ -796,8 +843,11 @@ rs_status rs_ras_apply_run(rs_cpr_s *M, const T *xp, T *out, hipStream_t s) {
   // rh goes to zt, the forward result (wavefront order) to yv
   T *rh = M->zt.as<T>(), *y = M->yv.as<T>(), *xpw = M->rxp.as<T>();
   const T *blk = M->rblk.as<T>();
-  k_ras_in<T><<<rs_grid(4 * g.n), RS_BLOCK, 0, s>>>(g.nx, g.ny, g.n, M->rt.as<T>(), D->col0.as<T>(), xp,
-                                                    M->dinv2.as<T>(), rh, xpw);
+  {
+    const int64_t tiles = (int64_t)g.nz * ((g.nx + RI - 1) / RI) * ((g.ny + RJ - 1) / RJ);
+    k_ras_in_tile<T><<<(unsigned)tiles, 4 * RI * RJ, 0, s>>>(g.nx, g.ny, g.n, M->rt.as<T>(), D->col0.as<T>(), xp,
+                                                             M->dinv2.as<T>(), rh, xpw);
+  }
   RS_HIP(hipGetLastError());
   const sweep_shape sh = ras_sweep_shape(g.ny);
   // compute lanes (at most 960) + one writer wave

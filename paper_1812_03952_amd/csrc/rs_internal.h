@@ -148,6 +148,7 @@ rs_status rs_spmv_any(const rs_bsr_s *A, const void *x, int xprec, double *y,
 rs_status rs_spmv_dots(const rs_bsr_s *A, const void *x, int xprec, double *y, const double *b_minus,
                        int nd, const double *u, double *part, hipStream_t s);
 unsigned rs_spmv_blocks(const rs_bsr_s *A);
+void rs_bsr_drop_adjoint(rs_bsr_s *A);
 rs_status rs_cpr_apply_any(rs_cpr_s *M, const double *r, void *z, int zprec,
                            hipStream_t s);
 rs_status rs_vcycle_run(rs_cpr_s *M, hipStream_t s);

@@ -68,6 +68,7 @@ def lib():
             "rs_bsr_create": (_i, [_i, _i, _i, _i, _i64, _vp, _vp, _vp, _vp, C.POINTER(_vp)]),
             "rs_bsr_update": (_i, [_vp, _vp, _vp]),
             "rs_decouple": (_i, [_vp, _i, _i, _vp, C.POINTER(_vp)]),
+            "rs_bsr_update_decouple": (_i, [_vp, _vp, _i, _i, _vp, C.POINTER(_vp)]),
             "rs_cpr_setup": (_i, [_vp, _vp, C.POINTER(CprOpts), _vp, C.POINTER(_vp)]),
             "rs_gmres_solve": (_i, [_vp, _vp, _vp, _vp, C.POINTER(GmresOpts), C.POINTER(SolveInfo), _vp]),
             "rs_bicgstab_solve": (_i, [_vp, _vp, _vp, _vp, C.POINTER(BicgstabOpts), C.POINTER(SolveInfo), _vp]),
@@ -219,6 +220,14 @@ def bsr_create(nx, ny, nz, row_ptr, col_idx, vals, stream=None) -> Bsr:
 
 def bsr_update(A: Bsr, vals, stream=None):
     _check(lib().rs_bsr_update(A.h, _ptr(vals, torch.float64, 16 * A.nnzb), _stream(stream)), "rs_bsr_update")
+
+
+def bsr_update_decouple(A: Bsr, vals, method=ABF, prec=64, stream=None) -> Dcpl:
+    """bsr_update(A, vals) and decouple(A, method, prec) in one pass."""
+    h = C.c_void_p()
+    _check(lib().rs_bsr_update_decouple(A.h, _ptr(vals, torch.float64, 16 * A.nnzb), method, prec, _stream(stream),
+                                        C.byref(h)), "rs_bsr_update_decouple")
+    return Dcpl(h, A, method, prec)
 
 
 def decouple(A: Bsr, method=ABF, prec=64, stream=None) -> Dcpl:

@@ -64,6 +64,38 @@ def test_decouple_fp64_bitwise(method, dims):
     assert np.array_equal(dd, dinv)
 
 
+@pytest.mark.parametrize("prec", [64, 32])
+@pytest.mark.parametrize("method", [rs.ABF, rs.QIMPES, rs.FRS, rs.FRS_ABF])
+def test_update_decouple_fused(method, prec):
+    """rs_bsr_update_decouple equals rs_bsr_update then rs_decouple, bitwise:
+    the stored values (through the SpMV) and every decoupled array."""
+    p = _prob((20, 20, 10), sigma=1.5)
+    A = oracle.assemble(p)
+    v2 = A.v * 1.0
+    v2[:, 0, :] *= 1.25                             # new values on the same pattern
+    vals = dev(v2.reshape(-1))
+    B1, B2 = upload(A), upload(A)
+    rs.bsr_update(B1, vals)
+    D1 = rs.decouple(B1, method, prec)
+    D2 = rs.bsr_update_decouple(B2, vals, method, prec)
+    for a, b in zip(rs.dcpl_get(D1), rs.dcpl_get(D2)):
+        assert np.array_equal(a, b)
+    x = dev(np.random.default_rng(3).standard_normal(4 * A.n))
+    y1, y2 = torch.empty_like(x), torch.empty_like(x)
+    rs.spmv(B1, x, y1)
+    rs.spmv(B2, x, y2)
+    assert torch.equal(y1, y2)
+    # errors: non-finite values, misaligned values
+    bad = vals.clone(); bad[17] = float("inf")
+    with pytest.raises(rs.RsError) as e:
+        rs.bsr_update_decouple(B2, bad, method, prec)
+    assert e.value.status == -5
+    buf = torch.zeros(vals.numel() + 1, dtype=torch.float64, device="cuda")
+    buf[1:] = vals
+    with pytest.raises(rs.RsError):
+        rs.bsr_update_decouple(B2, buf[1:], method, prec)
+
+
 def test_decouple_fp32():
     p = _prob((20, 20, 10), sigma=1.5)
     A = oracle.assemble(p)
@@ -283,6 +315,23 @@ def test_zero_guess_ignores_x(solver):
     i1 = solve(B, M, b, x1, opts(zero_guess=1))
     assert i0["return"] == 0 and i1["return"] == 0 and i0["iters"] == i1["iters"]
     assert torch.equal(x0, x1) and i0["relres"] == i1["relres"]
+
+
+def test_vectors_must_be_16_byte_aligned():
+    p = synth.config(0)
+    A = oracle.assemble(p)
+    B = upload(A)
+    M = rs.cpr_setup(B, rs.decouple(B, rs.ABF, 32))
+    N = 4 * A.n
+    buf = torch.zeros(N + 1, dtype=torch.float64, device="cuda")
+    ok = torch.zeros(N, dtype=torch.float64, device="cuda")
+    for call in (lambda: rs.gmres_solve(B, M, buf[1:], ok),
+                 lambda: rs.gmres_solve(B, M, ok, buf[1:]),
+                 lambda: rs.bicgstab_solve(B, M, buf[1:], ok),
+                 lambda: rs.spmv(B, buf[1:], ok)):
+        with pytest.raises(rs.RsError) as e:
+            call()
+        assert e.value.status == -1
 
 
 def test_gmres_deterministic_and_status():

@@ -94,11 +94,27 @@ __global__ __launch_bounds__(256) void k_bcg_reduce_chunks(int nparts, int strid
   if (threadIdx.x == 0) mid[k * nc + c] = sh[0];
 }
 
+// The vector kernels take two consecutive entries per thread and step
+// (16-byte loads; N = 4n is even), which streams markedly faster than one.
+template <class TZ> struct pair_of;
+template <> struct pair_of<double> {
+  __device__ static double2 ld(const double *p, int64_t t) { return ((const double2 *)p)[t]; }
+};
+template <> struct pair_of<float> {
+  __device__ static double2 ld(const float *p, int64_t t) {
+    const float2 f = ((const float2 *)p)[t];
+    return make_double2((double)f.x, (double)f.y);
+  }
+};
+
 // partial ||b||^2
 __global__ __launch_bounds__(256) void k_bcg_norm2(int64_t N, const double *__restrict__ b, double *__restrict__ part) {
   double acc = 0.0;
-  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < N; t += (int64_t)NBLK * blockDim.x)
-    acc = fma(b[t], b[t], acc);
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < (N >> 1); t += (int64_t)NBLK * blockDim.x) {
+    const double2 v = pair_of<double>::ld(b, t);
+    acc = fma(v.x, v.x, acc);
+    acc = fma(v.y, v.y, acc);
+  }
   store_partials<1>(acc, 0.0, part);
 }
 
@@ -124,8 +140,14 @@ __global__ void k_bcg_start(int64_t N, double *__restrict__ p, double *__restric
 __global__ __launch_bounds__(256) void k_bcg_p(int64_t N, const double *__restrict__ r, const double *__restrict__ v,
                                                double *__restrict__ p, const double *__restrict__ S) {
   const double beta = (S[B_RHO] / S[B_RHOP]) * (S[B_ALPHA] / S[B_OMEGA]), omega = S[B_OMEGA];
-  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < N; t += (int64_t)gridDim.x * blockDim.x)
-    p[t] = r[t] + beta * (p[t] - omega * v[t]);
+  double2 *p2 = (double2 *)p;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < (N >> 1); t += (int64_t)gridDim.x * blockDim.x) {
+    const double2 rv = pair_of<double>::ld(r, t), vv = pair_of<double>::ld(v, t);
+    double2 pv = p2[t];
+    pv.x = rv.x + beta * (pv.x - omega * vv.x);
+    pv.y = rv.y + beta * (pv.y - omega * vv.y);
+    p2[t] = pv;
+  }
 }
 
 // alpha = rho / (r^, v);  s = r - alpha v (in place);  partial ||s||^2
@@ -133,10 +155,15 @@ __global__ __launch_bounds__(256) void k_bcg_s(int64_t N, double *__restrict__ r
                                                double *__restrict__ S, double *__restrict__ part) {
   const double alpha = S[B_RHO] / S[B_RV];
   double acc = 0.0;
-  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < N; t += (int64_t)NBLK * blockDim.x) {
-    const double sv = r[t] - alpha * v[t];
-    r[t] = sv;
-    acc = fma(sv, sv, acc);
+  double2 *r2 = (double2 *)r;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < (N >> 1); t += (int64_t)NBLK * blockDim.x) {
+    const double2 vv = pair_of<double>::ld(v, t);
+    double2 sv = r2[t];
+    sv.x = sv.x - alpha * vv.x;
+    sv.y = sv.y - alpha * vv.y;
+    r2[t] = sv;
+    acc = fma(sv.x, sv.x, acc);
+    acc = fma(sv.y, sv.y, acc);
   }
   store_partials<1>(acc, 0.0, part);
   if (blockIdx.x == 0 && threadIdx.x == 0) S[B_ALPHA] = alpha;
@@ -159,12 +186,21 @@ __global__ __launch_bounds__(256) void k_bcg_xr(int64_t N, const TZ *__restrict_
                                                 const double *__restrict__ S, double *__restrict__ part) {
   const double alpha = S[B_ALPHA], omega = S[B_TT] != 0.0 ? S[B_TS] / S[B_TT] : 0.0;
   double a0 = 0.0, a1 = 0.0;
-  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < N; t += (int64_t)NBLK * blockDim.x) {
-    x[t] = x[t] + alpha * (double)ph[t] + omega * (double)sh[t];
-    const double rv = r[t] - omega * tv[t];
-    r[t] = rv;
-    a0 = fma(rh[t], rv, a0);
-    a1 = fma(rv, rv, a1);
+  double2 *x2 = (double2 *)x, *r2 = (double2 *)r;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < (N >> 1); t += (int64_t)NBLK * blockDim.x) {
+    const double2 pp = pair_of<TZ>::ld(ph, t), ss = pair_of<TZ>::ld(sh, t);
+    const double2 tt = pair_of<double>::ld(tv, t), hh = pair_of<double>::ld(rh, t);
+    double2 xv = x2[t], rv = r2[t];
+    xv.x = xv.x + alpha * pp.x + omega * ss.x;
+    xv.y = xv.y + alpha * pp.y + omega * ss.y;
+    rv.x = rv.x - omega * tt.x;
+    rv.y = rv.y - omega * tt.y;
+    x2[t] = xv;
+    r2[t] = rv;
+    a0 = fma(hh.x, rv.x, a0);
+    a0 = fma(hh.y, rv.y, a0);
+    a1 = fma(rv.x, rv.x, a1);
+    a1 = fma(rv.y, rv.y, a1);
   }
   store_partials<2>(a0, a1, part);
 }

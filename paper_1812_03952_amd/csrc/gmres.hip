@@ -5,8 +5,10 @@
 // One Arnoldi step j after z_j = M^{-1} v_j and w = A z_j makes three passes
 // over the basis, each reading every v_i (i <= j) once:
 //   pass 1  h1 = V^T w,  ||w||^2
-//   pass 2  w -= V h1;   h2 = V^T w        (axpy fused with the second dots)
-//   pass 3  w -= V h2;   ||w||^2           (axpy fused with the norm)
+//   pass 2  h2 = V^T (w - V h1)            (w - V h1 in registers only)
+//   pass 3  w = (w - V h1) - V h2;  ||w||^2
+// which is classical Gram-Schmidt applied twice, with the same operations
+// per entry as updating w in place after each pass.
 // followed by one single-thread kernel that forms h = h1 + h2, applies the
 // previous rotations, builds the new one and updates g, and a normalisation
 // v_{j+1} = w / h_{j+1,j} that reads h_{j+1,j} from device memory.  Every
@@ -71,17 +73,26 @@ __global__ __launch_bounds__(256) void k_dots(int64_t N, int K, const double *__
   block_store_partials<MK, double>(acc, K, true, part);
 }
 
-// pass 2 / 3: w -= sum_k h[k] V_k; then part[k] = V_k . w (dots) and part[K] = w . w
-template <int MK, bool DOTS>
+// pass 2 (PASS3 = false): w' = w - sum_k h1[k] V_k formed in registers only,
+//   part[k] = V_k . w', part[K] = w' . w'  (read-only: w is not written)
+// pass 3 (PASS3 = true): w' formed again with the same operations, then
+//   w'' = w' - sum_k h2[k] V_k stored into w, part[0] = w'' . w''
+// Keeping pass 2 read-only saves a vector write per Arnoldi step, and a
+// kernel that both streams several vectors in and one out runs slower
+// than a read-only one; the arithmetic is that of updating w in place.
+template <int MK, bool PASS3>
 __global__ __launch_bounds__(256) void k_axpy_dots(int64_t N, int K, const double *__restrict__ V,
-                                                    const double *__restrict__ h, double *__restrict__ w,
-                                                    double *__restrict__ part) {
+                                                    const double *__restrict__ h1, const double *__restrict__ h2,
+                                                    double *__restrict__ w, double *__restrict__ part) {
   double acc[MK + 1];
 #pragma unroll
   for (int k = 0; k <= MK; ++k) acc[k] = 0.0;
-  double hk[MK];
+  double g1[MK], g2[MK];
 #pragma unroll
-  for (int k = 0; k < MK; ++k) hk[k] = (k < K) ? h[k] : 0.0;
+  for (int k = 0; k < MK; ++k) {
+    g1[k] = (k < K) ? h1[k] : 0.0;
+    g2[k] = (PASS3 && k < K) ? h2[k] : 0.0;
+  }
   const int64_t N2 = N >> 1;
   double2 *w2 = (double2 *)w;
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < N2; t += (int64_t)NBLK * blockDim.x) {
@@ -90,11 +101,17 @@ __global__ __launch_bounds__(256) void k_axpy_dots(int64_t N, int K, const doubl
 #pragma unroll
     for (int k = 0; k < MK; ++k) {
       vk[k] = (k < K) ? ((const double2 *)(V + (int64_t)k * N))[t] : make_double2(0.0, 0.0);
-      wv.x = fma(-hk[k], vk[k].x, wv.x);
-      wv.y = fma(-hk[k], vk[k].y, wv.y);
+      wv.x = fma(-g1[k], vk[k].x, wv.x);
+      wv.y = fma(-g1[k], vk[k].y, wv.y);
     }
-    w2[t] = wv;
-    if (DOTS) {
+    if (PASS3) {
+#pragma unroll
+      for (int k = 0; k < MK; ++k) {
+        wv.x = fma(-g2[k], vk[k].x, wv.x);
+        wv.y = fma(-g2[k], vk[k].y, wv.y);
+      }
+      w2[t] = wv;
+    } else {
 #pragma unroll
       for (int k = 0; k < MK; ++k)
         if (k < K) {
@@ -105,7 +122,7 @@ __global__ __launch_bounds__(256) void k_axpy_dots(int64_t N, int K, const doubl
     acc[MK] = fma(wv.x, wv.x, acc[MK]);
     acc[MK] = fma(wv.y, wv.y, acc[MK]);
   }
-  block_store_partials<MK, double>(acc, DOTS ? K : 0, true, part);
+  block_store_partials<MK, double>(acc, PASS3 ? 0 : K, true, part);
 }
 
 // out[k] = sum over blocks of part[k] in a fixed order, k < K
@@ -240,13 +257,13 @@ static rs_status run_dots(int64_t N, int K, const double *V, const double *w, do
   return RS_OK;
 }
 
-template <bool DOTS>
-static rs_status run_axpy(int64_t N, int K, const double *V, const double *h, double *w, double *part,
-                          double *S, int off, hipStream_t s) {
-  if (K <= 8) k_axpy_dots<8, DOTS><<<NBLK, 256, 0, s>>>(N, K, V, h, w, part);
-  else if (K <= 16) k_axpy_dots<16, DOTS><<<NBLK, 256, 0, s>>>(N, K, V, h, w, part);
-  else k_axpy_dots<32, DOTS><<<NBLK, 256, 0, s>>>(N, K, V, h, w, part);
-  int nout = DOTS ? K + 1 : 1;
+template <bool PASS3>
+static rs_status run_axpy(int64_t N, int K, const double *V, const double *h1, const double *h2, double *w,
+                          double *part, double *S, int off, hipStream_t s) {
+  if (K <= 8) k_axpy_dots<8, PASS3><<<NBLK, 256, 0, s>>>(N, K, V, h1, h2, w, part);
+  else if (K <= 16) k_axpy_dots<16, PASS3><<<NBLK, 256, 0, s>>>(N, K, V, h1, h2, w, part);
+  else k_axpy_dots<32, PASS3><<<NBLK, 256, 0, s>>>(N, K, V, h1, h2, w, part);
+  int nout = PASS3 ? 1 : K + 1;
   k_reduce<<<nout, 256, 0, s>>>(nout, part, S + off);
   RS_HIP(hipGetLastError());
   return RS_OK;
@@ -323,8 +340,8 @@ static rs_status gmres_t(rs_bsr_s *A, rs_cpr_s *M, const double *b, double *x, c
         if ((st = rs_cpr_apply_any(M, vj, zj, sizeof(TZ) == 8 ? 64 : 32, s)) != RS_OK) break;
         if ((st = rs_spmv_any(A, zj, sizeof(TZ) == 8 ? 64 : 32, w, nullptr, s)) != RS_OK) break;
         if ((st = run_dots(N, j + 1, V, w, part, S, S_H1, s)) != RS_OK) break;
-        if ((st = run_axpy<true>(N, j + 1, V, S + S_H1, w, part, S, S_H2, s)) != RS_OK) break;
-        if ((st = run_axpy<false>(N, j + 1, V, S + S_H2, w, part, S, S_NRM, s)) != RS_OK) break;
+        if ((st = run_axpy<false>(N, j + 1, V, S + S_H1, nullptr, w, part, S, S_H2, s)) != RS_OK) break;
+        if ((st = run_axpy<true>(N, j + 1, V, S + S_H1, S + S_H2, w, part, S, S_NRM, s)) != RS_OK) break;
         k_givens<<<1, 64, 0, s>>>(j, S);
         k_scale<<<gN, RS_BLOCK, 0, s>>>(N, w, S, S_HN, 0.0, V + (int64_t)(j + 1) * N);
         if (hipGetLastError() != hipSuccess) { st = RS_E_HIP; break; }

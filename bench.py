@@ -58,9 +58,10 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_spmv7_cfg2_traffic.txt")
 SPMV_SOURCE = os.path.join(ROOT, "paper_1812_03952_amd", "csrc", "bsr.hip")
 
 
-def spmv_traffic():
+def spmv_traffic(cells):
     """HBM bytes per SpMV launch from the committed counter summary, or None
-    when the SpMV source has changed since the counters were taken."""
+    when the SpMV source has changed since the counters were taken or the
+    counters were taken on a grid of another size."""
     import hashlib
     try:
         kv = {}
@@ -69,7 +70,7 @@ def spmv_traffic():
                 k, v = line.split(":", 1)
                 kv[k.strip()] = v.strip()
         cur = hashlib.sha256(open(SPMV_SOURCE, "rb").read()).hexdigest()
-        if kv.get("source_sha256") != cur:
+        if kv.get("source_sha256") != cur or int(kv.get("cells", -1)) != cells:
             return None
         return float(kv["traffic_bytes"])
     except (OSError, KeyError, ValueError):
@@ -216,7 +217,7 @@ def main():
         "spmv": {"ms": spmv_ms, "GB_per_s": achieved, "bytes": spmv_bytes},
         "roofline": {"bound": "hbm", "kernel": "k_spmv7<double,false,0> (y = A x)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": spmv_traffic()},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": spmv_traffic(n)},
     }
     if not args.no_cpu_baseline:
         log("cpu baseline: FP64 oracle, one full solve of the same system (1 thread) ...")

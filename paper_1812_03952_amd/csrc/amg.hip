@@ -176,7 +176,11 @@ __global__ void k_strength_sym(int n, const int32_t *__restrict__ rp, const int3
   state[i] = deg ? ST_UND : ST_ISO;
 }
 
-// A fine-level cell's in-grid flags and neighbours by slot.
+// A fine-level cell's in-grid flags and neighbours by slot.  The kernels on
+// it load every slot's operand unconditionally (from the cell itself where
+// the slot is off-grid or masked out) and select afterwards: a load under a
+// branch is waited for before the next one issues, while unconditional
+// loads are all in flight at once.
 struct cell7 {
   int64_t c;
   bool in[7];
@@ -184,7 +188,8 @@ struct cell7 {
 };
 __device__ __forceinline__ cell7 cell7_of(int64_t c, int nx, int ny, int nz) {
   const int64_t nxy = (int64_t)nx * ny;
-  const int i = (int)(c % nx), j = (int)((c / nx) % ny), k = (int)(c / nxy);
+  const uint32_t cu = (uint32_t)c, t = cu / (uint32_t)nx;   // grids hold fewer than 2^31 cells
+  const int i = (int)(cu - t * (uint32_t)nx), j = (int)(t % (uint32_t)ny), k = (int)(t / (uint32_t)ny);
   cell7 e;
   e.c = c;
   e.in[0] = k > 0; e.in[1] = j > 0; e.in[2] = i > 0; e.in[3] = true;
@@ -238,8 +243,14 @@ __global__ void k_mis_decide(int n, int level, const uint64_t *__restrict__ m2, 
   if (prev && *prev == 0) return;             // *undecided stays 0
   int v = blockIdx.x * blockDim.x + threadIdx.x;
   int left = 0;
-  if (v < n && state[v] == ST_UND) {
-    uint64_t m = m2[v];
+  uint8_t st = ST_ISO;
+  uint64_t m = 0;
+  if (v < n) {
+    st = state[v];
+    m = m2[v];
+    asm volatile("" : "+v"(m));   // both loads issue before the test of st
+  }
+  if (st == ST_UND) {
     if (m == ~0ull) state[v] = ST_OUT;
     else if (m == prio(v, level)) state[v] = ST_ROOT;
     else left = 1;
@@ -332,25 +343,35 @@ __global__ void k_cand(int nc, const int32_t *__restrict__ mptr, const int32_t *
 // The additions happen in the same order either way.
 constexpr int GAL_BLOCK = 128, GAL_CAP = 32;
 
-// Row sources: each(i, f) calls f(col, a) for the entries of fine row i in
-// column order and stops when f returns false.
+// Row sources: each(i, agg, f) calls f(agg[col], a) for the entries of
+// fine row i in column order and stops when f returns false.
 struct rows_csr {
   const int32_t *rp, *ci;
   const double *a;
-  template <class F> __device__ __forceinline__ bool each(int i, F &&f) const {
+  template <class F> __device__ __forceinline__ bool each(int i, const int32_t *__restrict__ agg, F &&f) const {
     for (int p = rp[i]; p < rp[i + 1]; ++p)
-      if (!f(ci[p], a[p])) return false;
+      if (!f(agg[ci[p]], a[p])) return false;
     return true;
   }
 };
 struct rows_7 {
   int nx, ny, nz;
   const double *ap7;
-  template <class F> __device__ __forceinline__ bool each(int i, F &&f) const {
+  template <class F> __device__ __forceinline__ bool each(int i, const int32_t *__restrict__ agg, F &&f) const {
     const int64_t n = (int64_t)nx * ny * nz;
     const cell7 e = cell7_of(i, nx, ny, nz);
+    double a[7];
+    int32_t J[7];
+#pragma unroll
+    for (int sl = 0; sl < 7; ++sl) {           // all 14 loads in flight at once
+      int64_t q = e.in[sl] ? e.nb[sl] : (int64_t)i;
+      asm volatile("" : "+v"(q));
+      a[sl] = ap7[sl * n + i];
+      J[sl] = agg[q];
+    }
+#pragma unroll
     for (int sl = 0; sl < 7; ++sl)
-      if (e.in[sl] && !f((int)e.nb[sl], ap7[sl * n + i])) return false;
+      if (e.in[sl] && !f(J[sl], a[sl])) return false;
     return true;
   }
 };
@@ -361,22 +382,32 @@ __device__ __forceinline__ bool gal_row(int I, const int32_t *__restrict__ mptr,
                                         const R &rows, const int32_t *__restrict__ agg, K key, V val, int cap,
                                         int &m) {
   m = 0;
-  for (int x = mptr[I]; x < mptr[I + 1]; ++x) {
-    const bool ok = rows.each(mem[x], [&](int col, double a) -> bool {
-      const int J = agg[col];
+  int sI = -1;                                   // slot of column I (most entries), once seen
+  const int x0 = mptr[I], x1 = mptr[I + 1];
+  int cur = x0 < x1 ? mem[x0] : 0;
+  for (int x = x0; x < x1; ++x) {
+    const int nxt = mem[x + 1 < x1 ? x + 1 : x];   // the next member's row, one step ahead
+    const bool ok = rows.each(cur, agg, [&](int J, double a) -> bool {
       if (J < 0) return true;
-      int s = 0;
-      while (s < m && key(s) != J) ++s;
-      if (s == m) {
-        if (m == cap) return false;
-        key(m) = J;
-        val(m) = 0.0;
-        ++m;
+      int s;
+      if (J == I && sI >= 0) {
+        s = sI;
+      } else {
+        s = 0;
+        while (s < m && key(s) != J) ++s;
+        if (s == m) {
+          if (m == cap) return false;
+          key(m) = J;
+          val(m) = 0.0;
+          ++m;
+        }
+        if (J == I) sI = s;
       }
       val(s) = val(s) + a;
       return true;
     });
     if (!ok) return false;
+    cur = nxt;
   }
   for (int x = 1; x < m; ++x) {
     int k = key(x);
@@ -883,35 +914,36 @@ __global__ void k_from_f64(int n, const double *__restrict__ a, T *__restrict__ 
 // take the CSR kernels' operations in the same order, reading a cell's
 // entries from the slot planes: a row's CSR entries are exactly its in-grid
 // slots, in slot order.  Strong couplings are a 7-bit mask per cell.
+// One pass over a cell's entries: their copy in the preconditioner's
+// precision (s7, the operator of the fine-level smoother and residual), the
+// l1 diagonal (k_l1diag's operations) and the directed strong couplings,
+// dmask bit s: j = nbr(c, s) influences c (k_strength_dir's test).
 template <class T>
-__global__ void k_l1diag7(int nx, int ny, int nz, const double *__restrict__ ap7, T *__restrict__ d) {
-  const int64_t n = (int64_t)nx * ny * nz, c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= n) return;
-  const cell7 e = cell7_of(c, nx, ny, nz);
-  double sum = 0.0;
-#pragma unroll
-  for (int sl = 0; sl < 7; ++sl)
-    if (e.in[sl]) sum = sum + fabs(ap7[sl * n + c]);
-  const double aii = ap7[3 * n + c];
-  if (sum == 0.0) sum = 1.0;
-  d[c] = (T)(aii < 0.0 ? -sum : sum);
-}
-
-// dmask bit s: j = nbr(c, s) influences c (k_strength_dir's test)
-__global__ void k_strength7_dir(int nx, int ny, int nz, const double *__restrict__ ap7, double theta, double mrs,
-                                uint8_t *__restrict__ dmask) {
+__global__ void k_fine7(int nx, int ny, int nz, const double *__restrict__ ap7, double theta, double mrs,
+                        T *__restrict__ s7, T *__restrict__ d, uint8_t *__restrict__ dmask) {
   const int64_t n = (int64_t)nx * ny * nz, c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= n) return;
   const cell7 e = cell7_of(c, nx, ny, nz);
   double v[7];
-  double aii = 0.0, nm = 0.0, sum = 0.0;
+#pragma unroll
+  for (int sl = 0; sl < 7; ++sl) v[sl] = ap7[sl * n + c];
+#pragma unroll
+  for (int sl = 0; sl < 7; ++sl) s7[sl * n + c] = (T)v[sl];
+  // l1 diagonal: sign of a_ii times the sum of |a_ij| over the row
+  double l1 = 0.0;
+#pragma unroll
+  for (int sl = 0; sl < 7; ++sl)
+    if (e.in[sl]) l1 = l1 + fabs(v[sl]);
+  const double aii = v[3];
+  if (l1 == 0.0) l1 = 1.0;
+  d[c] = (T)(aii < 0.0 ? -l1 : l1);
+  // strength
+  double nm = 0.0, sum = 0.0;
 #pragma unroll
   for (int sl = 0; sl < 7; ++sl) {
-    v[sl] = e.in[sl] ? ap7[sl * n + c] : 0.0;
     if (!e.in[sl]) continue;
     sum = sum + v[sl];
-    if (sl == 3) aii = v[sl];
-    else if (-v[sl] > nm) nm = -v[sl];
+    if (sl != 3 && -v[sl] > nm) nm = -v[sl];
   }
   const bool weak = fabs(sum) > mrs * fabs(aii) || !(nm > 0.0);
   const double thr = theta * nm;
@@ -928,45 +960,74 @@ __global__ void k_strength7_sym(int nx, int ny, int nz, const uint8_t *__restric
   const int64_t n = (int64_t)nx * ny * nz, c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= n) return;
   const cell7 e = cell7_of(c, nx, ny, nz);
-  const uint8_t own = dmask[c];
+  uint8_t d[7];
+#pragma unroll
+  for (int sl = 0; sl < 7; ++sl) d[sl] = dmask[e.in[sl] ? e.nb[sl] : c];
+  const uint8_t own = d[3];
   uint8_t m = 0;
 #pragma unroll
   for (int sl = 0; sl < 7; ++sl)
-    if (e.in[sl] && sl != 3 && (((own >> sl) & 1u) || ((dmask[e.nb[sl]] >> (6 - sl)) & 1u))) m |= (uint8_t)(1u << sl);
+    if (e.in[sl] && sl != 3 && (((own >> sl) & 1u) || ((d[sl] >> (6 - sl)) & 1u))) m |= (uint8_t)(1u << sl);
   smask[c] = m;
   state[c] = m ? ST_UND : ST_ISO;
 }
 
+// Distance-2 MIS round on the grid: m1 as k_mis_m1; m2 and the decision
+// (k_mis_m2 and k_mis_decide) in one kernel that reads only m1 and the cell's
+// own state, so the state is updated in place.  Decided cells skip m2.
 __global__ void k_mis7_m1(int nx, int ny, int nz, int level, const uint8_t *__restrict__ smask,
                           const uint8_t *__restrict__ state, uint64_t *__restrict__ m1, const int *__restrict__ prev) {
   const int64_t n = (int64_t)nx * ny * nz, c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= n || (prev && *prev == 0)) return;
   const cell7 e = cell7_of(c, nx, ny, nz);
   const uint8_t sm = smask[c];
-  uint64_t m = keyof(state[c], (int)c, level);
+  int64_t q[7];
+  uint8_t st[7];
+#pragma unroll
+  for (int sl = 0; sl < 7; ++sl) {
+    q[sl] = ((sm >> sl) & 1u) ? e.nb[sl] : c;
+    int64_t a = q[sl];
+    asm volatile("" : "+v"(a));   // opaque: keeps the load unconditional
+    st[sl] = state[a];
+  }
+  uint64_t m = keyof(st[3], (int)c, level);
 #pragma unroll
   for (int sl = 0; sl < 7; ++sl)
     if ((sm >> sl) & 1u) {
-      const uint64_t kk = keyof(state[e.nb[sl]], (int)e.nb[sl], level);
+      const uint64_t kk = keyof(st[sl], (int)q[sl], level);
       m = kk > m ? kk : m;
     }
   m1[c] = m;
 }
 
-__global__ void k_mis7_m2(int nx, int ny, int nz, const uint8_t *__restrict__ smask, const uint64_t *__restrict__ m1,
-                          uint64_t *__restrict__ m2, const int *__restrict__ prev) {
+__global__ void k_mis7_m2d(int nx, int ny, int nz, int level, const uint8_t *__restrict__ smask,
+                           const uint64_t *__restrict__ m1, uint8_t *__restrict__ state,
+                           int *__restrict__ undecided, const int *__restrict__ prev) {
+  if (prev && *prev == 0) return;             // *undecided stays 0
   const int64_t n = (int64_t)nx * ny * nz, c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= n || (prev && *prev == 0)) return;
-  const cell7 e = cell7_of(c, nx, ny, nz);
-  const uint8_t sm = smask[c];
-  uint64_t m = m1[c];
+  int left = 0;
+  uint8_t st = ST_ISO, sm = 0;
+  if (c < n) {
+    st = state[c];
+    uint32_t t = smask[c];
+    asm volatile("" : "+v"(t));    // both loads issue before the test of st
+    sm = (uint8_t)t;
+  }
+  if (st == ST_UND) {
+    const cell7 e = cell7_of(c, nx, ny, nz);
+    uint64_t v[7];
 #pragma unroll
-  for (int sl = 0; sl < 7; ++sl)
-    if ((sm >> sl) & 1u) {
-      const uint64_t kk = m1[e.nb[sl]];
-      m = kk > m ? kk : m;
-    }
-  m2[c] = m;
+    for (int sl = 0; sl < 7; ++sl) v[sl] = m1[((sm >> sl) & 1u) ? e.nb[sl] : c];
+    uint64_t m = v[3];
+#pragma unroll
+    for (int sl = 0; sl < 7; ++sl)
+      if ((sm >> sl) & 1u) m = v[sl] > m ? v[sl] : m;
+    if (m == ~0ull) state[c] = ST_OUT;
+    else if (m == prio((int)c, level)) state[c] = ST_ROOT;
+    else left = 1;
+  }
+  // one plain store per block that still has undecided vertices
+  if (__syncthreads_or(left) && threadIdx.x == 0) *undecided = 1;
 }
 
 __global__ void k_agg1_7(int nx, int ny, int nz, const uint8_t *__restrict__ smask, const uint8_t *__restrict__ state,
@@ -975,11 +1036,20 @@ __global__ void k_agg1_7(int nx, int ny, int nz, const uint8_t *__restrict__ sma
   if (c >= n) return;
   const cell7 e = cell7_of(c, nx, ny, nz);
   int g = -1;
-  const uint8_t st = state[c], sm = smask[c];
-  if (st == ST_ROOT) g = id[c];
-  else if (st != ST_ISO)
-    for (int sl = 0; sl < 7; ++sl)
-      if (((sm >> sl) & 1u) && state[e.nb[sl]] == ST_ROOT) { g = id[e.nb[sl]]; break; }
+  const uint8_t sm = smask[c];
+  uint8_t st[7];
+  int32_t ids[7];
+#pragma unroll
+  for (int sl = 0; sl < 7; ++sl) {
+    const int64_t q = ((sm >> sl) & 1u) ? e.nb[sl] : c;
+    st[sl] = state[q];
+    ids[sl] = id[q];
+  }
+  if (st[3] == ST_ROOT) g = ids[3];
+  else if (st[3] != ST_ISO)
+#pragma unroll
+    for (int sl = 6; sl >= 0; --sl)               // the first root in slot order wins
+      if (((sm >> sl) & 1u) && st[sl] == ST_ROOT) g = ids[sl];
   agg1[c] = g;
 }
 
@@ -989,15 +1059,23 @@ __global__ void k_agg2_7(int nx, int ny, int nz, const uint8_t *__restrict__ sma
   const int64_t n = (int64_t)nx * ny * nz, c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= n) return;
   const cell7 e = cell7_of(c, nx, ny, nz);
-  int g = agg1[c];
+  const uint8_t sm = smask[c];
+  int32_t ags[7];
+  double ws[7];
+#pragma unroll
+  for (int sl = 0; sl < 7; ++sl) {
+    ags[sl] = agg1[((sm >> sl) & 1u) ? e.nb[sl] : c];
+    ws[sl] = ap7[sl * n + c];
+  }
+  int g = ags[3];
   if (g < 0 && state[c] != ST_ISO) {
-    const uint8_t sm = smask[c];
     double bw = -1.0;
+#pragma unroll
     for (int sl = 0; sl < 7; ++sl) {
       if (!((sm >> sl) & 1u)) continue;
-      const int ag = agg1[e.nb[sl]];
+      const int ag = ags[sl];
       if (ag < 0) continue;
-      const double w = fabs(ap7[sl * n + c]);
+      const double w = fabs(ws[sl]);
       if (w > bw || (w == bw && ag < g)) { bw = w; g = ag; }
     }
     if (g < 0) atomicOr(bad, 1);     // cannot happen for a maximal distance-2 set
@@ -1072,6 +1150,8 @@ rs_status rs_amg_build(rs_cpr_s *M, hipStream_t s) {
       size_t es = prec == 64 ? sizeof(double) : sizeof(float);
       RS_TRY(L->s7.alloc(es * 7 * (size_t)n));
       RS_TRY(L->y.alloc(es * ((size_t)n + 1)));
+    }
+    if (l == 0 && !st7) {
       if (prec == 64) k_cast7<double><<<rs_grid(7 * (int64_t)n), RS_BLOCK, 0, s>>>(7 * (int64_t)n, M->D->ap7.as<double>(), L->s7.as<double>());
       else k_cast7<float><<<rs_grid(7 * (int64_t)n), RS_BLOCK, 0, s>>>(7 * (int64_t)n, M->D->ap7.as<double>(), L->s7.as<float>());
       RS_HIP(hipGetLastError());
@@ -1079,9 +1159,15 @@ rs_status rs_amg_build(rs_cpr_s *M, hipStream_t s) {
     RS_TRY(L->agg.alloc(sizeof(int32_t) * (n + 1)));
     const grid3 &g = M->A->g;
     const double *ap7 = M->D->ap7.as<double>();
+    dbuf dir;
     if (st7) {
-      if (prec == 64) k_l1diag7<double><<<rs_grid(n), RS_BLOCK, 0, s>>>(g.nx, g.ny, g.nz, ap7, L->dl1.as<double>());
-      else k_l1diag7<float><<<rs_grid(n), RS_BLOCK, 0, s>>>(g.nx, g.ny, g.nz, ap7, L->dl1.as<float>());
+      RS_TRY(dir.alloc(n));
+      if (prec == 64)
+        k_fine7<double><<<rs_grid(n), RS_BLOCK, 0, s>>>(g.nx, g.ny, g.nz, ap7, o.theta, o.max_row_sum,
+                                                        L->s7.as<double>(), L->dl1.as<double>(), dir.as<uint8_t>());
+      else
+        k_fine7<float><<<rs_grid(n), RS_BLOCK, 0, s>>>(g.nx, g.ny, g.nz, ap7, o.theta, o.max_row_sum,
+                                                       L->s7.as<float>(), L->dl1.as<float>(), dir.as<uint8_t>());
     } else {
       if (prec == 64) k_l1diag<double><<<rs_grid(n), RS_BLOCK, 0, s>>>(n, L->rp.as<int32_t>(), L->ci.as<int32_t>(), L->a.as<double>(), L->dl1.as<double>());
       else k_l1diag<float><<<rs_grid(n), RS_BLOCK, 0, s>>>(n, L->rp.as<int32_t>(), L->ci.as<int32_t>(), L->a.as<double>(), L->dl1.as<float>());
@@ -1091,13 +1177,14 @@ rs_status rs_amg_build(rs_cpr_s *M, hipStream_t s) {
     RS_HIP(hipMemsetAsync(L->agg.p, 0xff, sizeof(int32_t) * (n + 1), s));
     if (last) break;
     // strength: per CSR entry, or a 7-bit mask per cell on the fine level
-    dbuf dir, strong, state, m1, m2, und;
-    RS_TRY(dir.alloc(st7 ? n : L->nnz)); RS_TRY(strong.alloc(st7 ? n : L->nnz)); RS_TRY(state.alloc(n));
-    RS_TRY(m1.alloc(sizeof(uint64_t) * n)); RS_TRY(m2.alloc(sizeof(uint64_t) * n));
+    dbuf strong, state, m1, m2, und;
+    if (!st7) RS_TRY(dir.alloc(L->nnz));
+    RS_TRY(strong.alloc(st7 ? n : L->nnz)); RS_TRY(state.alloc(n));
+    RS_TRY(m1.alloc(sizeof(uint64_t) * n));
+    if (!st7) RS_TRY(m2.alloc(sizeof(uint64_t) * n));
     RS_TRY(und.alloc(sizeof(int) * MIS_BATCH));
     const int32_t *rp = L->rp.as<int32_t>(), *ci = L->ci.as<int32_t>();
     if (st7) {
-      k_strength7_dir<<<rs_grid(n), RS_BLOCK, 0, s>>>(g.nx, g.ny, g.nz, ap7, o.theta, o.max_row_sum, dir.as<uint8_t>());
       k_strength7_sym<<<rs_grid(n), RS_BLOCK, 0, s>>>(g.nx, g.ny, g.nz, dir.as<uint8_t>(), strong.as<uint8_t>(),
                                                       state.as<uint8_t>());
     } else {
@@ -1115,16 +1202,16 @@ rs_status rs_amg_build(rs_cpr_s *M, hipStream_t s) {
         if (st7) {
           k_mis7_m1<<<rs_grid(n), RS_BLOCK, 0, s>>>(g.nx, g.ny, g.nz, l, strong.as<uint8_t>(), state.as<uint8_t>(),
                                                     m1.as<uint64_t>(), prev);
-          k_mis7_m2<<<rs_grid(n), RS_BLOCK, 0, s>>>(g.nx, g.ny, g.nz, strong.as<uint8_t>(), m1.as<uint64_t>(),
-                                                    m2.as<uint64_t>(), prev);
+          k_mis7_m2d<<<rs_grid(n), RS_BLOCK, 0, s>>>(g.nx, g.ny, g.nz, l, strong.as<uint8_t>(), m1.as<uint64_t>(),
+                                                     state.as<uint8_t>(), und.as<int>() + b, prev);
         } else {
           k_mis_m1<<<rs_grid(n), RS_BLOCK, 0, s>>>(n, l, rp, ci, strong.as<uint8_t>(), state.as<uint8_t>(),
                                                    m1.as<uint64_t>(), prev);
           k_mis_m2<<<rs_grid(n), RS_BLOCK, 0, s>>>(n, rp, ci, strong.as<uint8_t>(), m1.as<uint64_t>(),
                                                    m2.as<uint64_t>(), prev);
+          k_mis_decide<<<rs_grid(n), RS_BLOCK, 0, s>>>(n, l, m2.as<uint64_t>(), state.as<uint8_t>(),
+                                                       und.as<int>() + b, prev);
         }
-        k_mis_decide<<<rs_grid(n), RS_BLOCK, 0, s>>>(n, l, m2.as<uint64_t>(), state.as<uint8_t>(),
-                                                     und.as<int>() + b, prev);
       }
       RS_HIP(hipGetLastError());
       int h = 0;

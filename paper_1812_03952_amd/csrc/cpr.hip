@@ -87,15 +87,23 @@ template <class T> __device__ __forceinline__ T ldin(const double *p) { return (
 template <class T>
 __global__ __launch_bounds__(256) void k_cpr_in(int64_t n, const T *__restrict__ dinv,
                                                  const double *__restrict__ r, T *__restrict__ rt,
-                                                 T *__restrict__ bp) {
+                                                 T *__restrict__ bp, const double *__restrict__ hs,
+                                                 double *__restrict__ vout) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= 4 * n) return;
   int64_t c = t >> 2;
   int row = (int)(t & 3);
   const T *d = dinv + c * 16 + 4 * row;
+  // hs: the input is r / *hs (a Krylov vector before its normalisation),
+  // which also goes to vout
+  const double h = hs ? *hs : 1.0;
   T s = 0;
 #pragma unroll
-  for (int m = 0; m < 4; ++m) s = fma(d[m], (T)r[4 * c + m], s);
+  for (int m = 0; m < 4; ++m) {
+    const double rv = hs ? r[4 * c + m] / h : r[4 * c + m];
+    s = fma(d[m], (T)rv, s);
+  }
+  if (hs) vout[t] = r[t] / h;
   rt[t] = s;
   if (row == 0) bp[c] = s;
 }
@@ -323,12 +331,14 @@ static rs_status second_stage(rs_cpr_s *M, const T *xp, T *z, hipStream_t s) {
 }
 
 template <class T>
-static rs_status cpr_apply_t(rs_cpr_s *M, const double *r, T *z, hipStream_t s) {
+static rs_status cpr_apply_t(rs_cpr_s *M, const double *r, T *z, hipStream_t s, const double *hs = nullptr,
+                             double *vout = nullptr) {
   const rs_bsr_s *A = M->A;
   const grid3 &g = A->g;
   int64_t n = g.n;
   amg_level *L0 = M->lev[0];
-  k_cpr_in<T><<<rs_grid(4 * n), RS_BLOCK, 0, s>>>(n, M->D->dinv.as<T>(), r, M->rt.as<T>(), L0->b.as<T>());
+  k_cpr_in<T><<<rs_grid(4 * n), RS_BLOCK, 0, s>>>(n, M->D->dinv.as<T>(), r, M->rt.as<T>(), L0->b.as<T>(), hs,
+                                                 vout);
   RS_HIP(hipGetLastError());
   if (M->o.stages == 3) {
     T *y = M->fy.as<T>();
@@ -349,6 +359,13 @@ static rs_status cpr_apply_t(rs_cpr_s *M, const double *r, T *z, hipStream_t s) 
 rs_status rs_cpr_apply_any(rs_cpr_s *M, const double *r, void *z, int zprec, hipStream_t s) {
   if (zprec != M->prec) return RS_E_ARG;
   return M->prec == 64 ? cpr_apply_t<double>(M, r, (double *)z, s) : cpr_apply_t<float>(M, r, (float *)z, s);
+}
+
+rs_status rs_cpr_apply_scaled(rs_cpr_s *M, const double *w, const double *d_h, double *v, void *z, int zprec,
+                              hipStream_t s) {
+  if (zprec != M->prec || !d_h || !v) return RS_E_ARG;
+  return M->prec == 64 ? cpr_apply_t<double>(M, w, (double *)z, s, d_h, v)
+                       : cpr_apply_t<float>(M, w, (float *)z, s, d_h, v);
 }
 
 extern "C" rs_status rs_cpr_apply(rs_cpr M, const double *d_r, double *d_z, void *stream) {

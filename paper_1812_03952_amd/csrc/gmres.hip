@@ -337,13 +337,15 @@ static rs_status gmres_t(rs_bsr_s *A, rs_cpr_s *M, const double *b, double *x, c
       for (int j = 0; j < m; ++j) {
         double *vj = V + (int64_t)j * N;
         TZ *zj = Z + (int64_t)j * N;
-        if ((st = rs_cpr_apply_any(M, vj, zj, sizeof(TZ) == 8 ? 64 : 32, s)) != RS_OK) break;
+        // V_j = w / h_{j,j-1} is formed by the preconditioner's first pass
+        if ((st = j == 0 ? rs_cpr_apply_any(M, vj, zj, sizeof(TZ) == 8 ? 64 : 32, s)
+                         : rs_cpr_apply_scaled(M, w, S + S_HN, vj, zj, sizeof(TZ) == 8 ? 64 : 32, s)) != RS_OK)
+          break;
         if ((st = rs_spmv_any(A, zj, sizeof(TZ) == 8 ? 64 : 32, w, nullptr, s)) != RS_OK) break;
         if ((st = run_dots(N, j + 1, V, w, part, S, S_H1, s)) != RS_OK) break;
         if ((st = run_axpy<false>(N, j + 1, V, S + S_H1, nullptr, w, part, S, S_H2, s)) != RS_OK) break;
         if ((st = run_axpy<true>(N, j + 1, V, S + S_H1, S + S_H2, w, part, S, S_NRM, s)) != RS_OK) break;
         k_givens<<<1, 64, 0, s>>>(j, S);
-        k_scale<<<gN, RS_BLOCK, 0, s>>>(N, w, S, S_HN, 0.0, V + (int64_t)(j + 1) * N);
         if (hipGetLastError() != hipSuccess) { st = RS_E_HIP; break; }
         ++iters;
         k = j + 1;

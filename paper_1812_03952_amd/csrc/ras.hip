@@ -195,30 +195,32 @@ template <class T> __device__ __forceinline__ void order_after(int &idx, T tok) 
 }
 
 // ---- factorisation, per layer: D_c = A~_cc - sum_{q in {c-nx, c-1}} A~_cq D_q^{-1} A~_qc
-// One thread per line (line j = tid + LW*u) computes in FP64; the D^{-1}
-// block of the cell before in x stays in the thread's registers, that of the
-// cell before in y comes from an LDS slot per line (a barrier after the reads
-// of a level and one after its writes).  Same operation order as the
-// definition; D^{-1} blocks are rounded to the stored precision before the
-// next cells use them.  As in the sweeps, compute threads only load (the five
-// blocks of the next P levels stay in flight in registers, issued
-// unconditionally at clamped addresses over a level count padded to a
-// multiple of P) and one writer wave stores: while level lambda is computed
-// it copies the D^{-1} blocks of level lambda-1 from LDS to global memory.
-template <class T> struct ras_spre { T a[5][16]; };   // A~_cc, A~_{c,c-nx}, A~_{c,c-1}, A~_{c-nx,c}, A~_{c-1,c}
-
-template <class T, int U, int P>
-__global__ __launch_bounds__(320) void k_ras_setup(int nx, int ny, int64_t n, int LW, const T *__restrict__ t7,
-                                                   T *__restrict__ dinv2, int *__restrict__ flag) {
+// A quad of lanes per cell, lane r holding block row r, computes in FP64
+// (lines j = q + LW*u for quad q, U passes).  Each lane forms row r of
+// T = D_q^{-1} A~_qc and of the Schur update; the other rows of A~_qc and T
+// come from the quad by DPP.  The inverse is the Gauss-Jordan elimination
+// with row pivoting of the single-thread form, element by element the same
+// operations: the quad tracks the row permutation instead of moving rows
+// (every lane takes the same pivot decision from the broadcast column), and
+// each lane scales the pivot row, read from its lane, itself.  D^{-1} blocks
+// are rounded to the stored precision before the next cells use them; both
+// neighbours' D^{-1} (cell before in x: same line, previous level; before in
+// y: line j-1) come from an LDS slot per line, with a barrier after the
+// reads of a level and one after its writes.  One writer wave copies the
+// D^{-1} blocks of level lambda-1 from LDS to global memory while level
+// lambda is computed.
+template <class T, int U>
+__global__ __launch_bounds__(1024) void k_ras_setup(int nx, int ny, int64_t n, int LW, const T *__restrict__ t7,
+                                                    T *__restrict__ dinv2, int *__restrict__ flag) {
 #pragma clang fp contract(off)
   extern __shared__ __align__(16) unsigned char smem[];
   T *ring = (T *)smem;                                  // [ny][16]
   const int tid = threadIdx.x;
-  const bool compute = tid < LW;                        // wave-uniform (LW is a multiple of 64)
+  const bool compute = tid < 4 * LW;                    // wave-uniform (4 LW is a multiple of 64)
   const int64_t nxy = (int64_t)nx * ny, cl = nxy * blockIdx.x;
-  const int Lv = nx + ny - 1, Lpad = (Lv + P - 1) / P * P;
+  const int Lv = nx + ny - 1;
   if (!compute) {
-    const int w = tid - LW;
+    const int w = tid - 4 * LW;
     auto write_level = [&](int m) {
       if (m < 0 || m >= Lv) return;
       const int jlo = max(0, m - nx + 1), jhi = min(ny - 1, m);
@@ -229,107 +231,150 @@ __global__ __launch_bounds__(320) void k_ras_setup(int nx, int ny, int64_t n, in
           *(typename vec4t<T>::type *)(dinv2 + c * 16 + e) = *(const typename vec4t<T>::type *)(ring + j * 16 + e);
       }
     };
-    for (int lam = 0; lam < Lpad; ++lam) {
+    for (int lam = 0; lam < Lv; ++lam) {
       write_level(lam - 1);
       __syncthreads();
       __syncthreads();
     }
-    write_level(Lpad - 1);
+    write_level(Lv - 1);
     return;
   }
+  const int q = tid >> 2, r = tid & 3, wq = (tid & 63) & ~3;
   const T *Ad = t7 + 3 * n * 16, *Ay = t7 + 1 * n * 16, *Ax = t7 + 2 * n * 16;
   const T *Upx = t7 + 4 * n * 16, *Upy = t7 + 5 * n * 16;
-  ras_spre<T> R[P][U];
-  auto load = [&](int lam, ras_spre<T> &p, int u, T tok) {
-    int j = tid + LW * u;
-    order_after(j, tok);
-    j = min(j, ny - 1);
+  // this lane's row of A~_cc, A~_{c,c-nx}, A~_{c,c-1}, A~_{c-nx,c}, A~_{c-1,c}:
+  // one level ahead with one pass, loaded at use with several
+  T pre[5][4];
+  auto load = [&](int lam, int u, T (&p)[5][4]) {
+    const int j = min(q + LW * u, ny - 1);
     const int i = min(max(lam - j, 0), nx - 1);
     const int64_t c = cl + (int64_t)j * nx + i;
     const int64_t qy = j > 0 ? c - nx : c, qx = i > 0 ? c - 1 : c;
-    const T *src[5] = {Ad + c * 16, Ay + c * 16, Ax + c * 16, Upy + qy * 16, Upx + qx * 16};
-#pragma unroll
-    for (int b = 0; b < 5; ++b)
-#pragma unroll
-      for (int e = 0; e < 16; e += 4) {
-        T v4[4];
-        ld4v(src[b] + e, v4);
-#pragma unroll
-        for (int m = 0; m < 4; ++m) p.a[b][e + m] = v4[m];
-      }
+    ld4v(Ad + c * 16 + 4 * r, p[0]);
+    ld4v(Ay + c * 16 + 4 * r, p[1]);
+    ld4v(Ax + c * 16 + 4 * r, p[2]);
+    ld4v(Upy + qy * 16 + 4 * r, p[3]);
+    ld4v(Upx + qx * 16 + 4 * r, p[4]);
   };
-  T own[U][16];
-#pragma unroll
-  for (int u = 0; u < U; ++u)
-#pragma unroll
-    for (int e = 0; e < 16; ++e) own[u][e] = (T)0;
-#pragma unroll
-  for (int d = 0; d < P; ++d)
-#pragma unroll
-    for (int u = 0; u < U; ++u) load(d, R[d][u], u, (T)0);
+  if constexpr (U == 1) load(0, 0, pre);
   int bad = 0;
-  for (int lam0 = 0; lam0 < Lpad; lam0 += P) {
+  T orow[U][4];
+  int ok[U];
+  for (int lam = 0; lam < Lv; ++lam) {
 #pragma unroll
-    for (int d = 0; d < P; ++d) {
-      const int lam = lam0 + d;
+    for (int u = 0; u < U; ++u) {
+      const int j = q + LW * u, i = lam - j;
+      T a[5][4];
+      if constexpr (U == 1) {
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int j = tid + LW * u, i = lam - j;
-        if (j < ny && i >= 0 && i < nx) {
-          double D[4][4];
+        for (int b = 0; b < 5; ++b)
 #pragma unroll
-          for (int e = 0; e < 16; ++e) D[e >> 2][e & 3] = (double)R[d][u].a[0][e];
+          for (int cc = 0; cc < 4; ++cc) a[b][cc] = pre[b][cc];
+      } else {
+        load(lam, u, a);
+      }
+      if (j < ny && i >= 0 && i < nx) {                 // the same for the four lanes of the cell
+        double Lr[4];
 #pragma unroll
-          for (int s = 0; s < 2; ++s) {                 // -y, then -x (ascending column)
-            if (s == 0 ? j == 0 : i == 0) continue;
-            double Dq[4][4], Aqc[4][4], Acq[4][4], T1[4][4];
+        for (int cc = 0; cc < 4; ++cc) Lr[cc] = (double)a[0][cc];
 #pragma unroll
-            for (int e = 0; e < 16; ++e) {
-              Dq[e >> 2][e & 3] = (double)(s == 0 ? ring[(j - 1) * 16 + e] : own[u][e]);
-              Aqc[e >> 2][e & 3] = (double)R[d][u].a[s == 0 ? 3 : 4][e];
-              Acq[e >> 2][e & 3] = (double)R[d][u].a[s == 0 ? 1 : 2][e];
-            }
+        for (int s = 0; s < 2; ++s) {                   // -y, then -x (ascending column)
+          if (s == 0 ? j == 0 : i == 0) continue;
+          const T *dq = ring + (s == 0 ? j - 1 : j) * 16 + 4 * r;
+          double Aqc[4][4], t[4], Tm[4][4];
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
-#pragma unroll
-              for (int cc = 0; cc < 4; ++cc) {
-                double v = 0.0;
-#pragma unroll
-                for (int m = 0; m < 4; ++m) v = v + Dq[r][m] * Aqc[m][cc];
-                T1[r][cc] = v;
-              }
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-#pragma unroll
-              for (int cc = 0; cc < 4; ++cc) {
-                double v = 0.0;
-#pragma unroll
-                for (int m = 0; m < 4; ++m) v = v + Acq[r][m] * T1[m][cc];
-                D[r][cc] = D[r][cc] - v;
-              }
+          for (int cc = 0; cc < 4; ++cc) {
+            const T v = a[s == 0 ? 3 : 4][cc];
+            Aqc[0][cc] = (double)qb<0>(v); Aqc[1][cc] = (double)qb<1>(v);
+            Aqc[2][cc] = (double)qb<2>(v); Aqc[3][cc] = (double)qb<3>(v);
           }
-          double Rm[4][4];
 #pragma unroll
-          for (int r = 0; r < 4; ++r)
+          for (int cc = 0; cc < 4; ++cc) {
+            double v = 0.0;
 #pragma unroll
-            for (int cc = 0; cc < 4; ++cc) Rm[r][cc] = (r == cc) ? 1.0 : 0.0;
-          bad |= gje4<4>(D, Rm);
+            for (int m = 0; m < 4; ++m) v = v + (double)dq[m] * Aqc[m][cc];
+            t[cc] = v;
+          }
 #pragma unroll
-          for (int e = 0; e < 16; ++e) own[u][e] = (T)Rm[e >> 2][e & 3];
+          for (int cc = 0; cc < 4; ++cc) {
+            Tm[0][cc] = qb<0>(t[cc]); Tm[1][cc] = qb<1>(t[cc]);
+            Tm[2][cc] = qb<2>(t[cc]); Tm[3][cc] = qb<3>(t[cc]);
+          }
+#pragma unroll
+          for (int cc = 0; cc < 4; ++cc) {
+            double v = 0.0;
+#pragma unroll
+            for (int m = 0; m < 4; ++m) v = v + (double)a[s == 0 ? 1 : 2][m] * Tm[m][cc];
+            Lr[cc] = Lr[cc] - v;
+          }
         }
-        load(lam + P, R[d][u], u, own[u][0]);
-      }
-      __syncthreads();                                  // level lam-1 reads done
+        // Gauss-Jordan on [L | I]; lane `mine` holds logical row `mine`
+        double Rr[4];
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int j = tid + LW * u, i = lam - j;
-        if (j < ny && i >= 0 && i < nx) {
+        for (int cc = 0; cc < 4; ++cc) Rr[cc] = cc == r ? 1.0 : 0.0;
+        double rmax = 0.0;
 #pragma unroll
-          for (int e = 0; e < 16; ++e) ring[j * 16 + e] = own[u][e];
+        for (int cc = 0; cc < 4; ++cc) rmax = fmax(rmax, fabs(Lr[cc]));
+        const double amax = fmax(fmax(fmax(fmax(0.0, qb<0>(rmax)), qb<1>(rmax)), qb<2>(rmax)), qb<3>(rmax));
+        int mine = r;
+        if (!isfinite(amax)) {
+          bad |= RSF_NONFINITE;
+        } else {
+          unsigned perm = 0xE4u;                        // 2 bits per logical row k: its lane
+          auto lane_of = [&](int k) { return (int)((perm >> (2 * k)) & 3u); };
+#pragma unroll
+          for (int p = 0; p < 4; ++p) {
+            const double c0 = qb<0>(Lr[p]), c1 = qb<1>(Lr[p]), c2 = qb<2>(Lr[p]), c3 = qb<3>(Lr[p]);
+            auto col = [&](int l) { return l == 0 ? c0 : (l == 1 ? c1 : (l == 2 ? c2 : c3)); };
+            int piv = p;
+            double best = fabs(col(lane_of(p)));
+#pragma unroll
+            for (int k = p + 1; k < 4; ++k)
+              if (fabs(col(lane_of(k))) > best) { best = fabs(col(lane_of(k))); piv = k; }
+            const unsigned lp = (unsigned)lane_of(p), lq = (unsigned)lane_of(piv);
+            perm = (perm & ~(3u << (2 * p)) & ~(3u << (2 * piv))) | (lq << (2 * p)) | (lp << (2 * piv));
+            mine = mine == p ? piv : (mine == piv ? p : mine);
+            const int src = wq + (int)lq;
+            double pv = col((int)lq);
+            if (fabs(pv) <= 1e-300 || fabs(pv) <= 1e-14 * amax) { bad |= RSF_SINGULAR; pv = 1.0; }
+            const double inv = 1.0 / pv;
+            double pL[4], pR[4];
+#pragma unroll
+            for (int cc = p + 1; cc < 4; ++cc) pL[cc] = __shfl(Lr[cc], src, 64) * inv;
+#pragma unroll
+            for (int cc = 0; cc < 4; ++cc) pR[cc] = __shfl(Rr[cc], src, 64) * inv;
+            if (mine == p) {
+#pragma unroll
+              for (int cc = p + 1; cc < 4; ++cc) Lr[cc] = pL[cc];
+#pragma unroll
+              for (int cc = 0; cc < 4; ++cc) Rr[cc] = pR[cc];
+              Lr[p] = 1.0;
+            } else {
+              const double f = Lr[p];
+#pragma unroll
+              for (int cc = p + 1; cc < 4; ++cc) Lr[cc] = Lr[cc] - f * pL[cc];
+#pragma unroll
+              for (int cc = 0; cc < 4; ++cc) Rr[cc] = Rr[cc] - f * pR[cc];
+              Lr[p] = 0.0;
+            }
+          }
         }
+#pragma unroll
+        for (int cc = 0; cc < 4; ++cc) orow[u][cc] = (T)Rr[cc];
+        ok[u] = mine;
       }
-      __syncthreads();                                  // level lam visible
+      if constexpr (U == 1) load(lam + 1, 0, pre);
     }
+    __syncthreads();                                    // level lam-1 reads done
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int j = q + LW * u, i = lam - j;
+      if (j < ny && i >= 0 && i < nx) {
+#pragma unroll
+        for (int cc = 0; cc < 4; ++cc) ring[j * 16 + 4 * ok[u] + cc] = orow[u][cc];
+      }
+    }
+    __syncthreads();                                    // level lam visible
   }
   if (bad) atomicOr(flag, bad);
 }
@@ -796,10 +841,11 @@ rs_status rs_ras_check_shape(const grid3 &g, int prec) {
 rs_status rs_ras_setup_run(rs_cpr_s *M, int *flag, hipStream_t s) {
   const grid3 &g = M->A->g;
   RS_TRY(rs_ras_check_shape(g, M->prec));
-  // compute threads: one per line, at most 256 lines per pass; one writer wave
+  // a quad of lanes per line, at most 240 lines per pass (U passes), and
+  // one writer wave: at most 1024 threads
   int u = 1;
-  while ((g.ny + u - 1) / u > 256) u *= 2;            // 1, 2 or 4
-  const int lw = ((g.ny + u - 1) / u + 63) / 64 * 64;
+  while ((g.ny + u - 1) / u > 240) u *= 2;            // 1, 2 or 4
+  const int lw = ((g.ny + u - 1) / u + 15) / 16 * 16;
   size_t es = M->prec == 64 ? sizeof(double) : sizeof(float);
   size_t lds = es * 16 * (size_t)g.ny;
   RS_TRY(M->rblk.alloc(es * 4 * 16 * (size_t)g.n));
@@ -817,12 +863,12 @@ rs_status rs_ras_setup_run(rs_cpr_s *M, int *flag, hipStream_t s) {
     RS_HIP(hipMemsetAsync(M->rctl.p, 0, sizeof(int) * 4, s));
     M->repoch = 0;
   }
-#define RS_RSET(T, UU, PP)                                                                            \
-  k_ras_setup<T, UU, PP><<<g.nz, lw + 64, lds, s>>>(g.nx, g.ny, g.n, lw, M->D->t7.as<T>(), M->dinv2.as<T>(), flag)
+#define RS_RSET(T, UU)                                                                                \
+  k_ras_setup<T, UU><<<g.nz, 4 * lw + 64, lds, s>>>(g.nx, g.ny, g.n, lw, M->D->t7.as<T>(), M->dinv2.as<T>(), flag)
   if (M->prec == 64) {
-    if (u == 1) RS_RSET(double, 1, 1); else RS_RSET(double, 2, 1);
+    if (u == 1) RS_RSET(double, 1); else RS_RSET(double, 2);
   } else {
-    if (u == 1) RS_RSET(float, 1, 1); else if (u == 2) RS_RSET(float, 2, 1); else RS_RSET(float, 4, 1);
+    if (u == 1) RS_RSET(float, 1); else if (u == 2) RS_RSET(float, 2); else RS_RSET(float, 4);
   }
 #undef RS_RSET
   RS_HIP(hipGetLastError());

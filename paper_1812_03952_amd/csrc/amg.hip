@@ -33,6 +33,7 @@
 //              recompute it); on the fine level, which keeps the 7-point
 //              pattern and is stored by stencil slot, it is formed once.
 #include "rs_internal.h"
+#include <type_traits>
 #include <math.h>
 
 namespace {
@@ -357,22 +358,31 @@ struct rows_csr {
 struct rows_7 {
   int nx, ny, nz;
   const double *ap7;
-  template <class F> __device__ __forceinline__ bool each(int i, const int32_t *__restrict__ agg, F &&f) const {
+  // a row's entries and their columns' aggregates, all 14 loads issued at once
+  struct row { double a[7]; int32_t J[7]; unsigned in; };
+  __device__ __forceinline__ void fetch(int i, const int32_t *__restrict__ agg, row &w) const {
     const int64_t n = (int64_t)nx * ny * nz;
     const cell7 e = cell7_of(i, nx, ny, nz);
-    double a[7];
-    int32_t J[7];
+    w.in = 0;
 #pragma unroll
-    for (int sl = 0; sl < 7; ++sl) {           // all 14 loads in flight at once
+    for (int sl = 0; sl < 7; ++sl) {
       int64_t q = e.in[sl] ? e.nb[sl] : (int64_t)i;
       asm volatile("" : "+v"(q));
-      a[sl] = ap7[sl * n + i];
-      J[sl] = agg[q];
+      w.a[sl] = ap7[sl * n + i];
+      w.J[sl] = agg[q];
+      w.in |= e.in[sl] ? (1u << sl) : 0u;
     }
+  }
+  template <class F> __device__ __forceinline__ bool apply(const row &w, F &&f) const {
 #pragma unroll
     for (int sl = 0; sl < 7; ++sl)
-      if (e.in[sl] && !f(J[sl], a[sl])) return false;
+      if (((w.in >> sl) & 1u) && !f(w.J[sl], w.a[sl])) return false;
     return true;
+  }
+  template <class F> __device__ __forceinline__ bool each(int i, const int32_t *__restrict__ agg, F &&f) const {
+    row w;
+    fetch(i, agg, w);
+    return apply(w, f);
   }
 };
 
@@ -384,10 +394,7 @@ __device__ __forceinline__ bool gal_row(int I, const int32_t *__restrict__ mptr,
   m = 0;
   int sI = -1;                                   // slot of column I (most entries), once seen
   const int x0 = mptr[I], x1 = mptr[I + 1];
-  int cur = x0 < x1 ? mem[x0] : 0;
-  for (int x = x0; x < x1; ++x) {
-    const int nxt = mem[x + 1 < x1 ? x + 1 : x];   // the next member's row, one step ahead
-    const bool ok = rows.each(cur, agg, [&](int J, double a) -> bool {
+  auto add = [&](int J, double a) -> bool {
       if (J < 0) return true;
       int s;
       if (J == I && sI >= 0) {
@@ -405,9 +412,26 @@ __device__ __forceinline__ bool gal_row(int I, const int32_t *__restrict__ mptr,
       }
       val(s) = val(s) + a;
       return true;
-    });
-    if (!ok) return false;
-    cur = nxt;
+  };
+  if constexpr (std::is_same<R, rows_7>::value) {
+    // the next member's entries are in flight while a member's are added
+    // (member indices two ahead; clamped, so that every fetch is issued
+    // unconditionally)
+    if (x0 < x1) {
+      typename R::row cur, nxt;
+      int inx = mem[x0 + 1 < x1 ? x0 + 1 : x0];
+      rows.fetch(mem[x0], agg, cur);
+      for (int x = x0; x < x1; ++x) {
+        const int in2 = mem[x + 2 < x1 ? x + 2 : x1 - 1];
+        rows.fetch(inx, agg, nxt);
+        if (!rows.apply(cur, add)) return false;
+        cur = nxt;
+        inx = in2;
+      }
+    }
+  } else {
+    for (int x = x0; x < x1; ++x)
+      if (!rows.each(mem[x], agg, add)) return false;
   }
   for (int x = 1; x < m; ++x) {
     int k = key(x);

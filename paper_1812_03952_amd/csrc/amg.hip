@@ -810,10 +810,25 @@ __global__ __launch_bounds__(256) void k_vc_pre(int n, const int32_t *__restrict
                                                  T *__restrict__ r) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  const int p0 = rp[i], p1 = rp[i + 1];
   T s = 0;
-  for (int p = rp[i]; p < rp[i + 1]; ++p) {
-    int j = ci[p];
-    s = fma(a[p], b[j] / d[j], s);
+  // eight entries at a time: their columns, then the gathers, all issued at
+  // once (positions past the row read its first entry and are not added)
+  for (int pb = p0; pb < p1; pb += 8) {
+    int j[8];
+    T av[8], bj[8], dj[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      int p = pb + k < p1 ? pb + k : p0;
+      asm volatile("" : "+v"(p));
+      j[k] = ci[p];
+      av[k] = a[p];
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) { bj[k] = b[j[k]]; dj[k] = d[j[k]]; }
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      if (pb + k < p1) s = fma(av[k], bj[k] / dj[k], s);
   }
   r[i] = b[i] - s;
 }
@@ -823,8 +838,23 @@ __global__ void k_vc_restrict(int nc, const int32_t *__restrict__ mptr, const in
                               const T *__restrict__ r, T *__restrict__ bc) {
   int I = blockIdx.x * blockDim.x + threadIdx.x;
   if (I >= nc) return;
+  const int x0 = mptr[I], x1 = mptr[I + 1];
   T s = 0;
-  for (int x = mptr[I]; x < mptr[I + 1]; ++x) s = s + r[mem[x]];
+  for (int xb = x0; xb < x1; xb += 8) {          // eight members at a time, as in k_vc_pre
+    int m[8];
+    T rv[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      int x = xb + k < x1 ? xb + k : x0;
+      asm volatile("" : "+v"(x));
+      m[k] = mem[x];
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) rv[k] = r[m[k]];
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      if (xb + k < x1) s = s + rv[k];
+  }
   bc[I] = s;
 }
 
@@ -838,17 +868,39 @@ __global__ __launch_bounds__(256) void k_vc_post(int n, const int32_t *__restric
                                                   T *__restrict__ x) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  const int p0 = rp[i], p1 = rp[i + 1];
+  const T bi = b[i], di = d[i];
+  const int gi = agg[i];
   T s = 0;
-  for (int p = rp[i]; p < rp[i + 1]; ++p) {
-    int j = ci[p];
-    T yj = b[j] / d[j];
-    int g = agg[j];
-    if (g >= 0) yj = yj + xc[g];
-    s = fma(a[p], yj, s);
+  for (int pb = p0; pb < p1; pb += 8) {          // eight entries at a time, as in k_vc_pre
+    int j[8], g[8];
+    T av[8], bj[8], dj[8], xq[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      int p = pb + k < p1 ? pb + k : p0;
+      asm volatile("" : "+v"(p));
+      j[k] = ci[p];
+      av[k] = a[p];
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) { bj[k] = b[j[k]]; dj[k] = d[j[k]]; g[k] = agg[j[k]]; }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      int gc = g[k] >= 0 ? g[k] : 0;
+      asm volatile("" : "+v"(gc));
+      xq[k] = xc[gc];
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      if (pb + k >= p1) continue;
+      T yj = bj[k] / dj[k];
+      if (g[k] >= 0) yj = yj + xq[k];
+      s = fma(av[k], yj, s);
+    }
   }
-  T yi = b[i] / d[i];
-  if (agg[i] >= 0) yi = yi + xc[agg[i]];
-  x[i] = yi + (b[i] - s) / d[i];
+  T yi = bi / di;
+  if (gi >= 0) yi = yi + xc[gi];
+  x[i] = yi + (bi - s) / di;
 }
 
 
@@ -895,17 +947,26 @@ __global__ __launch_bounds__(256) void k_vc_post7(int n, int nx, int nxy, const 
                                                    const T *__restrict__ xc, T *__restrict__ x) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  T s = 0;
+  // two batches of loads, each issued at once: the neighbours' y and
+  // aggregates, then their coarse corrections (index 0 for no aggregate)
+  T yq[7], xq[7];
+  int g[7];
 #pragma unroll
   for (int k = 0; k < 7; ++k) {
-    int q = nbr7(i, k, n, nx, nxy);
-    T yq = y[q];
-    int g = agg[q];
-    if (g >= 0) yq = yq + xc[g];
-    s = fma(s7[(int64_t)k * n + i], yq, s);
+    const int q = nbr7(i, k, n, nx, nxy);
+    yq[k] = y[q];
+    g[k] = agg[q];
   }
-  T yi = y[i];
-  if (agg[i] >= 0) yi = yi + xc[agg[i]];
+#pragma unroll
+  for (int k = 0; k < 7; ++k) {
+    int gc = g[k] >= 0 ? g[k] : 0;
+    asm volatile("" : "+v"(gc));
+    xq[k] = xc[gc];
+  }
+  T s = 0;
+#pragma unroll
+  for (int k = 0; k < 7; ++k) s = fma(s7[(int64_t)k * n + i], g[k] >= 0 ? yq[k] + xq[k] : yq[k], s);
+  const T yi = g[3] >= 0 ? yq[3] + xq[3] : yq[3];     // slot 3 is the cell itself
   x[i] = yi + (b[i] - s) / d[i];
 }
 

@@ -473,7 +473,20 @@ __global__ void k_galerkin_copy(int nc, const int32_t *__restrict__ off, const i
   int I = blockIdx.x * blockDim.x + threadIdx.x;
   if (I >= nc) return;
   int b = off[I], o = crp[I], m = crp[I + 1] - crp[I];
-  for (int s = 0; s < m; ++s) { cci[o + s] = skey[b + s]; ca[o + s] = sval[b + s]; }
+  for (int sb = 0; sb < m; sb += 8) {            // eight entries' loads in flight at once
+    int32_t kv[8];
+    double vv[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      int e = sb + k < m ? sb + k : 0;
+      asm volatile("" : "+v"(e));
+      kv[k] = skey[b + e];
+      vv[k] = sval[b + e];
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      if (sb + k < m) { cci[o + sb + k] = kv[k]; ca[o + sb + k] = vv[k]; }
+  }
 }
 
 __global__ void k_set_last(int32_t *__restrict__ p, int64_t idx, const int32_t *__restrict__ v) { p[idx] = *v; }

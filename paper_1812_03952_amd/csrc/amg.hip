@@ -215,14 +215,18 @@ __global__ void k_mis_m1(int n, int level, const int32_t *__restrict__ rp, const
                          uint64_t *__restrict__ m1, const int *__restrict__ prev) {
   int u = blockIdx.x * blockDim.x + threadIdx.x;
   if (u >= n || (prev && *prev == 0)) return;
-  uint64_t m = keyof(state[u], u, level);
+  const uint8_t su = state[u];
+  uint64_t m = keyof(su, u, level);
+  bool und = su == ST_UND;
   for (int p = rp[u]; p < rp[u + 1]; ++p)
     if (strong[p]) {
       int w = ci[p];
-      uint64_t k = keyof(state[w], w, level);
+      const uint8_t sw = state[w];
+      uint64_t k = keyof(sw, w, level);
       m = k > m ? k : m;
+      und = und || sw == ST_UND;
     }
-  m1[u] = m;
+  if (und) m1[u] = m;                            // as in k_mis7_m1
 }
 
 __global__ void k_mis_m2(int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
@@ -1089,13 +1093,18 @@ __global__ void k_mis7_m1(int nx, int ny, int nz, int level, const uint8_t *__re
     st[sl] = state[a];
   }
   uint64_t m = keyof(st[3], (int)c, level);
+  bool und = st[3] == ST_UND;
 #pragma unroll
   for (int sl = 0; sl < 7; ++sl)
     if ((sm >> sl) & 1u) {
       const uint64_t kk = keyof(st[sl], (int)q[sl], level);
       m = kk > m ? kk : m;
+      und = und || st[sl] == ST_UND;
     }
-  m1[c] = m;
+  // m1 is read only at undecided vertices and their strong neighbours, so a
+  // vertex with no undecided one in its closed neighbourhood (strength is
+  // symmetric) skips the store
+  if (und) m1[c] = m;
 }
 
 __global__ void k_mis7_m2d(int nx, int ny, int nz, int level, const uint8_t *__restrict__ smask,

@@ -214,11 +214,11 @@ __global__ void k_zero(int64_t N, double *__restrict__ x) {
 
 template <class TZ>
 __global__ void k_update_x(int64_t N, int k, const TZ *__restrict__ Z, const double *__restrict__ S,
-                           double *__restrict__ x) {
+                           double *__restrict__ x, int x_zero) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= N) return;
   const double *y = S + S_Y;
-  double v = x[t];
+  double v = x_zero ? 0.0 : x[t];                // x_zero: x = 0, not yet written
   for (int i = 0; i < k; ++i) v = fma(y[i], (double)Z[(int64_t)i * N + t], v);
   x[t] = v;
 }
@@ -312,11 +312,12 @@ static rs_status gmres_t(rs_bsr_s *A, rs_cpr_s *M, const double *b, double *x, c
       break;
     }
     bool zero_start = o.zero_guess != 0;
+    bool x_zero = false;                         // x = 0 is implied, not stored
     for (;;) {
       double beta;
       if (zero_start) {
         // x0 = 0: r0 = b, ||r0|| = ||b||, V_0 = b / ||b|| (the k_scale below)
-        k_zero<<<gN, RS_BLOCK, 0, s>>>(N, x);
+        x_zero = true;
         beta = bnorm;
       } else {
         // r = b - A x into V_0
@@ -357,9 +358,11 @@ static rs_status gmres_t(rs_bsr_s *A, rs_cpr_s *M, const double *b, double *x, c
       }
       if (st != RS_OK) break;
       k_backsolve<<<1, 64, 0, s>>>(k, S);
-      k_update_x<TZ><<<gN, RS_BLOCK, 0, s>>>(N, k, Z, S, x);
+      k_update_x<TZ><<<gN, RS_BLOCK, 0, s>>>(N, k, Z, S, x, x_zero ? 1 : 0);
+      x_zero = false;
       if (hipGetLastError() != hipSuccess) { st = RS_E_HIP; break; }
     }
+    if (x_zero) k_zero<<<gN, RS_BLOCK, 0, s>>>(N, x);   // stopped before any update
     est = (bnorm > 0.0) ? est / bnorm : 0.0;
   } while (0);
   if (st == RS_OK || st == RS_NOT_CONVERGED) {

@@ -330,7 +330,11 @@ static rs_status gmres_t(rs_bsr_s *A, rs_cpr_s *M, const double *b, double *x, c
       if (!isfinite(beta)) { st = RS_E_NONFINITE; break; }
       if (beta <= o.rtol * bnorm) { st = RS_OK; break; }
       if (iters >= o.maxit) { st = RS_NOT_CONVERGED; break; }
-      k_scale<<<gN, RS_BLOCK, 0, s>>>(N, zero_start ? b : V, S, -1, beta, V);
+      // V_0 = r0 / beta: from x0 = 0 (r0 = b) the preconditioner's first pass
+      // forms it (with beta from S_BETA); a restart's residual is in V_0
+      // itself and is scaled in place
+      const bool v0_fused = zero_start;
+      if (!v0_fused) k_scale<<<gN, RS_BLOCK, 0, s>>>(N, V, S, -1, beta, V);
       zero_start = false;
       k_init_cycle<<<1, 128, 0, s>>>(S, beta);
       ++cycles;
@@ -339,8 +343,10 @@ static rs_status gmres_t(rs_bsr_s *A, rs_cpr_s *M, const double *b, double *x, c
         double *vj = V + (int64_t)j * N;
         TZ *zj = Z + (int64_t)j * N;
         // V_j = w / h_{j,j-1} is formed by the preconditioner's first pass
-        if ((st = j == 0 ? rs_cpr_apply_any(M, vj, zj, sizeof(TZ) == 8 ? 64 : 32, s)
-                         : rs_cpr_apply_scaled(M, w, S + S_HN, vj, zj, sizeof(TZ) == 8 ? 64 : 32, s)) != RS_OK)
+        const int zp = sizeof(TZ) == 8 ? 64 : 32;
+        if ((st = j > 0     ? rs_cpr_apply_scaled(M, w, S + S_HN, vj, zj, zp, s)
+                  : v0_fused ? rs_cpr_apply_scaled(M, b, S + S_BETA, vj, zj, zp, s)
+                             : rs_cpr_apply_any(M, vj, zj, zp, s)) != RS_OK)
           break;
         if ((st = rs_spmv_any(A, zj, sizeof(TZ) == 8 ? 64 : 32, w, nullptr, s)) != RS_OK) break;
         if ((st = run_dots(N, j + 1, V, w, part, S, S_H1, s)) != RS_OK) break;

@@ -603,14 +603,22 @@ __global__ __launch_bounds__(320) void k_ras_fwd1(int nx, int ny, int nz, int S,
     const int w = tid - LW, nw = blockDim.x - LW;
     bool failed = false;
     // ghost line j0-1 for local level m (cell i = m) goes to gh[m % 32]; the
-    // writer fetches 16 levels at a time (64 lanes: level offset, block row),
-    // 16 levels ahead of their use, so the neighbour's words are normally
-    // published by then and one load latency covers 16 levels
-    auto fetch16 = [&](int m16) {
+    // writer loads 16 levels at a time (64 lanes: level offset, block row),
+    // issued 16 levels ahead of their use and checked one level before it,
+    // so the neighbour's words are normally published by the time they are
+    // loaded and the load latency is hidden behind 15 levels; a word not yet
+    // published is polled
+    auto issue16 = [&](int m16, uint64_t &slot) {
+      const int m = m16 + (w >> 2), r = w & 3;
+      if (s == 0 || w >= 64 || m >= nx) return;
+      slot = __hip_atomic_load(xw + ras_xword(k, s - 1, S, nx, m) + r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    };
+    auto finish16 = [&](int m16, uint64_t slot) {
       const int m = m16 + (w >> 2), r = w & 3;
       if (s == 0 || w >= 64 || m >= nx) return;
       float v;
-      if (!ras_get(xw + ras_xword(k, s - 1, S, nx, m) + r, tag, v, failed)) atomicOr(&ctl[2], 1);
+      if ((uint32_t)(slot >> 32) == tag) v = __uint_as_float((uint32_t)slot);
+      else if (!ras_get(xw + ras_xword(k, s - 1, S, nx, m) + r, tag, v, failed)) atomicOr(&ctl[2], 1);
       gh[m & 31][r] = v;
     };
     // own last line j1-1 at local level m (cell i = m + j0 - (j1-1)), buffer m&1
@@ -620,12 +628,15 @@ __global__ __launch_bounds__(320) void k_ras_fwd1(int nx, int ny, int nz, int S,
       if (i < 0 || i >= nx) return;
       ras_put(xw + ras_xword(k, s, S, nx, i) + w, ring[(m & 1) * RS * 4 + (j1 - j0) * 4 + w], tag);
     };
-    fetch16(0);
+    uint64_t pend = 0;
+    issue16(0, pend);
+    finish16(0, pend);
     __syncthreads();
     for (int m = 0; m < Lpad; ++m) {
+      if ((m & 15) == 0) issue16(m + 16, pend);
       ras_write_strip<true>(j0 + m - 1, nx, ny, j0, j1, cl, ring + ((m + 1) & 1) * RS * 4, y, w, nw);
       publish(m - 1);
-      if ((m & 15) == 0) fetch16(m + 16);
+      if ((m & 15) == 15) finish16(m + 1, pend);        // levels m+1 .. m+16
       __syncthreads();
     }
     ras_write_strip<true>(j0 + Lpad - 1, nx, ny, j0, j1, cl, ring + ((Lpad + 1) & 1) * RS * 4, y, w, nw);
@@ -720,13 +731,20 @@ __global__ __launch_bounds__(320) void k_ras_bwd1(int nx, int ny, int nz, int S,
     const int w = tid - LW, nw = blockDim.x - LW;
     bool failed = false;
     // ghost line j1 for step m (cell i = ltop - m - (j1-1)) goes to gh[m % 32],
-    // fetched 16 steps at a time, 16 steps ahead (as in the forward sweep)
-    auto fetch16 = [&](int m16) {
+    // loaded 16 steps at a time as in the forward sweep
+    auto issue16 = [&](int m16, uint64_t &slot) {
+      const int m = m16 + (w >> 2), r = w & 3;
+      const int i = ltop - m - (j1 - 1);
+      if (s == S - 1 || w >= 64 || i < 0 || i >= nx) return;
+      slot = __hip_atomic_load(xw + ras_xword(k, s + 1, S, nx, i) + r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    };
+    auto finish16 = [&](int m16, uint64_t slot) {
       const int m = m16 + (w >> 2), r = w & 3;
       const int i = ltop - m - (j1 - 1);
       if (s == S - 1 || w >= 64 || i < 0 || i >= nx) return;
       float v;
-      if (!ras_get(xw + ras_xword(k, s + 1, S, nx, i) + r, tag, v, failed)) atomicOr(&ctl[2], 1);
+      if ((uint32_t)(slot >> 32) == tag) v = __uint_as_float((uint32_t)slot);
+      else if (!ras_get(xw + ras_xword(k, s + 1, S, nx, i) + r, tag, v, failed)) atomicOr(&ctl[2], 1);
       gh[m & 31][r] = v;
     };
     // own first line j0 at step m (cell i = ltop - m - j0), buffer m&1, slot 1
@@ -736,12 +754,15 @@ __global__ __launch_bounds__(320) void k_ras_bwd1(int nx, int ny, int nz, int S,
       if (i < 0 || i >= nx) return;
       ras_put(xw + ras_xword(k, s, S, nx, i) + w, ring[(m & 1) * RS * 4 + 4 + w], tag);
     };
-    fetch16(0);
+    uint64_t pend = 0;
+    issue16(0, pend);
+    finish16(0, pend);
     __syncthreads();
     for (int m = 0; m < Lpad; ++m) {
+      if ((m & 15) == 0) issue16(m + 16, pend);
       if (m >= 1) ras_write_strip<false>(ltop - m + 1, nx, ny, j0, j1, cl, oring + ((m + 1) & 1) * RS * 4, out, w, nw);
       publish(m - 1);
-      if ((m & 15) == 0) fetch16(m + 16);
+      if ((m & 15) == 15) finish16(m + 1, pend);        // steps m+1 .. m+16
       __syncthreads();
     }
     ras_write_strip<false>(ltop - Lpad + 1, nx, ny, j0, j1, cl, oring + ((Lpad + 1) & 1) * RS * 4, out, w, nw);

@@ -604,10 +604,10 @@ __global__ __launch_bounds__(320) void k_ras_fwd1(int nx, int ny, int nz, int S,
     bool failed = false;
     // ghost line j0-1 for local level m (cell i = m) goes to gh[m % 32]; the
     // writer loads 16 levels at a time (64 lanes: level offset, block row),
-    // issued 16 levels ahead of their use and checked one level before it,
-    // so the neighbour's words are normally published by the time they are
-    // loaded and the load latency is hidden behind 15 levels; a word not yet
-    // published is polled
+    // issued 8 levels before the first of them is needed and checked one
+    // level before it, so the neighbour's words are normally published by
+    // the time they are loaded and the load latency is hidden behind 7
+    // levels; a word not yet published is polled
     auto issue16 = [&](int m16, uint64_t &slot) {
       const int m = m16 + (w >> 2), r = w & 3;
       if (s == 0 || w >= 64 || m >= nx) return;
@@ -633,7 +633,7 @@ __global__ __launch_bounds__(320) void k_ras_fwd1(int nx, int ny, int nz, int S,
     finish16(0, pend);
     __syncthreads();
     for (int m = 0; m < Lpad; ++m) {
-      if ((m & 15) == 0) issue16(m + 16, pend);
+      if ((m & 15) == 8) issue16(m + 8, pend);          // the next batch, 8 levels ahead
       ras_write_strip<true>(j0 + m - 1, nx, ny, j0, j1, cl, ring + ((m + 1) & 1) * RS * 4, y, w, nw);
       publish(m - 1);
       if ((m & 15) == 15) finish16(m + 1, pend);        // levels m+1 .. m+16
@@ -759,7 +759,7 @@ __global__ __launch_bounds__(320) void k_ras_bwd1(int nx, int ny, int nz, int S,
     finish16(0, pend);
     __syncthreads();
     for (int m = 0; m < Lpad; ++m) {
-      if ((m & 15) == 0) issue16(m + 16, pend);
+      if ((m & 15) == 8) issue16(m + 8, pend);          // the next batch, 8 levels ahead
       if (m >= 1) ras_write_strip<false>(ltop - m + 1, nx, ny, j0, j1, cl, oring + ((m + 1) & 1) * RS * 4, out, w, nw);
       publish(m - 1);
       if ((m & 15) == 15) finish16(m + 1, pend);        // steps m+1 .. m+16

@@ -84,13 +84,16 @@ __global__ void k_bj_setup(int64_t n, const T *__restrict__ t7, T *__restrict__ 
 template <class T> __device__ __forceinline__ T ldin(const double *p) { return (T)*p; }
 
 // r~ = D^{-1} r; the pressure right-hand side b_p = r~[:,0].  Four lanes per cell.
+// With `halt` set, the kernel does nothing when *halt is nonzero (a pass
+// enqueued before the solver knew whether it would be needed).
 template <class T>
 __global__ __launch_bounds__(256) void k_cpr_in(int64_t n, const T *__restrict__ dinv,
                                                  const double *__restrict__ r, T *__restrict__ rt,
                                                  T *__restrict__ bp, const double *__restrict__ hs,
-                                                 double *__restrict__ vout) {
+                                                 double *__restrict__ vout, const double *__restrict__ halt) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= 4 * n) return;
+  if (halt && *halt != 0.0) return;
   int64_t c = t >> 2;
   int row = (int)(t & 3);
   const T *d = dinv + c * 16 + 4 * row;
@@ -330,16 +333,23 @@ static rs_status second_stage(rs_cpr_s *M, const T *xp, T *z, hipStream_t s) {
   return RS_OK;
 }
 
+// The first pass of the CPR apply: r~ = D^{-1} r into M->rt and b_p.
 template <class T>
-static rs_status cpr_apply_t(rs_cpr_s *M, const double *r, T *z, hipStream_t s, const double *hs = nullptr,
-                             double *vout = nullptr) {
-  const rs_bsr_s *A = M->A;
-  const grid3 &g = A->g;
+static rs_status cpr_in_t(rs_cpr_s *M, const double *r, hipStream_t s, const double *hs, double *vout,
+                          const double *halt) {
+  int64_t n = M->A->g.n;
+  k_cpr_in<T><<<rs_grid(4 * n), RS_BLOCK, 0, s>>>(n, M->D->dinv.as<T>(), r, M->rt.as<T>(), M->lev[0]->b.as<T>(),
+                                                 hs, vout, halt);
+  RS_HIP(hipGetLastError());
+  return RS_OK;
+}
+
+// The rest of the CPR apply, from M->rt and b_p to z.
+template <class T>
+static rs_status cpr_rest_t(rs_cpr_s *M, T *z, hipStream_t s) {
+  const grid3 &g = M->A->g;
   int64_t n = g.n;
   amg_level *L0 = M->lev[0];
-  k_cpr_in<T><<<rs_grid(4 * n), RS_BLOCK, 0, s>>>(n, M->D->dinv.as<T>(), r, M->rt.as<T>(), L0->b.as<T>(), hs,
-                                                 vout);
-  RS_HIP(hipGetLastError());
   if (M->o.stages == 3) {
     T *y = M->fy.as<T>();
     RS_TRY(second_stage<T>(M, M->fzero.as<T>() + g.nxy, y, s));
@@ -356,16 +366,26 @@ static rs_status cpr_apply_t(rs_cpr_s *M, const double *r, T *z, hipStream_t s, 
   return RS_OK;
 }
 
+template <class T>
+static rs_status cpr_apply_t(rs_cpr_s *M, const double *r, T *z, hipStream_t s) {
+  RS_TRY(cpr_in_t<T>(M, r, s, nullptr, nullptr, nullptr));
+  return cpr_rest_t<T>(M, z, s);
+}
+
 rs_status rs_cpr_apply_any(rs_cpr_s *M, const double *r, void *z, int zprec, hipStream_t s) {
   if (zprec != M->prec) return RS_E_ARG;
   return M->prec == 64 ? cpr_apply_t<double>(M, r, (double *)z, s) : cpr_apply_t<float>(M, r, (float *)z, s);
 }
 
-rs_status rs_cpr_apply_scaled(rs_cpr_s *M, const double *w, const double *d_h, double *v, void *z, int zprec,
-                              hipStream_t s) {
-  if (zprec != M->prec || !d_h || !v) return RS_E_ARG;
-  return M->prec == 64 ? cpr_apply_t<double>(M, w, (double *)z, s, d_h, v)
-                       : cpr_apply_t<float>(M, w, (float *)z, s, d_h, v);
+rs_status rs_cpr_apply_in(rs_cpr_s *M, const double *w, const double *d_h, double *v, const double *d_halt,
+                          hipStream_t s) {
+  if (!d_h || !v) return RS_E_ARG;
+  return M->prec == 64 ? cpr_in_t<double>(M, w, s, d_h, v, d_halt) : cpr_in_t<float>(M, w, s, d_h, v, d_halt);
+}
+
+rs_status rs_cpr_apply_rest(rs_cpr_s *M, void *z, int zprec, hipStream_t s) {
+  if (zprec != M->prec) return RS_E_ARG;
+  return M->prec == 64 ? cpr_rest_t<double>(M, (double *)z, s) : cpr_rest_t<float>(M, (float *)z, s);
 }
 
 extern "C" rs_status rs_cpr_apply(rs_cpr M, const double *d_r, double *d_z, void *stream) {

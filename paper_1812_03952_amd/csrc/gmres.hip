@@ -148,7 +148,7 @@ enum {
   S_NRM = 128,         // ||w||^2 after pass 3
   S_HN = 129,          // h_{j+1,j}
   S_BETA = 130,        // norm of the residual at the cycle start
-  S_STAT = 132,        // [0] |g_{j+1}|, [1] breakdown flag, [2] reserved
+  S_STAT = 132,        // [0] |g_{j+1}|, [1] breakdown flag, [2] halt flag
   S_G = 136,           // 65: rotated rhs g
   S_CS = 208,          // 64
   S_SN = 272,          // 64
@@ -157,7 +157,9 @@ enum {
   S_TOTAL = 400 + 65 * 64
 };
 
-__global__ void k_givens(int j, double *__restrict__ S) {
+// tol: the stopping bound on |g_{j+1}|; S_STAT[2] = 1 when the solve stops
+// after this step (converged, broken down or not finite), else 0
+__global__ void k_givens(int j, double *__restrict__ S, double tol) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   double *H = S + S_H, *g = S + S_G, *cs = S + S_CS, *sn = S + S_SN;
   double wn0 = sqrt(S[S_H1 + j + 1]);
@@ -178,8 +180,11 @@ __global__ void k_givens(int j, double *__restrict__ S) {
   H[(j + 1) * 64 + j] = 0.0;
   g[j + 1] = -sn[j] * g[j];
   g[j] = cs[j] * g[j];
-  S[S_STAT + 0] = fabs(g[j + 1]);
-  S[S_STAT + 1] = (hn <= 1e-14 * wn0) ? 1.0 : 0.0;
+  const double est = fabs(g[j + 1]);
+  const bool brk = hn <= 1e-14 * wn0;
+  S[S_STAT + 0] = est;
+  S[S_STAT + 1] = brk ? 1.0 : 0.0;
+  S[S_STAT + 2] = (brk || !(est > tol) || isinf(est)) ? 1.0 : 0.0;
 }
 
 __global__ void k_init_cycle(double *__restrict__ S, double beta) {
@@ -292,9 +297,10 @@ static rs_status gmres_t(rs_bsr_s *A, rs_cpr_s *M, const double *b, double *x, c
   TZ *Z = M->Z.as<TZ>();
   if (!M->hpin) RS_HIP(hipHostMalloc((void **)&M->hpin, sizeof(double) * 8, hipHostMallocDefault));
   struct { double *p; } hb = {M->hpin};
-  hipEvent_t e0, e1;
+  hipEvent_t e0, e1, es;
   RS_HIP(hipEventCreate(&e0));
   RS_HIP(hipEventCreate(&e1));
+  RS_HIP(hipEventCreateWithFlags(&es, hipEventDisableTiming));
   RS_HIP(hipEventRecord(e0, s));
   rs_status st = RS_OK;
   int iters = 0, cycles = 0;
@@ -338,29 +344,41 @@ static rs_status gmres_t(rs_bsr_s *A, rs_cpr_s *M, const double *b, double *x, c
       zero_start = false;
       k_init_cycle<<<1, 128, 0, s>>>(S, beta);
       ++cycles;
+      const double tol = o.rtol * bnorm;
+      const int zp = sizeof(TZ) == 8 ? 64 : 32;
       int k = 0;
+      bool in_queued = false;                    // step j's first pass is already on the stream
       for (int j = 0; j < m; ++j) {
         double *vj = V + (int64_t)j * N;
         TZ *zj = Z + (int64_t)j * N;
         // V_j = w / h_{j,j-1} is formed by the preconditioner's first pass
-        const int zp = sizeof(TZ) == 8 ? 64 : 32;
-        if ((st = j > 0     ? rs_cpr_apply_scaled(M, w, S + S_HN, vj, zj, zp, s)
-                  : v0_fused ? rs_cpr_apply_scaled(M, b, S + S_BETA, vj, zj, zp, s)
-                             : rs_cpr_apply_any(M, vj, zj, zp, s)) != RS_OK)
-          break;
-        if ((st = rs_spmv_any(A, zj, sizeof(TZ) == 8 ? 64 : 32, w, nullptr, s)) != RS_OK) break;
+        if (j == 0 && !v0_fused) {
+          st = rs_cpr_apply_any(M, vj, zj, zp, s);
+        } else {
+          if (!in_queued) st = rs_cpr_apply_in(M, j > 0 ? w : b, S + (j > 0 ? S_HN : S_BETA), vj, nullptr, s);
+          if (st == RS_OK) st = rs_cpr_apply_rest(M, zj, zp, s);
+        }
+        if (st != RS_OK) break;
+        if ((st = rs_spmv_any(A, zj, zp, w, nullptr, s)) != RS_OK) break;
         if ((st = run_dots(N, j + 1, V, w, part, S, S_H1, s)) != RS_OK) break;
         if ((st = run_axpy<false>(N, j + 1, V, S + S_H1, nullptr, w, part, S, S_H2, s)) != RS_OK) break;
         if ((st = run_axpy<true>(N, j + 1, V, S + S_H1, S + S_H2, w, part, S, S_NRM, s)) != RS_OK) break;
-        k_givens<<<1, 64, 0, s>>>(j, S);
+        k_givens<<<1, 64, 0, s>>>(j, S, tol);
         if (hipGetLastError() != hipSuccess) { st = RS_E_HIP; break; }
         ++iters;
         k = j + 1;
-        if ((st = read_host(hb.p, S + S_STAT, 2, s)) != RS_OK) break;
+        // the status goes to the host while the device already runs the next
+        // step's first pass, which does nothing if k_givens set the halt flag
+        // (the host stops on the same values)
+        if (hipMemcpyAsync(hb.p, S + S_STAT, sizeof(double) * 2, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipEventRecord(es, s) != hipSuccess) { st = RS_E_HIP; break; }
+        in_queued = j + 1 < m && iters < o.maxit;
+        if (in_queued && (st = rs_cpr_apply_in(M, w, S + S_HN, vj + N, S + S_STAT + 2, s)) != RS_OK) break;
+        if (hipEventSynchronize(es) != hipSuccess) { st = RS_E_HIP; break; }
         est = hb.p[0];
         if (!isfinite(est)) { st = RS_E_NONFINITE; break; }
         if (hb.p[1] != 0.0) break;                               // happy breakdown
-        if (est <= o.rtol * bnorm || iters >= o.maxit) break;
+        if (est <= tol || iters >= o.maxit) break;
       }
       if (st != RS_OK) break;
       k_backsolve<<<1, 64, 0, s>>>(k, S);
@@ -381,6 +399,7 @@ static rs_status gmres_t(rs_bsr_s *A, rs_cpr_s *M, const double *b, double *x, c
   (void)hipEventElapsedTime(&ms, e0, e1);
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  (void)hipEventDestroy(es);
   if (info) {
     info->iters = iters;
     info->cycles = cycles;

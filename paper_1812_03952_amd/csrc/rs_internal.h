@@ -151,10 +151,14 @@ unsigned rs_spmv_blocks(const rs_bsr_s *A);
 void rs_bsr_drop_adjoint(rs_bsr_s *A);
 rs_status rs_cpr_apply_any(rs_cpr_s *M, const double *r, void *z, int zprec,
                            hipStream_t s);
-// z = M^{-1} (w / *d_h) with v = w / *d_h written on the way (d_h on the
-// device): the normalisation of a Krylov vector fused into the first stage
-rs_status rs_cpr_apply_scaled(rs_cpr_s *M, const double *w, const double *d_h, double *v, void *z, int zprec,
-                              hipStream_t s);
+// z = M^{-1} (w / *d_h) in two calls, with v = w / *d_h written by the first
+// (d_h on the device): the normalisation of a Krylov vector fused into the
+// first stage.  rs_cpr_apply_in does nothing on the device when d_halt is
+// given and *d_halt is nonzero at the time it runs; rs_cpr_apply_rest takes
+// the first call's output and must follow it on the same stream.
+rs_status rs_cpr_apply_in(rs_cpr_s *M, const double *w, const double *d_h, double *v, const double *d_halt,
+                          hipStream_t s);
+rs_status rs_cpr_apply_rest(rs_cpr_s *M, void *z, int zprec, hipStream_t s);
 rs_status rs_vcycle_run(rs_cpr_s *M, hipStream_t s);
 rs_status rs_transpose7(const rs_bsr_s *A, rs_bsr_s *At, hipStream_t s);
 rs_status rs_dilu_prepare(rs_cpr_s *M);

@@ -2,8 +2,9 @@
 FP32-stored preconditioner inside FP64 GMRES (headline) beside plain FP64,
 plus the HBM roofline of the block SpMV and the FP64 CPU oracle's rate.
 
-One step = one Newton-step linear solve on the whole path: ingest the new
-values and decouple them (ABF) in one pass (rs_bsr_update_decouple), CPR setup
+One step = one Newton-step linear solve on the whole path: take the new
+values in place and decouple them (ABF) in one pass (rs_bsr_attach_decouple:
+the Jacobian stays in the caller's device buffer, no copy), CPR setup
 (AMG + layer RAS), and restarted GMRES from x0 = 0 to a true FP64 relative
 residual of 1e-8.  Inputs are seeded synthetic draws already resident in HBM;
 the Jacobian is assembled on the device.
@@ -96,7 +97,7 @@ def run_variant(rs, dp, A, prec, steps, warmup, tag, smoother, solver="gmres", m
     for it in range(warmup + steps):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        D = rs.bsr_update_decouple(A, dp.vals, method, prec)   # new Jacobian values, decoupled
+        D = rs.bsr_attach_decouple(A, dp.vals, method, prec)   # new Jacobian values, decoupled
         t1 = time.perf_counter()
         M = rs.cpr_setup(A, D, rs.cpr_opts(smoother=smoother, stages=stages))
         t2 = time.perf_counter()
@@ -215,7 +216,7 @@ def main():
         "fp64": res.get("fp64"),
         "bicgstab_fp32_precond": res.get("bicgstab_fp32"),
         "spmv": {"ms": spmv_ms, "GB_per_s": achieved, "bytes": spmv_bytes},
-        "roofline": {"bound": "hbm", "kernel": "k_spmv7<double,false,0> (y = A x)",
+        "roofline": {"bound": "hbm", "kernel": "k_spmv7<double,false,0,true> (y = A x, values read in place)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": spmv_traffic(n)},
     }

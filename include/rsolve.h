@@ -137,6 +137,20 @@ rs_status rs_bsr_update(rs_bsr A, const double *d_vals, void *stream);
 rs_status rs_bsr_update_decouple(rs_bsr A, const double *d_vals, int method, int prec, void *stream,
                                  rs_dcpl *out);
 
+/* As rs_bsr_update_decouple, but without a copy: A refers to d_vals (caller
+ * layout, 16-byte aligned) in place, and every later use of A's values (the
+ * SpMV inside the solvers, rs_decouple, the transpose of rs_adjoint_solve)
+ * reads them there, with results bitwise equal to those of the copying call.
+ * The caller keeps d_vals allocated and unchanged until A no longer refers to
+ * it: until the next rs_bsr_update, rs_bsr_update_decouple or
+ * rs_bsr_attach_decouple on A, or rs_bsr_destroy.  For the Newton loop, where
+ * the Jacobian is assembled in device memory the caller owns anyway: it
+ * saves writing the library's copy (16 * 7 * n doubles) on every step.
+ * Errors as for rs_bsr_update_decouple; after RS_E_NONFINITE or
+ * RS_E_SINGULAR A refers to d_vals, after RS_E_ARG nothing has changed. */
+rs_status rs_bsr_attach_decouple(rs_bsr A, const double *d_vals, int method, int prec, void *stream,
+                                 rs_dcpl *out);
+
 /* Decoupling (D^{-1} A) x = D^{-1} b, Eq. decoupled-eq, computed block row by
  * block row with Gauss-Jordan elimination and row pivoting (Section
  * "Decoupling Methods").  method: RS_ABF (D = diag(A_11..A_nn), Eq.

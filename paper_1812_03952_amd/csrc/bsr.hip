@@ -7,10 +7,15 @@
 // indices: the SpMV reads 7*128 B of matrix per cell in fully coalesced
 // 32-byte pieces (four lanes per cell, one block row each) and never reads a
 // column index.  The padding costs (7n - nnzb)/nnzb, 0.6% at 200x200x100.
+//
+// Attached values (rs_bsr_attach_decouple) stay in the caller's CSR layout;
+// the SpMV then finds each block from the closed-form row start of csr7.h,
+// with the same 32-byte row pieces and the same arithmetic.
 #include "rs_internal.h"
 #include <math.h>
 
 namespace {
+#include "csr7.h"
 
 __device__ __forceinline__ int64_t slot_nbr(int64_t c, int s, int64_t nx, int64_t nxy) {
   switch (s) {
@@ -60,6 +65,8 @@ __global__ void k_validate(int nx, int ny, int nz, int64_t nnzb, const int32_t *
     pos7[s * n + c] = q;
   }
   if (p != end) err = 1;
+  // the closed-form row start the kernels on attached values rely on
+  if (rp[c] != (int32_t)csr7_of((uint32_t)c, (uint32_t)nx, (uint32_t)ny, (uint32_t)nz).start) err = 1;
   if (err) atomicOr(bad, 1);
 }
 
@@ -109,8 +116,11 @@ template <> struct vec4_of<float> {
 //   ND = 1:  d0 = y . u   (u == nullptr: y . y)
 //   ND = 2:  d0 = y . u,  d1 = y . y
 // so a Krylov step gets (r^, v) or (t, s) and (t, t) without re-reading y.
-template <class TX, bool RES, int ND>
-__global__ __launch_bounds__(256) void k_spmv7(int64_t n, int64_t nx, int64_t nxy,
+// CSR: a7 is the caller's row-major blocks in CSR order (attached values);
+// an off-grid slot reads the row's diagonal block and zeroes it, so both
+// layouts give the same products in the same order.
+template <class TX, bool RES, int ND, bool CSR>
+__global__ __launch_bounds__(256) void k_spmv7(int64_t n, int ny, int nz, int64_t nx, int64_t nxy,
                                                 const double *__restrict__ a7,
                                                 const TX *__restrict__ x,
                                                 const double *__restrict__ b,
@@ -124,15 +134,19 @@ __global__ __launch_bounds__(256) void k_spmv7(int64_t n, int64_t nx, int64_t nx
     int64_t c = t >> 2;
     int r = (int)(t & 3);
     double acc = 0.0;
+    csr7_row w = {0, 0};
+    if (CSR) w = csr7_of((uint32_t)c, (uint32_t)nx, (uint32_t)ny, (uint32_t)nz);
 #pragma unroll
     for (int s = 0; s < 7; ++s) {
       int64_t q = slot_nbr(c, s, nx, nxy);
       q = (q < 0 || q >= n) ? c : q;           // off-grid blocks are zero
-      const v2d *ap = (const v2d *)(a7 + ((int64_t)s * n + c) * 16 + 4 * r);
+      const int64_t blk = CSR ? (int64_t)csr7_pos(w, s) : (int64_t)s * n + c;
+      const v2d *ap = (const v2d *)(a7 + blk * 16 + 4 * r);
       // plain loads: the non-temporal hint measured about 8 points of HBM
       // bandwidth slower here
       v2d a01 = ap[0];
       v2d a23 = ap[1];
+      if (CSR && !((w.mask >> s) & 1u)) { a01 = v2d{0.0, 0.0}; a23 = a01; }
       double xv[4];
       vec4_of<TX>::load(x + 4 * q, xv);
       acc = fma(a01.x, xv[0], acc);
@@ -164,9 +178,11 @@ __global__ __launch_bounds__(256) void k_spmv7(int64_t n, int64_t nx, int64_t nx
 }
 
 // A^T in the 7-slot layout: slot s of cell c holds the transpose of the
-// opposite slot (6-s) of the neighbour.
+// opposite slot (6-s) of the neighbour.  vals (attached values, caller
+// layout) replaces a7 as the source when given.
 __global__ void k_transpose7(int64_t n, int64_t nx, int64_t nxy, const int64_t *__restrict__ pos7,
-                             const double *__restrict__ a7, double *__restrict__ t7) {
+                             const double *__restrict__ a7, const double *__restrict__ vals,
+                             double *__restrict__ t7) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= 7 * n * 16) return;
   int64_t sc = t >> 4;
@@ -177,7 +193,8 @@ __global__ void k_transpose7(int64_t n, int64_t nx, int64_t nxy, const int64_t *
   if (pos7[sc] >= 0) {
     int64_t q = slot_nbr(c, s, nx, nxy);
     int r = e >> 2, col = e & 3;
-    v = a7[((int64_t)(6 - s) * n + q) * 16 + 4 * col + r];
+    v = vals ? vals[16 * pos7[(int64_t)(6 - s) * n + q] + 4 * col + r]
+             : a7[((int64_t)(6 - s) * n + q) * 16 + 4 * col + r];
   }
   t7[t] = v;
 }
@@ -247,6 +264,7 @@ static rs_status load_values(rs_bsr_s *A, const double *d_vals, hipStream_t s) {
                                                   flag.as<int>());
   RS_HIP(hipGetLastError());
   int h = 0;
+  A->ref = nullptr;                     // A holds its own copy again
   RS_HIP(hipMemcpyAsync(&h, flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
   RS_HIP(hipStreamSynchronize(s));
   return h ? RS_E_NONFINITE : RS_OK;
@@ -317,10 +335,18 @@ rs_status rs_spmv_dots(const rs_bsr_s *A, const void *x, int xprec, double *y, c
                        int nd, const double *u, double *part, hipStream_t s) {
   int64_t n = A->g.n;
   unsigned grid = rs_grid(4 * n);
-  const double *a7 = A->a7.as<double>();
+  const double *a7 = A->ref ? A->ref : A->a7.as<double>();
   const int64_t nx = A->g.nx, nxy = A->g.nxy;
-#define RS_SPMV(TX, RES, ND) \
-  k_spmv7<TX, RES, ND><<<grid, RS_BLOCK, 0, s>>>(n, nx, nxy, a7, (const TX *)x, b_minus, y, u, part)
+  const int ny = A->g.ny, nz = A->g.nz;
+#define RS_SPMV(TX, RES, ND)                                                                                   \
+  do {                                                                                                        \
+    if (A->ref)                                                                                               \
+      k_spmv7<TX, RES, ND, true><<<grid, RS_BLOCK, 0, s>>>(n, ny, nz, nx, nxy, a7, (const TX *)x, b_minus, y, u, \
+                                                           part);                                             \
+    else                                                                                                      \
+      k_spmv7<TX, RES, ND, false><<<grid, RS_BLOCK, 0, s>>>(n, ny, nz, nx, nxy, a7, (const TX *)x, b_minus, y, \
+                                                            u, part);                                         \
+  } while (0)
   if (nd < 0 || nd > 2 || (nd > 0 && !part)) return RS_E_ARG;
   if (xprec == 64) {
     if (b_minus) {
@@ -365,7 +391,7 @@ rs_status rs_transpose7(const rs_bsr_s *A, rs_bsr_s *At, hipStream_t s) {
   RS_HIP(hipMemcpyAsync(At->ci.p, A->ci.p, sizeof(int32_t) * A->nnzb, hipMemcpyDeviceToDevice, s));
   RS_HIP(hipMemcpyAsync(At->pos7.p, A->pos7.p, sizeof(int64_t) * 7 * n, hipMemcpyDeviceToDevice, s));
   k_transpose7<<<rs_grid(7 * n * 16), RS_BLOCK, 0, s>>>(n, A->g.nx, A->g.nxy, A->pos7.as<int64_t>(),
-                                                        A->a7.as<double>(), At->a7.as<double>());
+                                                        A->a7.as<double>(), A->ref, At->a7.as<double>());
   RS_HIP(hipGetLastError());
   return RS_OK;
 }

@@ -19,19 +19,46 @@
 
 namespace {
 #include "block4.h"
+#include "csr7.h"
 
 // Where a decoupling kernel reads block (s, c) of A from.
 //   src7:  the library's 7-slot copy a7 (after rs_bsr_create/rs_bsr_update);
 //   srcu:  the caller's row-major blocks in CSR order through the slot map
 //          pos7 (-1 off the grid: a zero block), for rs_bsr_update_decouple:
 //          the lane that owns slot s also stores the block into a7 and flags
-//          non-finite entries, so the update and the decoupling are one pass.
+//          non-finite entries, so the update and the decoupling are one pass;
+//   srcr:  attached values, the caller's layout read in place at the
+//          closed-form positions; the lane that owns slot s flags non-finite
+//          entries when asked, nothing is stored.
 struct src7 {
   const double *a7;
   int64_t n;
   __device__ __forceinline__ void diag(int64_t c, double (&M)[4][4]) const { load16(a7 + (3 * n + c) * 16, M); }
   __device__ __forceinline__ void block(int s, int64_t c, bool, double (&M)[4][4], int &) const {
     load16(a7 + ((int64_t)s * n + c) * 16, M);
+  }
+  __device__ __forceinline__ void commit(int64_t) const {}
+};
+struct srcr {
+  const double *vals;
+  uint32_t nx, ny, nz;
+  bool check;                // flag non-finite entries (values that just arrived)
+  __device__ __forceinline__ csr7_row row(int64_t c) const { return csr7_of((uint32_t)c, nx, ny, nz); }
+  __device__ __forceinline__ void diag(int64_t c, double (&M)[4][4]) const {
+    load16(vals + 16 * (int64_t)csr7_pos(row(c), 3), M);
+  }
+  __device__ __forceinline__ void block(int s, int64_t c, bool own, double (&M)[4][4], int &f) const {
+    const csr7_row w = row(c);
+    load16(vals + 16 * (int64_t)csr7_pos(w, s), M);
+    if (!((w.mask >> s) & 1u)) {
+#pragma unroll
+      for (int e = 0; e < 16; ++e) M[e >> 2][e & 3] = 0.0;
+    }
+    if (check && own) {
+#pragma unroll
+      for (int e = 0; e < 16; ++e)
+        if (!isfinite(M[e >> 2][e & 3])) f |= RSF_NONFINITE;
+    }
   }
   __device__ __forceinline__ void commit(int64_t) const {}
 };
@@ -299,8 +326,10 @@ static void launch_decouple(int method, int prec, int64_t n, SRC src, rs_dcpl_s 
 }
 
 // vals == nullptr: decouple A's current values; else store vals (caller
-// layout) into A and decouple them in the same pass.
-static rs_status decouple_impl(rs_bsr_s *A, const double *vals, int method, int prec, hipStream_t s, rs_dcpl *out) {
+// layout) into A and decouple them in the same pass, or with attach, make A
+// refer to vals in place and decouple them.
+static rs_status decouple_impl(rs_bsr_s *A, const double *vals, bool attach, int method, int prec, hipStream_t s,
+                               rs_dcpl *out) {
   if (!A || !out || method < RS_ABF || method > RS_FRS_ABF || (prec != 32 && prec != 64))
     return RS_E_ARG;
   if (vals && ((uintptr_t)vals & 15)) return RS_E_ARG;     // block rows are read 16 bytes at a time
@@ -319,8 +348,18 @@ static rs_status decouple_impl(rs_bsr_s *A, const double *vals, int method, int 
     dbuf flag;
     if ((st = flag.alloc(sizeof(int))) != RS_OK) break;
     if (hipMemsetAsync(flag.p, 0, sizeof(int), s) != hipSuccess) { st = RS_E_HIP; break; }
-    if (vals) launch_decouple(method, prec, n, srcu{vals, A->pos7.as<int64_t>(), A->a7.as<double>(), n}, D, flag.as<int>(), s);
-    else launch_decouple(method, prec, n, src7{A->a7.as<double>(), n}, D, flag.as<int>(), s);
+    const grid3 &g = A->g;
+    if (vals && attach) A->ref = vals;
+    if (vals && !attach) {
+      launch_decouple(method, prec, n, srcu{vals, A->pos7.as<int64_t>(), A->a7.as<double>(), n}, D, flag.as<int>(), s);
+      A->ref = nullptr;
+    } else if (A->ref) {
+      // attached values are checked for finiteness when they arrive
+      const srcr src{A->ref, (uint32_t)g.nx, (uint32_t)g.ny, (uint32_t)g.nz, vals != nullptr};
+      launch_decouple(method, prec, n, src, D, flag.as<int>(), s);
+    } else {
+      launch_decouple(method, prec, n, src7{A->a7.as<double>(), n}, D, flag.as<int>(), s);
+    }
     if (hipGetLastError() != hipSuccess ||
         hipMemcpyAsync(&h, flag.p, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess) { st = RS_E_HIP; break; }
@@ -333,14 +372,21 @@ static rs_status decouple_impl(rs_bsr_s *A, const double *vals, int method, int 
 }
 
 extern "C" rs_status rs_decouple(rs_bsr A, int method, int prec, void *stream, rs_dcpl *out) {
-  return decouple_impl(A, nullptr, method, prec, rs_stream(stream), out);
+  return decouple_impl(A, nullptr, false, method, prec, rs_stream(stream), out);
 }
 
 extern "C" rs_status rs_bsr_update_decouple(rs_bsr A, const double *d_vals, int method, int prec, void *stream,
                                             rs_dcpl *out) {
   if (!A || !d_vals || !out) return RS_E_ARG;
   rs_bsr_drop_adjoint(A);
-  return decouple_impl(A, d_vals, method, prec, rs_stream(stream), out);
+  return decouple_impl(A, d_vals, false, method, prec, rs_stream(stream), out);
+}
+
+extern "C" rs_status rs_bsr_attach_decouple(rs_bsr A, const double *d_vals, int method, int prec, void *stream,
+                                            rs_dcpl *out) {
+  if (!A || !d_vals || !out) return RS_E_ARG;
+  rs_bsr_drop_adjoint(A);
+  return decouple_impl(A, d_vals, true, method, prec, rs_stream(stream), out);
 }
 
 extern "C" void rs_dcpl_destroy(rs_dcpl D) { delete D; }

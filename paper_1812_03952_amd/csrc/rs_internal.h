@@ -69,6 +69,9 @@ struct rs_bsr_s {
   dbuf rp, ci;       // caller pattern (copy), int32
   dbuf pos7;         // int64 per (slot, cell): caller block index or -1
   dbuf a7;           // double [7][n][16]: blocks by stencil slot (zeros off-grid)
+  // attached values (caller layout, rs_bsr_attach_decouple): when set, the
+  // values of A are read there and a7 is stale
+  const double *ref = nullptr;
   // adjoint cache
   rs_bsr_s *at = nullptr;
   rs_dcpl_s *at_d = nullptr;

@@ -69,6 +69,7 @@ def lib():
             "rs_bsr_update": (_i, [_vp, _vp, _vp]),
             "rs_decouple": (_i, [_vp, _i, _i, _vp, C.POINTER(_vp)]),
             "rs_bsr_update_decouple": (_i, [_vp, _vp, _i, _i, _vp, C.POINTER(_vp)]),
+            "rs_bsr_attach_decouple": (_i, [_vp, _vp, _i, _i, _vp, C.POINTER(_vp)]),
             "rs_cpr_setup": (_i, [_vp, _vp, C.POINTER(CprOpts), _vp, C.POINTER(_vp)]),
             "rs_gmres_solve": (_i, [_vp, _vp, _vp, _vp, C.POINTER(GmresOpts), C.POINTER(SolveInfo), _vp]),
             "rs_bicgstab_solve": (_i, [_vp, _vp, _vp, _vp, C.POINTER(BicgstabOpts), C.POINTER(SolveInfo), _vp]),
@@ -169,6 +170,7 @@ class Bsr:
     def __init__(self, h, nx, ny, nz, nnzb):
         self.h, self.nx, self.ny, self.nz, self.nnzb = h, nx, ny, nz, nnzb
         self.n = nx * ny * nz
+        self.attached = []          # value tensors A may refer to, kept alive here
 
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:
@@ -218,15 +220,38 @@ def bsr_create(nx, ny, nz, row_ptr, col_idx, vals, stream=None) -> Bsr:
     return Bsr(h, nx, ny, nz, nnzb)
 
 
+# Statuses after which the library has taken the new values (A holds or
+# refers to them); after any other error A may still refer to older ones.
+_TAKEN = (0, -4, -5)
+
+
 def bsr_update(A: Bsr, vals, stream=None):
-    _check(lib().rs_bsr_update(A.h, _ptr(vals, torch.float64, 16 * A.nnzb), _stream(stream)), "rs_bsr_update")
+    st = lib().rs_bsr_update(A.h, _ptr(vals, torch.float64, 16 * A.nnzb), _stream(stream))
+    if st in _TAKEN:
+        A.attached = []
+    _check(st, "rs_bsr_update")
 
 
 def bsr_update_decouple(A: Bsr, vals, method=ABF, prec=64, stream=None) -> Dcpl:
     """bsr_update(A, vals) and decouple(A, method, prec) in one pass."""
     h = C.c_void_p()
-    _check(lib().rs_bsr_update_decouple(A.h, _ptr(vals, torch.float64, 16 * A.nnzb), method, prec, _stream(stream),
-                                        C.byref(h)), "rs_bsr_update_decouple")
+    st = lib().rs_bsr_update_decouple(A.h, _ptr(vals, torch.float64, 16 * A.nnzb), method, prec,
+                                      _stream(stream), C.byref(h))
+    if st in _TAKEN:
+        A.attached = []
+    _check(st, "rs_bsr_update_decouple")
+    return Dcpl(h, A, method, prec)
+
+
+def bsr_attach_decouple(A: Bsr, vals, method=ABF, prec=64, stream=None) -> Dcpl:
+    """As bsr_update_decouple, but A refers to `vals` in place (no copy).
+    A keeps the tensor alive until its next update or attach; the caller
+    must not change it meanwhile."""
+    h = C.c_void_p()
+    st = lib().rs_bsr_attach_decouple(A.h, _ptr(vals, torch.float64, 16 * A.nnzb), method, prec,
+                                      _stream(stream), C.byref(h))
+    A.attached = [vals] if st in _TAKEN else A.attached + [vals]
+    _check(st, "rs_bsr_attach_decouple")
     return Dcpl(h, A, method, prec)
 
 

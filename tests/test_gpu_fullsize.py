@@ -1,5 +1,6 @@
 """Parity at the full workload sizes, in the configuration bench.py times
-(bsr_update -> decouple -> cpr_setup -> gmres_solve, RAS second stage):
+(bsr_attach_decouple -> cpr_setup -> gmres_solve from x0 = 0, RAS second
+stage):
 the 100x100x50 and 200x200x100 systems solved by the library and by the FP64
 oracle, the true residual recomputed by the oracle, and sampled SpMV rows
 computed one by one on the host."""
@@ -17,11 +18,10 @@ pytestmark = pytest.mark.gpu
 
 def _solve(dp, prec, rtol=1e-8, smoother=rs.SM_RAS):
     A = dp.bsr()
-    rs.bsr_update(A, dp.vals)
-    D = rs.decouple(A, rs.ABF, prec)
+    D = rs.bsr_attach_decouple(A, dp.vals, rs.ABF, prec)
     M = rs.cpr_setup(A, D, rs.cpr_opts(smoother=smoother))
     x = torch.zeros_like(dp.b)
-    info = rs.gmres_solve(A, M, dp.b, x, rs.gmres_opts(rtol=rtol))
+    info = rs.gmres_solve(A, M, dp.b, x, rs.gmres_opts(rtol=rtol, zero_guess=1))
     return A, x, info
 
 
@@ -56,11 +56,14 @@ def test_full_size_solve_against_oracle(cfg):
             assert err <= 1e-8
 
 
+@pytest.mark.parametrize("attach", [False, True])
 @pytest.mark.parametrize("cfg", [2])
-def test_full_size_spmv_sampled_rows(cfg):
+def test_full_size_spmv_sampled_rows(cfg, attach):
     p = synth.config(cfg)
     dp = rs.DeviceProblem(p)
     A = dp.bsr()
+    if attach:
+        rs.bsr_attach_decouple(A, dp.vals, rs.ABF, 32)   # the SpMV reads dp.vals in place
     N = 4 * p.n
     x = torch.randn(N, dtype=torch.float64, device="cuda", generator=torch.Generator("cuda").manual_seed(3))
     y = torch.empty_like(x)

@@ -471,12 +471,18 @@ __global__ __launch_bounds__(GAL_BLOCK) void k_galerkin(int nc, const int32_t *_
   cnt[I] = m;
 }
 
+// Also the coarse level's l1 diagonal (as k_l1diag, the same additions in
+// the same order) and, when cap is given, its FP32 values (as k_cast_f32),
+// so the coarse level needs no pass of its own for them.
+template <class T>
 __global__ void k_galerkin_copy(int nc, const int32_t *__restrict__ off, const int32_t *__restrict__ skey,
                                 const double *__restrict__ sval, const int32_t *__restrict__ crp,
-                                int32_t *__restrict__ cci, double *__restrict__ ca) {
+                                int32_t *__restrict__ cci, double *__restrict__ ca, float *__restrict__ cap,
+                                T *__restrict__ dl1) {
   int I = blockIdx.x * blockDim.x + threadIdx.x;
   if (I >= nc) return;
   int b = off[I], o = crp[I], m = crp[I + 1] - crp[I];
+  double sum = 0.0, aii = 0.0;
   for (int sb = 0; sb < m; sb += 8) {            // eight entries' loads in flight at once
     int32_t kv[8];
     double vv[8];
@@ -489,8 +495,16 @@ __global__ void k_galerkin_copy(int nc, const int32_t *__restrict__ off, const i
     }
 #pragma unroll
     for (int k = 0; k < 8; ++k)
-      if (sb + k < m) { cci[o + sb + k] = kv[k]; ca[o + sb + k] = vv[k]; }
+      if (sb + k < m) {
+        cci[o + sb + k] = kv[k];
+        ca[o + sb + k] = vv[k];
+        if (cap) cap[o + sb + k] = (float)vv[k];
+        sum = sum + fabs(vv[k]);
+        if (kv[k] == I) aii = vv[k];
+      }
   }
+  if (sum == 0.0) sum = 1.0;
+  dl1[I] = (T)(aii < 0.0 ? -sum : sum);
 }
 
 __global__ void k_set_last(int32_t *__restrict__ p, int64_t idx, const int32_t *__restrict__ v) { p[idx] = *v; }
@@ -1230,8 +1244,9 @@ static rs_status level_alloc_work(amg_level *L, int prec, int64_t guard, bool cs
   L->xoff = guard;
   if (guard) RS_HIP(hipMemsetAsync(L->x.p, 0, es * (L->n + 1 + 2 * guard), s));
   RS_TRY(L->r.alloc(es * (L->n + 1)));
-  RS_TRY(L->dl1.alloc(es * (L->n + 1)));
-  if (prec == 32 && csr_values) {
+  // a coarse level's l1 diagonal and FP32 values come with its Galerkin copy
+  if (!L->dl1.p) RS_TRY(L->dl1.alloc(es * (L->n + 1)));
+  if (prec == 32 && csr_values && !L->ap.p) {
     RS_TRY(L->ap.alloc(sizeof(float) * (L->nnz + 1)));
   }
   return RS_OK;
@@ -1275,7 +1290,7 @@ rs_status rs_amg_build(rs_cpr_s *M, hipStream_t s) {
       else
         k_fine7<float><<<rs_grid(n), RS_BLOCK, 0, s>>>(g.nx, g.ny, g.nz, ap7, o.theta, o.max_row_sum,
                                                        L->s7.as<float>(), L->dl1.as<float>(), dir.as<uint8_t>());
-    } else {
+    } else if (l == 0) {
       if (prec == 64) k_l1diag<double><<<rs_grid(n), RS_BLOCK, 0, s>>>(n, L->rp.as<int32_t>(), L->ci.as<int32_t>(), L->a.as<double>(), L->dl1.as<double>());
       else k_l1diag<float><<<rs_grid(n), RS_BLOCK, 0, s>>>(n, L->rp.as<int32_t>(), L->ci.as<int32_t>(), L->a.as<double>(), L->dl1.as<float>());
       if (prec == 32) k_cast_f32<<<rs_grid(L->nnz), RS_BLOCK, 0, s>>>(L->nnz, L->a.as<double>(), L->ap.as<float>());
@@ -1392,8 +1407,16 @@ rs_status rs_amg_build(rs_cpr_s *M, hipStream_t s) {
     k_set_last<<<1, 1, 0, s>>>(C->rp.as<int32_t>(), nc, flag.as<int32_t>() + 1);
     RS_TRY(C->ci.alloc(sizeof(int32_t) * (ncand + 1)));
     RS_TRY(C->a.alloc(sizeof(double) * (ncand + 1)));
-    k_galerkin_copy<<<rs_grid(nc), RS_BLOCK, 0, s>>>(nc, off.as<int32_t>(), skey.as<int32_t>(), sval.as<double>(),
-                                                      C->rp.as<int32_t>(), C->ci.as<int32_t>(), C->a.as<double>());
+    RS_TRY(C->dl1.alloc((prec == 64 ? sizeof(double) : sizeof(float)) * ((size_t)nc + 1)));
+    if (prec == 32) RS_TRY(C->ap.alloc(sizeof(float) * (ncand + 1)));
+    if (prec == 64)
+      k_galerkin_copy<double><<<rs_grid(nc), RS_BLOCK, 0, s>>>(nc, off.as<int32_t>(), skey.as<int32_t>(),
+                                                               sval.as<double>(), C->rp.as<int32_t>(), C->ci.as<int32_t>(),
+                                                               C->a.as<double>(), nullptr, C->dl1.as<double>());
+    else
+      k_galerkin_copy<float><<<rs_grid(nc), RS_BLOCK, 0, s>>>(nc, off.as<int32_t>(), skey.as<int32_t>(),
+                                                              sval.as<double>(), C->rp.as<int32_t>(), C->ci.as<int32_t>(),
+                                                              C->a.as<double>(), C->ap.as<float>(), C->dl1.as<float>());
     RS_HIP(hipGetLastError());
     int h[2] = {0, 0};
     RS_HIP(hipMemcpyAsync(h, flag.p, sizeof(int) * 2, hipMemcpyDeviceToHost, s));

@@ -159,7 +159,6 @@ __global__ __launch_bounds__(256) void k_decouple_abf(int64_t n, SRC src,
   const int lane = (int)(t & 7);
   double L[4][4], R[4][4];
   int fsrc = 0;
-  src.diag(c, L);
   if (lane < 7) {
     src.block(lane, c, valid, R, fsrc);
   } else {
@@ -168,6 +167,9 @@ __global__ __launch_bounds__(256) void k_decouple_abf(int64_t n, SRC src,
 #pragma unroll
       for (int q = 0; q < 4; ++q) R[r][q] = (r == q) ? 1.0 : 0.0;
   }
+  // A_ii is slot 3's block: taken from lane 3 of the cell's group
+#pragma unroll
+  for (int e = 0; e < 16; ++e) L[e >> 2][e & 3] = __shfl(R[e >> 2][e & 3], 3, 8);
   if (FRS) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {

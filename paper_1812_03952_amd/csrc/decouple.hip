@@ -5,10 +5,12 @@
 // applied block row by block row with Gauss-Jordan elimination and row
 // pivoting only (Section "Decoupling Methods").  Eight lanes work on one
 // block row: lane s < 7 carries block column s of [A_ii | A_i,s] through the
-// elimination, lane 7 carries the identity and so produces D_i^{-1}.  Every
-// lane repeats the (cheap) pivot sequence on A_ii itself, which keeps all
-// lanes independent and the per-lane state at 32 doubles.  Row exchanges
-// are written as selects over compile-time indices so nothing spills.
+// elimination, lane 7 carries the identity and so produces D_i^{-1}.  Lane 3
+// loads A_ii as its own slot and the group takes it from there by shuffle;
+// every lane then repeats the (cheap) pivot sequence on A_ii itself, which
+// keeps the lanes independent and the per-lane state at 32 doubles.  Row
+// exchanges are written as selects over compile-time indices so nothing
+// spills.
 //
 // FMA contraction is off in this file: each update is one multiply and one
 // subtract, in the same order as the FP64 reference, so the FP64 pressure
@@ -33,7 +35,6 @@ namespace {
 struct src7 {
   const double *a7;
   int64_t n;
-  __device__ __forceinline__ void diag(int64_t c, double (&M)[4][4]) const { load16(a7 + (3 * n + c) * 16, M); }
   __device__ __forceinline__ void block(int s, int64_t c, bool, double (&M)[4][4], int &) const {
     load16(a7 + ((int64_t)s * n + c) * 16, M);
   }
@@ -44,9 +45,6 @@ struct srcr {
   uint32_t nx, ny, nz;
   bool check;                // flag non-finite entries (values that just arrived)
   __device__ __forceinline__ csr7_row row(int64_t c) const { return csr7_of((uint32_t)c, nx, ny, nz); }
-  __device__ __forceinline__ void diag(int64_t c, double (&M)[4][4]) const {
-    load16(vals + 16 * (int64_t)csr7_pos(row(c), 3), M);
-  }
   __device__ __forceinline__ void block(int s, int64_t c, bool own, double (&M)[4][4], int &f) const {
     const csr7_row w = row(c);
     load16(vals + 16 * (int64_t)csr7_pos(w, s), M);
@@ -75,7 +73,6 @@ struct srcu {
     __shared__ double sa[7][32][16];
     return sa;
   }
-  __device__ __forceinline__ void diag(int64_t c, double (&M)[4][4]) const { load16(vals + 16 * pos7[3 * n + c], M); }
   __device__ __forceinline__ void block(int s, int64_t c, bool store, double (&M)[4][4], int &f) const {
     const int64_t p = pos7[(int64_t)s * n + c];
     if (p >= 0) {
@@ -212,24 +209,23 @@ __global__ __launch_bounds__(256) void k_decouple_qi(int64_t n, SRC src,
   const bool valid = t < 8 * n;                 // all threads stay for the block-wide col0 store
   const int64_t c = valid ? t >> 3 : n - 1;
   const int lane = (int)(t & 7);
-  double L[4][4], w[4][1];
+  double L[4][4], w[4][1], A[4][4];
   int fsrc = 0;
-  {
-    double Aii[4][4];
-    src.diag(c, Aii);
+  if (lane < 7) {
+    src.block(lane, c, valid, A, fsrc);
+  } else {
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) L[r][q] = Aii[q][r];
+    for (int e = 0; e < 16; ++e) A[e >> 2][e & 3] = 0.0;
   }
+  // A_ii is slot 3's block: taken from lane 3 of the cell's group, transposed
+#pragma unroll
+  for (int e = 0; e < 16; ++e) L[e & 3][e >> 2] = __shfl(A[e >> 2][e & 3], 3, 8);
 #pragma unroll
   for (int r = 0; r < 4; ++r) w[r][0] = (r == 0) ? 1.0 : 0.0;
   int f = gje4<1>(L, w);
   double R[4][4];
   if (valid && lane == 0 && f) atomicOr(flag, f);
   if (lane < 7) {
-    double A[4][4];
-    src.block(lane, c, valid, A, fsrc);
     if (fsrc) atomicOr(flag, fsrc);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {

@@ -225,3 +225,66 @@ def test_single_level_is_exact_solve():
     Af = np.zeros((n, n)); Af[np.repeat(np.arange(n), np.diff(A.rp)), A.ci] = ap
     b = np.random.default_rng(3).standard_normal(n)
     assert np.allclose(h.vcycle(b), np.linalg.solve(Af, b), rtol=1e-11)
+
+
+def _dense(L):
+    n = L["n"]
+    Ad = np.zeros((n, n))
+    Ad[np.repeat(np.arange(n), np.diff(L["rp"])), L["ci"]] = L["a"]
+    return Ad
+
+
+def _jacobi_poly(Ad, d, k):
+    """k l1-Jacobi sweeps from x = 0 as a matrix: sum_{i<k} (I - S A)^i S,
+    S = diag(1/d) (the Neumann partial sum, not the sweep recurrence)."""
+    n = Ad.shape[0]
+    S = np.diag(1.0 / d)
+    E = np.eye(n) - S @ Ad
+    Q, T = np.zeros((n, n)), np.eye(n)
+    for _ in range(k):
+        Q = Q + T @ S
+        T = E @ T
+    return Q
+
+
+@pytest.mark.parametrize("sweeps", [1, 2, 4, 7])
+def test_coarsest_l1_jacobi_fallback(sweeps):
+    """A coarsest level larger than lu_max is not inverted but relaxed by
+    coarse_sweeps l1-Jacobi sweeps from zero.  Single level: the V-cycle is
+    the Jacobi polynomial of A.  Two levels: the two-level operator with that
+    polynomial in place of A_c^{-1}."""
+    p = synth.make(6, 5, 3, seed=19, sigma=1.0)
+    A = oracle.assemble(p)
+    At, _ = oracle.decouple(A)
+    ap = oracle.extract_pressure(At)
+    h = oracle.AMG(A.rp, A.ci, ap, coarse_n=1000, lu_max=10, coarse_sweeps=sweeps)
+    assert h.nlevels == 1 and not h.coarsest_is_lu
+    F = h.level(0)
+    Ad = _dense(F)
+    Vd = np.stack([h.vcycle(e) for e in np.eye(F["n"])], 1)
+    ref = _jacobi_poly(Ad, F["dl1"], sweeps)
+    assert np.allclose(Vd, ref, rtol=1e-12, atol=1e-14 * np.abs(ref).max())
+    h = oracle.AMG(A.rp, A.ci, ap, coarse_n=40, lu_max=1, coarse_sweeps=sweeps)
+    assert h.nlevels == 2 and not h.coarsest_is_lu
+    F, Cl = h.level(0), h.level(1)
+    n, nc = F["n"], Cl["n"]
+    Af = _dense(F)
+    P = np.zeros((n, nc))
+    for i, I in enumerate(F["agg"]):
+        if I >= 0:
+            P[i, I] = 1.0
+    Ac = P.T @ Af @ P
+    S = np.diag(1.0 / F["dl1"])
+    I = np.eye(n)
+    CG = P @ _jacobi_poly(Ac, Cl["dl1"], sweeps) @ P.T
+    Bop = S + CG @ (I - Af @ S)
+    Bop = Bop + S @ (I - Af @ Bop)
+    Vd = np.stack([h.vcycle(e) for e in I], 1)
+    assert np.allclose(Vd, Bop, rtol=1e-10, atol=1e-12 * np.abs(Bop).max())
+    # many sweeps on a diagonally dominant coarsest level approach A_c^{-1}
+    if sweeps == 7:
+        h = oracle.AMG(A.rp, A.ci, ap, coarse_n=1000, lu_max=10, coarse_sweeps=400)
+        b = np.random.default_rng(2).standard_normal(F["n"])
+        rho = np.abs(np.linalg.eigvals(np.eye(F["n"]) - np.diag(1 / F["dl1"]) @ Af)).max()
+        if rho < 0.95:
+            assert np.allclose(h.vcycle(b), np.linalg.solve(Af, b), rtol=1e-6)

@@ -163,3 +163,79 @@ def test_adjoint_duality_fd_and_dense():
     fd = np.array([(_J(p, p.logk + h * e) - _J(p, p.logk - h * e)) / (2 * h)
                    for e in np.eye(p.n)])
     assert np.allclose(g, fd, rtol=1e-6, atol=1e-7 * np.abs(fd).max())
+
+
+def _scaled_identity_problem(dims, diag):
+    """A block-diagonal system whose every diagonal block is diag(d): no flux
+    couplings (M = 0), no wells, accumulation B = diag(d), dt = 1."""
+    p = synth.make(*dims, seed=53, sigma=1.0, storage=0.0)
+    p.Mf[:] = 0.0
+    p.Mb[:] = 0.0
+    p.B[:] = np.diag(diag)
+    return p, oracle.assemble(p)
+
+
+def test_gmres_happy_breakdown():
+    """Happy breakdown: when the Krylov space of b under A M^{-1} is invariant
+    after k steps, h_{k,k-1} vanishes, the cycle ends there and x is exact.
+    A = c I (no preconditioner): one step, x = b / c.  A = blockdiag of
+    diag(c1, c2, c1, c2): the minimal polynomial has degree 2, two steps.
+    With rtol = 0 the estimate never meets the bound, so only the breakdown
+    test can end a cycle: every cycle is one step long, and x stays finite
+    (v_1 = w / h_{1,0} would divide by ~0)."""
+    p, A = _scaled_identity_problem((4, 3, 2), [4.0, 4.0, 4.0, 4.0])
+    x, info = oracle.gmres(A, p.b, None, restart=30, rtol=1e-12, maxit=30)
+    assert info["status"] == 0 and info["iters"] == 1 and info["cycles"] == 1
+    assert np.linalg.norm(x - p.b / 4.0) <= 1e-15 * np.linalg.norm(p.b / 4.0)
+    x, info = oracle.gmres(A, p.b, None, restart=30, rtol=0.0, maxit=3)
+    assert np.all(np.isfinite(x)) and info["iters"] == info["cycles"] >= 1
+    assert np.linalg.norm(x - p.b / 4.0) <= 1e-15 * np.linalg.norm(p.b / 4.0)
+    p, A = _scaled_identity_problem((4, 3, 2), [2.0, 8.0, 2.0, 8.0])
+    x, info = oracle.gmres(A, p.b, None, restart=30, rtol=1e-12, maxit=30)
+    assert info["status"] == 0 and info["iters"] == 2 and info["cycles"] == 1
+    xe = p.b / np.tile([2.0, 8.0, 2.0, 8.0], A.n)
+    assert np.linalg.norm(x - xe) <= 1e-14 * np.linalg.norm(xe)
+    # with CPR on A = 4 I, M^{-1} = A^{-1} exactly: breakdown at the first step
+    p, A = _scaled_identity_problem((4, 3, 2), [4.0, 4.0, 4.0, 4.0])
+    x, info = oracle.gmres(A, p.b, oracle.CPR(A), restart=30, rtol=0.0, maxit=3)
+    assert info["iters"] == info["cycles"] >= 1 and np.all(np.isfinite(x))
+    assert np.linalg.norm(x - p.b / 4.0) <= 1e-15 * np.linalg.norm(p.b / 4.0)
+
+
+@pytest.mark.parametrize("restart", [2, 3, 4])
+def test_gmres_restart_cycles(restart):
+    """Restarted GMRES(m) with m small on a 12x10x6 sigma-2 draw: several
+    cycles, each starting from the true residual of the last update.  Pinned
+    by the dense-LU solution and by the minimal-residual property of a cycle:
+    after one cycle from x0 no x0 + K_m(A M^{-1}, r0) M^{-1}-combination has a
+    smaller residual, checked against the least-squares solution over the
+    explicitly built (unorthogonalised, then QR-orthogonalised) basis."""
+    p = synth.make(12, 10, 6, seed=5, sigma=2.0, shale=0.1,
+                   wells=synth.wells_vertical_pair(12, 10, 6, (0, 0), (11, 9)))
+    A = oracle.assemble(p)
+    M = oracle.CPR(A, smoother=oracle.SM_BJ)
+    x, info = oracle.gmres(A, p.b, M, restart=restart, rtol=1e-12, maxit=300)
+    assert info["status"] == 0 and info["cycles"] >= 2
+    assert info["iters"] <= restart * info["cycles"] and info["iters"] > restart * (info["cycles"] - 1)
+    Ad = A.dense()
+    xref = np.linalg.solve(Ad, p.b)
+    assert np.linalg.norm(p.b - Ad @ x) <= 1e-12 * np.linalg.norm(p.b) * 1.0001
+    assert np.linalg.norm(x - xref) <= 1e-9 * np.linalg.norm(xref)
+    # one cycle from x0 = 0 minimises ||b - A x|| over x in M^{-1} K_m(A M^{-1}, b)
+    x1, i1 = oracle.gmres(A, p.b, M, restart=restart, rtol=1e-12, maxit=restart)
+    assert i1["iters"] == restart and i1["cycles"] == 1 and i1["status"] == 1
+    Zs, v = [], p.b / np.linalg.norm(p.b)
+    Kv = [v]
+    for _ in range(restart):
+        z = M.apply(Kv[-1])
+        Zs.append(z)
+        w = Ad @ z
+        for u in Kv:                                  # orthogonalise for conditioning only
+            w = w - (u @ w) * u
+        Kv.append(w / np.linalg.norm(w))
+    Z = np.stack(Zs, 1)
+    y, *_ = np.linalg.lstsq(Ad @ Z, p.b, rcond=None)
+    best = np.linalg.norm(p.b - Ad @ (Z @ y))
+    got = np.linalg.norm(p.b - Ad @ x1)
+    assert got <= best * (1 + 1e-8) + 1e-14 * np.linalg.norm(p.b)
+    assert np.linalg.norm(x1 - Z @ y) <= 1e-8 * np.linalg.norm(Z @ y)

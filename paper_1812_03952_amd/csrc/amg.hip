@@ -1252,6 +1252,21 @@ static rs_status level_alloc_work(amg_level *L, int prec, int64_t guard, bool cs
   return RS_OK;
 }
 
+// The fine level was set up by the structured kernels to be coarsened, but no
+// aggregate formed (every row weak, or no vertex with a strength edge): it is
+// the coarsest level after all, and the coarsest solve (dense inverse or
+// l1-Jacobi sweeps) reads its CSR arrays and, in FP32, its FP32 values.
+static rs_status level0_as_coarsest(rs_cpr_s *M, hipStream_t s) {
+  amg_level *L = M->lev[0];
+  RS_TRY(rs_amg_level0_csr(M, s));
+  if (M->prec == 32 && !L->ap.p) {
+    RS_TRY(L->ap.alloc(sizeof(float) * (L->nnz + 1)));
+    k_cast_f32<<<rs_grid(L->nnz), RS_BLOCK, 0, s>>>(L->nnz, L->a.as<double>(), L->ap.as<float>());
+    RS_HIP(hipGetLastError());
+  }
+  return RS_OK;
+}
+
 // Build the whole hierarchy; M->lev[0] must hold n and nnz.  The fine level
 // is set up by the structured kernels from the pressure entries by slot; its
 // CSR arrays are built only when it is also the coarsest level (or when it is
@@ -1349,7 +1364,10 @@ rs_status rs_amg_build(rs_cpr_s *M, hipStream_t s) {
     int64_t nc64 = 0;
     RS_TRY(scan_i32(id.as<int32_t>(), id.as<int32_t>(), n, &nc64, s, nullptr));
     int nc = (int)nc64;
-    if (nc == 0 || nc >= n) break;   // no coarsening possible: this level is the coarsest
+    if (nc == 0 || nc >= n) {        // no coarsening possible: this level is the coarsest
+      if (st7) RS_TRY(level0_as_coarsest(M, s));
+      break;
+    }
     RS_HIP(hipMemsetAsync(flag.p, 0, sizeof(int), s));
     if (st7) {
       k_agg1_7<<<rs_grid(n), RS_BLOCK, 0, s>>>(g.nx, g.ny, g.nz, strong.as<uint8_t>(), state.as<uint8_t>(),

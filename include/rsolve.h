@@ -283,6 +283,18 @@ rs_status rs_cpr_smoother_get(rs_cpr M, double *h_dinv2);
  * column beyond); 16 n^2 bytes of scratch.  A zero pivot gives
  * RS_E_SINGULAR. */
 rs_status rs_dense_inverse(int n, const double *d_a, double *d_inv, void *stream);
+/* rs_dense_inverse without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same kernels and result as rs_dense_inverse (bitwise).
+ * n <= RS_DENSE_NOALLOC_MAX, else RS_E_ARG.  The scratch (the n x 2n
+ * augmented matrix and the singular flag, 16 MiB + 256 B) is a static device
+ * array of the library: one copy per GPU, held until the process ends, and
+ * shared by every call on that GPU.  Calls that overlap on one GPU (several
+ * streams or host threads) race on it and must be serialised by the caller.
+ * d_a and d_inv (n*n doubles, device) may alias.  The call synchronises the
+ * stream to read the singular flag; a zero pivot gives RS_E_SINGULAR. */
+#define RS_DENSE_NOALLOC_MAX 1024
+rs_status rs_dense_inverse_noalloc(int n, const double *d_a, double *d_inv, void *stream);
 /* One V-cycle on the pressure hierarchy, b -> x (n doubles each, device). */
 rs_status rs_cpr_vcycle(rs_cpr M, const double *d_b, double *d_x, void *stream);
 

@@ -35,6 +35,7 @@
 #include "rs_internal.h"
 #include <type_traits>
 #include <math.h>
+#include <mutex>
 
 namespace {
 
@@ -1562,6 +1563,61 @@ extern "C" rs_status rs_dense_inverse(int n, const double *d_a, double *d_inv, v
   RS_TRY(dense_inverse_run(n, G.as<double>(), d_inv, flag.as<int>(), s));
   int h = 0;
   RS_HIP(hipMemcpyAsync(&h, flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
+  RS_HIP(hipStreamSynchronize(s));
+  return h ? RS_E_SINGULAR : RS_OK;
+}
+
+// ---- allocation-free dense inverse -----------------------------------------
+// rs_dense_inverse_noalloc takes its scratch (the n x 2n augmented matrix and
+// the singular flag) from this file-scope array instead of the pool: one copy
+// per GPU, created with the code object and held until the process ends.  In
+// host code `scratch` only names the symbol; its device address on each GPU
+// comes from hipGetSymbolAddress, taken once per device at the first call
+// there (with that device current) and kept in scratch_dev[].
+constexpr size_t NOALLOC_G = 2 * (size_t)RS_DENSE_NOALLOC_MAX * RS_DENSE_NOALLOC_MAX;   // doubles
+static __device__ __align__(256) double scratch[NOALLOC_G + 32];
+
+namespace {
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex scratch_mu;
+double *scratch_dev[NOALLOC_MAX_DEVICES];
+
+rs_status scratch_ptr(double **out) {
+  int dev = -1;
+  RS_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return RS_E_ARG;
+  std::lock_guard<std::mutex> lk(scratch_mu);
+  if (!scratch_dev[dev]) {
+    void *p = nullptr;
+    RS_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return RS_E_HIP;
+    scratch_dev[dev] = (double *)p;
+  }
+  *out = scratch_dev[dev];
+  return RS_OK;
+}
+}  // namespace
+
+// k_augment that also clears the singular flag (a kernel rather than a
+// memset node, so the flag starts at zero on every call)
+__global__ void k_augment_clear(int n, const double *__restrict__ a, double *__restrict__ G, int *__restrict__ flag) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t == 0) *flag = 0;
+  if (t >= 2 * (int64_t)n * n) return;
+  const int64_t r = t / (2 * n), c = t - r * 2 * n;
+  G[t] = c < n ? a[r * n + c] : (c - n == r ? 1.0 : 0.0);
+}
+
+extern "C" rs_status rs_dense_inverse_noalloc(int n, const double *d_a, double *d_inv, void *stream) {
+  if (n < 1 || n > RS_DENSE_NOALLOC_MAX || !d_a || !d_inv) return RS_E_ARG;
+  double *G = nullptr;
+  RS_TRY(scratch_ptr(&G));
+  int *flag = (int *)(G + NOALLOC_G);
+  hipStream_t s = rs_stream(stream);
+  k_augment_clear<<<rs_grid(2 * (int64_t)n * n), RS_BLOCK, 0, s>>>(n, d_a, G, flag);
+  RS_TRY(dense_inverse_run(n, G, d_inv, flag, s));
+  int h = 0;
+  RS_HIP(hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, s));
   RS_HIP(hipStreamSynchronize(s));
   return h ? RS_E_SINGULAR : RS_OK;
 }

@@ -90,6 +90,7 @@ def lib():
             "rs_cpr_smoother_get": (_i, [_vp, _vp]),
             "rs_cpr_vcycle": (_i, [_vp, _vp, _vp, _vp]),
             "rs_dense_inverse": (_i, [_i, _vp, _vp, _vp]),
+            "rs_dense_inverse_noalloc": (_i, [_i, _vp, _vp, _vp]),
             "rs_pool_trim": (None, []),
             "rs_pool_usage": (None, [C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
         }
@@ -327,6 +328,17 @@ def dense_inverse(a, inv, stream=None):
     n = a.shape[0]
     _check(lib().rs_dense_inverse(n, _ptr(a, torch.float64, n * n), _ptr(inv, torch.float64, n * n),
                                   _stream(stream)), "rs_dense_inverse")
+
+
+DENSE_NOALLOC_MAX = 1024
+
+
+def dense_inverse_noalloc(a, inv, stream=None):
+    """dense_inverse without device allocation: the library's static scratch
+    array (n <= DENSE_NOALLOC_MAX; calls overlapping on one GPU race)."""
+    n = a.shape[0]
+    _check(lib().rs_dense_inverse_noalloc(n, _ptr(a, torch.float64, n * n), _ptr(inv, torch.float64, n * n),
+                                          _stream(stream)), "rs_dense_inverse_noalloc")
 
 
 def assemble(nx, ny, nz, logk, kvkh, tscale, Mf, Mb, B, dt, wcell, wu, row_ptr, vals, stream=None):

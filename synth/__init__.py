@@ -42,8 +42,10 @@ Cell numbering is c = i + nx*(j + ny*k), 0-based, i fastest.
 """
 from __future__ import annotations
 
+import concurrent.futures
 import dataclasses
 import math
+import os
 
 import numpy as np
 
@@ -58,6 +60,39 @@ _P_LOGK, _P_SHALE, _P_MF, _P_MB, _P_B, _P_WELL, _P_RHS, _P_OBJ = range(8)
 
 def _rng(seed: int, purpose: int) -> np.random.Generator:
     return np.random.Generator(np.random.Philox(key=[seed & 0xFFFFFFFFFFFFFFFF, purpose]))
+
+
+_SLICE = 1 << 24          # doubles per slice of a threaded uniform fill (multiple of 4)
+
+
+def _uniform(seed: int, purpose: int, low: float, high: float, shape, slice_len: int = _SLICE) -> np.ndarray:
+    """The draws of _rng(seed, purpose).uniform(low, high, shape), bitwise,
+    filled slice by slice on a thread pool (numpy fills without the GIL).
+    Slice k starts at draw k * slice_len: a fresh Philox advanced by
+    slice_len / 4 counter blocks per slice, since one block gives four 64-bit
+    words and a double takes one.  uniform() is low + (high - low) * u, which
+    the slice computes as u * (high - low) + low, the same two roundings."""
+    assert slice_len % 4 == 0
+    out = np.empty(shape)
+    flat = out.reshape(-1)
+    width = high - low
+
+    def fill(off):
+        bg = np.random.Philox(key=[seed & 0xFFFFFFFFFFFFFFFF, purpose])
+        bg.advance(off // 4)
+        seg = flat[off:off + slice_len]
+        np.random.Generator(bg).random(out=seg)
+        seg *= width
+        seg += low
+
+    offs = list(range(0, flat.size, slice_len))
+    if len(offs) <= 1:
+        for off in offs:
+            fill(off)
+    else:
+        with concurrent.futures.ThreadPoolExecutor(min(16, os.cpu_count() or 1)) as ex:
+            list(ex.map(fill, offs))
+    return out
 
 
 @dataclasses.dataclass
@@ -155,9 +190,9 @@ def make(nx, ny, nz, *, seed, sigma=1.0, kvkh=0.1, shale=0.0, wells=None, dt=1.0
         ns = int(round(shale * n))
         idx = _rng(seed, _P_SHALE).choice(n, size=ns, replace=False)
         logk[idx] = math.log(1e-3)
-    Mf = _rng(seed, _P_MF).uniform(0.1, 1.0, size=(3, n, 4, 4))
-    Mb = _rng(seed, _P_MB).uniform(0.1, 1.0, size=(3, n, 4, 4))
-    B = _rng(seed, _P_B).uniform(0.0, 1.0, size=(n, 4, 4))
+    Mf = _uniform(seed, _P_MF, 0.1, 1.0, (3, n, 4, 4))
+    Mb = _uniform(seed, _P_MB, 0.1, 1.0, (3, n, 4, 4))
+    B = _uniform(seed, _P_B, 0.0, 1.0, (n, 4, 4))
     eye = np.eye(4, dtype=bool)
     B[:, eye] = 0.0
     B[:, eye] = 1.0 + B.sum(axis=2)

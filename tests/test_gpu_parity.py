@@ -242,10 +242,13 @@ def test_cpr_apply_fpf(method, smoother, dims):
 @pytest.mark.parametrize("method,smoother", [(rs.FRS, rs.SM_RAS), (rs.FRS_ABF, rs.SM_DILU), (rs.ABF, rs.SM_BJ)])
 def test_fpf_solves(method, smoother, prec):
     """GMRES and BiCGSTAB with CPR-FPF on the 20x20x10 workload: true residual
-    1e-8, solution against the oracle's, iteration counts equal in FP64."""
+    1e-8, solution within 1e-6 of the oracle's solve at the same rtol and of
+    a tight (1e-13) oracle solution, iteration counts equal in FP64."""
     p = synth.config(0)
     A = oracle.assemble(p)
     Mo = oracle.CPR(A, method=method, smoother=smoother, stages=3)
+    xt, it = oracle.gmres(A, p.b, Mo, rtol=1e-13)
+    assert it["status"] == 0
     B = upload(A)
     M = rs.cpr_setup(B, rs.decouple(B, method, prec), rs.cpr_opts(smoother=smoother, stages=3))
     nb = np.linalg.norm(p.b)
@@ -261,7 +264,7 @@ def test_fpf_solves(method, smoother, prec):
         xg = x.cpu().numpy()
         true = np.linalg.norm(p.b - oracle.spmv(A, xg)) / nb
         assert info["return"] == 0 and true <= 1e-8, solver
-        assert relerr(xg, xo) <= 1e-5, solver
+        assert relerr(xg, xo) <= 1e-6 and relerr(xg, xt) <= 1e-6, solver
         if prec == 64:
             assert info["iters"] == io["iters"], solver
 
@@ -292,7 +295,9 @@ def test_gmres_solution(cfg, prec, smoother):
     xg = x.cpu().numpy()
     true = np.linalg.norm(p.b - oracle.spmv(A, xg)) / np.linalg.norm(p.b)
     assert info["return"] == 0 and true <= 1e-8 and abs(true - info["relres"]) <= 1e-12
-    assert relerr(xg, xo) <= 1e-5
+    # against the oracle's solution at rtol 1e-13: the benchmark spec's 1e-6
+    # (measured under 1e-10 on this workload)
+    assert relerr(xg, xo) <= 1e-6
     if prec == 64:
         xo8, io8 = oracle.gmres(A, p.b, oracle.CPR(A, smoother=smoother), rtol=1e-8)
         assert info["iters"] == io8["iters"]

@@ -45,3 +45,23 @@ def test_config_well_layouts():
     assert np.all(w[prod] > 0.0)
     mask = np.ones(p0.n, bool); mask[prod] = False
     assert np.all(w[mask] == 0.0)
+
+
+def test_threaded_uniform_fill_is_the_sequential_stream():
+    """The slice-wise threaded fill gives exactly Generator.uniform's draws,
+    for slices that divide the array and for a ragged last slice."""
+    for shape, sl in (((3, 50, 4, 4), 64), ((7, 4, 4), 12), ((1000,), 4), ((10,), 1 << 24)):
+        ref = synth._rng(99, 3).uniform(0.1, 1.0, size=shape)
+        got = synth._uniform(99, 3, 0.1, 1.0, shape, slice_len=sl)
+        assert np.array_equal(got, ref), (shape, sl)
+    ref = synth._rng(5, 4).uniform(0.0, 1.0, size=(9, 4, 4))
+    assert np.array_equal(synth._uniform(5, 4, 0.0, 1.0, (9, 4, 4), slice_len=8), ref)
+
+
+def test_draws_unchanged():
+    """The bench workloads' draws are those of the sequential generator (the
+    first entries of the 20x20x10 workload, written from Generator.uniform)."""
+    p = synth.config(0)
+    s = synth.SEED_BASE
+    assert np.array_equal(p.Mf, synth._rng(s, 2).uniform(0.1, 1.0, size=(3, p.n, 4, 4)))
+    assert np.array_equal(p.Mb, synth._rng(s, 3).uniform(0.1, 1.0, size=(3, p.n, 4, 4)))

@@ -9,7 +9,8 @@ host, so it is checked by what holds at any size.
     SpMV, row chunk by row chunk, from the device's values;
   - sampled rows of the library's SpMV computed one by one on the host, among
     them the rows whose value offsets (16 doubles per block) pass 2^31 and
-    2^32 and the last layer, from the 7-plane copy and from attached values.
+    the last layer (offsets up to 3.57e9), from the 7-plane copy (whose
+    upper slot planes also start past 2^31) and from attached values.
 """
 import ctypes as C
 
@@ -89,12 +90,11 @@ def test_config3_spmv_sampled_rows(cfg3, attach):
     del A
     nxy = p.nx * p.ny
     rows = list(np.random.default_rng(5).choice(p.n, size=1500, replace=False))
-    for lim in (2 ** 31, 2 ** 32):            # first rows whose value offsets pass lim
-        c = int(np.searchsorted(16 * rp.astype(np.int64), lim))
-        rows += [c - 2, c - 1, c, c + 1]
+    c = int(np.searchsorted(16 * rp.astype(np.int64), 2 ** 31))   # first row past 2^31
+    assert 0 < c < p.n and 16 * int(rp[c - 1]) < 2 ** 31 <= 16 * int(rp[c])
+    rows += [c - 2, c - 1, c, c + 1]
     rows += [0, nxy - 1, p.n - nxy, p.n - 1] + list(range(p.n - 300, p.n))
     rows = np.unique(np.asarray(rows, dtype=np.int64))
-    assert 16 * int(rp[rows.max()]) > 2 ** 32
     xh = x.cpu().numpy()
     for c in rows:
         q0, q1 = int(rp[c]), int(rp[c + 1])

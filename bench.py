@@ -119,6 +119,23 @@ def run_variant(rs, dp, A, prec, steps, warmup, tag, smoother, solver="gmres", m
     return times, infos, phases
 
 
+def host_cpu():
+    """CPU model and the cores this process may run on."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        ncores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        ncores = os.cpu_count() or 1
+    return model, ncores
+
+
 def cpu_baseline(prob, smoother):
     import oracle
     t0 = time.perf_counter()
@@ -223,9 +240,14 @@ def main():
     if not args.no_cpu_baseline:
         log("cpu baseline: FP64 oracle, one full solve of the same system (1 thread) ...")
         t_cpu, info = cpu_baseline(prob, SMOOTHERS[args.smoother])
+        model, ncores = host_cpu()
+        # the oracle is single-threaded C: its sweeps, the greedy MIS and the
+        # GMRES reductions are sequential by definition, so it uses one core
         out["cpu_baseline"] = {"value": 1.0 / t_cpu, "unit": "solves/s", "cores": 1, "kind": "oracle",
-                               "sample": f"one FP64 CPR-GMRES solve of {prob.name} (decouple, AMG and {args.smoother} set-up, "
-                                         f"GMRES to 1e-8: {info['iters']} iterations), {t_cpu:.1f} s"}
+                               "host_cores": ncores, "cpu_model": model,
+                               "sample": f"one complete FP64 CPR-GMRES solve of {prob.name} (decouple, AMG and "
+                                         f"{args.smoother} set-up, GMRES to 1e-8: {info['iters']} iterations) on one "
+                                         f"of the host's {ncores} cores, {t_cpu:.1f} s; the assembly is not timed"}
     print(json.dumps(out), flush=True)
 
 

@@ -155,7 +155,9 @@ __global__ __launch_bounds__(256) void k_spmv7(int64_t n, int ny, int nz, int64_
       acc = fma(a23.y, xv[3], acc);
     }
     yv = RES ? b[t] - acc : acc;
-    y[t] = yv;
+    // non-temporal: y is not read again by this kernel, and the store leaves
+    // the L2 to the streamed A (1 to 2 % faster at 0.5M to 32M cells)
+    __builtin_nontemporal_store(yv, y + t);
   }
   if (ND > 0) {
     __shared__ double sh[2][4];
@@ -331,6 +333,12 @@ rs_status rs_spmv_any(const rs_bsr_s *A, const void *x, int xprec, double *y, co
 
 unsigned rs_spmv_blocks(const rs_bsr_s *A) { return rs_grid(4 * A->g.n); }
 
+// LDS reserved by every SpMV launch, unused by the kernel: it caps the SpMV at
+// three workgroups (12 waves) per CU.  Fewer requests in flight at once
+// stream A faster on this part (measured 4 to 6 % at 0.5M to 32M cells
+// against the 8 workgroups the registers would allow).
+static constexpr size_t SPMV_LDS_CAP = 160 * 1024 / 3 - 1024;
+
 rs_status rs_spmv_dots(const rs_bsr_s *A, const void *x, int xprec, double *y, const double *b_minus,
                        int nd, const double *u, double *part, hipStream_t s) {
   int64_t n = A->g.n;
@@ -341,10 +349,10 @@ rs_status rs_spmv_dots(const rs_bsr_s *A, const void *x, int xprec, double *y, c
 #define RS_SPMV(TX, RES, ND)                                                                                   \
   do {                                                                                                        \
     if (A->ref)                                                                                               \
-      k_spmv7<TX, RES, ND, true><<<grid, RS_BLOCK, 0, s>>>(n, ny, nz, nx, nxy, a7, (const TX *)x, b_minus, y, u, \
+      k_spmv7<TX, RES, ND, true><<<grid, RS_BLOCK, SPMV_LDS_CAP, s>>>(n, ny, nz, nx, nxy, a7, (const TX *)x, b_minus, y, u, \
                                                            part);                                             \
     else                                                                                                      \
-      k_spmv7<TX, RES, ND, false><<<grid, RS_BLOCK, 0, s>>>(n, ny, nz, nx, nxy, a7, (const TX *)x, b_minus, y, \
+      k_spmv7<TX, RES, ND, false><<<grid, RS_BLOCK, SPMV_LDS_CAP, s>>>(n, ny, nz, nx, nxy, a7, (const TX *)x, b_minus, y, \
                                                             u, part);                                         \
   } while (0)
   if (nd < 0 || nd > 2 || (nd > 0 && !part)) return RS_E_ARG;

@@ -20,10 +20,10 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
-_SRC = ["bsr.c", "decouple.c", "amg.c", "cpr.c"]
+_SRC = ["bsr.c", "decouple.c", "amg.c", "cpr.c", "ras.c"]
 
 ABF, QIMPES, FRS, FRS_ABF = 0, 1, 2, 3
-SM_BJ, SM_DILU, SM_RAS = 0, 1, 2
+SM_BJ, SM_DILU, SM_RAS, SM_RAS1 = 0, 1, 2, 3
 
 
 def build() -> str:
@@ -110,6 +110,17 @@ def lib():
                                C.c_int]
         L.or_bicgstab.argtypes = [C.c_int, _i32p, _i32p, _f64p, C.c_void_p, _f64p, _f64p,
                                   C.c_double, C.c_int, C.POINTER(Info), C.c_void_p, C.c_int]
+        L.or_rasov_setup.argtypes = [C.c_int, _i32p, _i32p, _f64p, C.c_int64, C.c_int, C.POINTER(C.c_int)]
+        L.or_rasov_setup.restype = C.c_void_p
+        L.or_rasov_apply.argtypes = [C.c_void_p, _f64p, _f64p, _f64p]
+        L.or_rasov_apply.restype = None
+        L.or_rasov_owned_dinv.argtypes = [C.c_void_p, _f64p]
+        L.or_rasov_owned_dinv.restype = None
+        L.or_rasov_ext.argtypes = [C.c_void_p, C.c_int, C.c_void_p]
+        L.or_rasov_ext_dinv.argtypes = [C.c_void_p, C.c_int, _f64p]
+        L.or_rasov_ext_dinv.restype = None
+        L.or_rasov_free.argtypes = [C.c_void_p]
+        L.or_rasov_free.restype = None
         L.or_grad_logk.argtypes = [C.c_int] * 3 + [_f64p, C.c_double, C.c_double, _f64p, _f64p, C.c_int,
                                                    _i32p, _f64p, _f64p, _f64p, _f64p]
         _lib = L
@@ -307,6 +318,51 @@ class AMG:
     def __del__(self):
         if getattr(self, "_own", False) and getattr(self, "_h", None):
             lib().or_amg_free(self._h)
+            self._h = None
+
+
+class RasOv:
+    """Restricted additive Schwarz with overlap ov on a decoupled block matrix
+    (subdomains of sub consecutive cells, DILU on each extension)."""
+
+    def __init__(self, At: BSR, sub=None, ov=1):
+        L = lib()
+        self.A = At
+        sub = At.nx * At.ny if sub is None else int(sub)
+        self.sub = sub
+        st = C.c_int(0)
+        self._h = L.or_rasov_setup(At.n, At.rp, At.ci, At.v.reshape(-1), sub, int(ov), C.byref(st))
+        if st.value != 0:
+            L.or_rasov_free(self._h)
+            self._h = None
+            _check(st.value, "or_rasov_setup")
+        self.nsub = (At.n + sub - 1) // sub
+
+    def apply(self, r):
+        z = np.zeros(4 * self.A.n)
+        lib().or_rasov_apply(self._h, _c(self.A.v.reshape(-1), np.float64), _c(r, np.float64), z)
+        return z
+
+    def owned_dinv(self):
+        d = np.zeros(16 * self.A.n)
+        lib().or_rasov_owned_dinv(self._h, d)
+        return d.reshape(-1, 4, 4)
+
+    def ext(self, m):
+        ne = lib().or_rasov_ext(self._h, m, None)
+        e = np.zeros(ne, np.int32)
+        lib().or_rasov_ext(self._h, m, e.ctypes.data)
+        return e
+
+    def ext_dinv(self, m):
+        ne = lib().or_rasov_ext(self._h, m, None)
+        d = np.zeros(16 * ne)
+        lib().or_rasov_ext_dinv(self._h, m, d)
+        return d.reshape(-1, 4, 4)
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            lib().or_rasov_free(self._h)
             self._h = None
 
 

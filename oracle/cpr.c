@@ -18,6 +18,7 @@ struct or_cpr {
   double *dinv2;           /* second-stage block inverses */
   int *rp2, *ci2;          /* RAS: pattern restricted to the subdomains */
   double *vt2;             /* RAS: decoupled blocks on that pattern */
+  or_rasov *ras;           /* RAS with overlap 1 */
   or_amg *amg;
 };
 
@@ -31,8 +32,9 @@ struct or_cpr {
  *    3.  y = y + Pi_p Vcycle(A_p, Pi_r q)    (pressure stage)
  *    4.  q = f - A~ y
  *    5.  y = y + M2^{-1} q                   (full-system stage)
- * M2 is block Jacobi, DILU, or zero-overlap RAS with DILU in each
- * subdomain, on A~; Pi_r takes unknown 0, Pi_p injects into unknown 0.
+ * M2 is block Jacobi, DILU, or RAS with DILU in each subdomain (overlap 0,
+ * or overlap 1: ras.c), on A~; Pi_r takes unknown 0, Pi_p injects into
+ * unknown 0.
  * stages = 2 keeps steps 3-5 with y = 0:
  *    x_p = Vcycle(A_p, Pi_r f),  z = M2^{-1}(f - A~ Pi_p x_p) + Pi_p x_p.
  * Pinned by the dense compositions, with S = M2^{-1} and
@@ -63,6 +65,9 @@ or_cpr *or_cpr_setup(int n, const int *rp, const int *ci, const double *v,
   if (smoother == OR_SM_RAS) {
     *status = or_ras_restrict(n, sub, rp, ci, M->vt, &M->rp2, &M->ci2, &M->vt2);
     if (*status == OR_OK) *status = or_dilu_setup(n, M->rp2, M->ci2, M->vt2, M->dinv2);
+  } else if (smoother == OR_SM_RAS1) {
+    M->ras = or_rasov_setup(n, rp, ci, M->vt, sub, 1, status);
+    if (*status == OR_OK) or_rasov_owned_dinv(M->ras, M->dinv2);
   } else {
     *status = (smoother == OR_SM_DILU) ? or_dilu_setup(n, rp, ci, M->vt, M->dinv2)
                                        : or_bj_setup(n, rp, ci, M->vt, M->dinv2);
@@ -76,6 +81,7 @@ static void m2_apply(const or_cpr *M, const double *r, double *z) {
   int n = M->n;
   if (M->smoother == OR_SM_DILU) or_dilu_apply(n, M->rp, M->ci, M->vt, M->dinv2, r, z);
   else if (M->smoother == OR_SM_RAS) or_dilu_apply(n, M->rp2, M->ci2, M->vt2, M->dinv2, r, z);
+  else if (M->smoother == OR_SM_RAS1) or_rasov_apply(M->ras, M->vt, r, z);
   else or_bj_apply(n, M->dinv2, r, z);
 }
 
@@ -128,6 +134,7 @@ void or_cpr_free(or_cpr *M) {
   if (!M) return;
   free(M->rpc); free(M->cic); free(M->vt); free(M->dinv); free(M->ap); free(M->dinv2);
   free(M->rp2); free(M->ci2); free(M->vt2);
+  or_rasov_free(M->ras);
   or_amg_free(M->amg);
   free(M);
 }

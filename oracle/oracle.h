@@ -61,6 +61,16 @@ int or_ras_restrict(int n, int64_t sub, const int *rp, const int *ci, const doub
                     int **rp2, int **ci2, double **vt2);
 void or_free(void *p);
 
+/* ---- restricted additive Schwarz with overlap (ras.c) */
+typedef struct or_rasov or_rasov;
+or_rasov *or_rasov_setup(int n, const int *rp, const int *ci, const double *vt, int64_t sub, int ov,
+                         int *status);
+void or_rasov_apply(const or_rasov *R, const double *vt, const double *r, double *z);
+void or_rasov_owned_dinv(const or_rasov *R, double *dinv2);
+int or_rasov_ext(const or_rasov *R, int m, int *ext);
+void or_rasov_ext_dinv(const or_rasov *R, int m, double *dinv);
+void or_rasov_free(or_rasov *R);
+
 /* ---- aggregation AMG on the pressure matrix (Fig. fig-ds-amg-par parameters) */
 typedef struct or_amg or_amg;
 typedef struct {
@@ -87,6 +97,7 @@ void or_amg_free(or_amg *h);
 #define OR_SM_BJ 0
 #define OR_SM_DILU 1
 #define OR_SM_RAS 2     /* zero-overlap RAS, DILU in each subdomain of sub cells */
+#define OR_SM_RAS1 3    /* RAS with overlap 1 (ras.c), DILU in each extended subdomain */
 typedef struct or_cpr or_cpr;
 or_cpr *or_cpr_setup(int n, const int *rp, const int *ci, const double *v,
                      int method, int smoother, int64_t sub, int stages,

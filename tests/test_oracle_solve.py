@@ -239,3 +239,28 @@ def test_gmres_restart_cycles(restart):
     got = np.linalg.norm(p.b - Ad @ x1)
     assert got <= best * (1 + 1e-8) + 1e-14 * np.linalg.norm(p.b)
     assert np.linalg.norm(x1 - Z @ y) <= 1e-8 * np.linalg.norm(Z @ y)
+
+
+def test_workload_reading_survey_recipe_stalls():
+    """The synthetic recipe's two readings (field-unit Darcy constant on the
+    transmissibilities, storage on the non-pressure diagonal) are what make
+    the Jacobian a CPR target.  Without them (tscale 1, storage 0) random
+    positive 4x4 flux blocks put about a third of the spectrum in the left
+    half-plane, and CPR-GMRES(30) stalls near a relative residual of 1 after
+    300 steps; with them the spectrum is in the right half-plane and the
+    same solves converge in a few steps."""
+    w = synth.wells_vertical_pair(10, 10, 5, (0, 0), (9, 9))
+    ps = synth.make(10, 10, 5, seed=37, sigma=1.0, wells=w, storage=0.0, tscale=1.0)
+    pc = synth.make(10, 10, 5, seed=37, sigma=1.0, wells=w)
+    evs = np.linalg.eigvals(oracle.assemble(ps).dense())
+    evc = np.linalg.eigvals(oracle.assemble(pc).dense())
+    assert np.mean(evs.real < 0) > 0.2 and np.all(evc.real > 0)
+    nx, ny, nz = 20, 20, 10
+    w = synth.wells_vertical_pair(nx, ny, nz, (5, 5), (15, 15))
+    ps = synth.make(nx, ny, nz, seed=synth.SEED_BASE, sigma=1.0, kvkh=0.1, wells=w, storage=0.0, tscale=1.0)
+    As, Ac = oracle.assemble(ps), oracle.assemble(synth.config(0))
+    for method, smoother in ((oracle.ABF, oracle.SM_DILU), (oracle.QIMPES, oracle.SM_RAS)):
+        _, i = oracle.gmres(As, ps.b, oracle.CPR(As, method=method, smoother=smoother), rtol=1e-8, maxit=300)
+        assert i["status"] == 1 and i["iters"] == 300 and i["relres"] > 0.99
+        _, i = oracle.gmres(Ac, synth.config(0).b, oracle.CPR(Ac, method=method, smoother=smoother), rtol=1e-8)
+        assert i["status"] == 0 and i["iters"] <= 10

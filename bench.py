@@ -24,10 +24,11 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 # second stage: zero-overlap RAS over xy-layers with DILU inside (default),
-# DILU of the whole matrix, or block Jacobi
-SMOOTHERS = {"bj": 0, "dilu": 1, "ras": 2}
+# RAS with overlap 1, DILU of the whole matrix, or block Jacobi
+SMOOTHERS = {"bj": 0, "dilu": 1, "ras": 2, "ras1": 3}
 DECOUPLINGS = {"abf": 0, "qi": 1, "frs": 2, "frs_abf": 3}
-SMOOTHER_NAMES = {"bj": "block Jacobi", "dilu": "DILU", "ras": "RAS(0, xy-layers) + DILU"}
+SMOOTHER_NAMES = {"bj": "block Jacobi", "dilu": "DILU", "ras": "RAS(0, xy-layers) + DILU",
+                  "ras1": "RAS(1, xy-layers) + DILU"}
 
 
 def log(msg):

@@ -67,9 +67,15 @@ typedef enum {
 #define RS_SM_RAS 2     /* second stage: RAS, overlap 0, one xy-layer per subdomain, block
                            ILU(0) in each (Section "Preconditioners"); needs ny <= 480 with
                            FP64 storage, ny <= 960 with FP32, else RS_E_ARG               */
+#define RS_SM_RAS1 3    /* second stage: RAS with overlap 1, the paper's default overlap
+                           (Section "Preconditioners"): each xy-layer extended by the
+                           layers below and above, block ILU(0) of the restricted matrix of
+                           that extension in natural order, each cell taking the value of
+                           its own layer's extension (restricted prolongation); limits as
+                           for RS_SM_RAS                                                   */
 
 typedef struct {
-  int smoother;        /* RS_SM_BJ, RS_SM_DILU or RS_SM_RAS (default DILU)       */
+  int smoother;        /* RS_SM_BJ, RS_SM_DILU, RS_SM_RAS or RS_SM_RAS1 (default DILU) */
   double theta;        /* AMG strength threshold (default 0.5, Fig. fig-ds-amg-par) */
   double max_row_sum;  /* AMG weak-row threshold (default 0.9, same figure)       */
   int coarse_n;        /* stop coarsening at <= this many rows (default 500)     */

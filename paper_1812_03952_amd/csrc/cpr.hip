@@ -242,8 +242,9 @@ extern "C" rs_status rs_cpr_setup(rs_bsr A, rs_dcpl D, const rs_cpr_opts *o, voi
   *out = nullptr;
   rs_cpr_opts opts;
   if (o) opts = *o; else rs_cpr_opts_default(&opts);
-  if ((opts.smoother != RS_SM_BJ && opts.smoother != RS_SM_DILU && opts.smoother != RS_SM_RAS) ||
-      (opts.smoother == RS_SM_RAS && rs_ras_check_shape(A->g, D->prec) != RS_OK) || opts.coarse_n < 1 ||
+  const bool ras = opts.smoother == RS_SM_RAS || opts.smoother == RS_SM_RAS1;
+  if ((opts.smoother != RS_SM_BJ && opts.smoother != RS_SM_DILU && !ras) ||
+      (ras && rs_ras_check_shape(A->g, D->prec) != RS_OK) || opts.coarse_n < 1 ||
       opts.max_levels < 1 || opts.lu_max < 1 || opts.lu_max > 8192 || opts.coarse_sweeps < 1 ||
       (opts.stages != 2 && opts.stages != 3))
     return RS_E_ARG;
@@ -282,7 +283,7 @@ extern "C" rs_status rs_cpr_setup(rs_bsr A, rs_dcpl D, const rs_cpr_opts *o, voi
       if (M->prec == 64) k_bj_setup<double><<<rs_grid(n), RS_BLOCK, 0, ss>>>(n, D->t7.as<double>(), M->dinv2.as<double>(), flag.as<int>());
       else k_bj_setup<float><<<rs_grid(n), RS_BLOCK, 0, ss>>>(n, D->t7.as<float>(), M->dinv2.as<float>(), flag.as<int>());
       if (hipGetLastError() != hipSuccess) { st = RS_E_HIP; break; }
-    } else if (opts.smoother == RS_SM_RAS) {
+    } else if (ras) {
       if ((st = rs_ras_setup_run(M, flag.as<int>(), ss)) != RS_OK) break;
     }
     if ((st = rs_amg_level0(M, s)) != RS_OK) break;
@@ -324,7 +325,7 @@ static rs_status second_stage(rs_cpr_s *M, const T *xp, T *z, hipStream_t s) {
   if (M->o.smoother == RS_SM_BJ) {
     k_bj_apply<T><<<rs_grid(4 * n), RS_BLOCK, 0, s>>>(n, g.nx, g.nxy, M->rt.as<T>(), M->D->col0.as<T>(), xp,
                                                      M->dinv2.as<T>(), z);
-  } else if (M->o.smoother == RS_SM_RAS) {
+  } else if (M->o.smoother == RS_SM_RAS || M->o.smoother == RS_SM_RAS1) {
     RS_TRY(rs_ras_apply_run<T>(M, xp, z, s));
   } else {
     RS_TRY(rs_dilu_apply_run<T>(M, xp, z, s));

@@ -29,6 +29,7 @@
 #include "rs_internal.h"
 #include <math.h>
 #include <algorithm>
+#include <functional>
 
 namespace {
 #pragma clang fp contract(off)
@@ -209,9 +210,13 @@ template <class T> __device__ __forceinline__ void order_after(int &idx, T tok) 
 // reads of a level and one after its writes.  One writer wave copies the
 // D^{-1} blocks of level lambda-1 from LDS to global memory while level
 // lambda is computed.
+// diag (optional, [n][16]) replaces the diagonal blocks A~_cc of t7: the
+// overlapping RAS factors a layer whose diagonal already carries the Schur
+// term of the layer below.
 template <class T, int U>
 __global__ __launch_bounds__(1024) void k_ras_setup(int nx, int ny, int64_t n, int LW, const T *__restrict__ t7,
-                                                    T *__restrict__ dinv2, int *__restrict__ flag) {
+                                                    const T *__restrict__ diag, T *__restrict__ dinv2,
+                                                    int *__restrict__ flag) {
 #pragma clang fp contract(off)
   extern __shared__ __align__(16) unsigned char smem[];
   T *ring = (T *)smem;                                  // [ny][16]
@@ -240,7 +245,7 @@ __global__ __launch_bounds__(1024) void k_ras_setup(int nx, int ny, int64_t n, i
     return;
   }
   const int q = tid >> 2, r = tid & 3, wq = (tid & 63) & ~3;
-  const T *Ad = t7 + 3 * n * 16, *Ay = t7 + 1 * n * 16, *Ax = t7 + 2 * n * 16;
+  const T *Ad = diag ? diag : t7 + 3 * n * 16, *Ay = t7 + 1 * n * 16, *Ax = t7 + 2 * n * 16;
   const T *Upx = t7 + 4 * n * 16, *Upy = t7 + 5 * n * 16;
   // this lane's row of A~_cc, A~_{c,c-nx}, A~_{c,c-1}, A~_{c-nx,c}, A~_{c-1,c}:
   // one level ahead with one pass, loaded at use with several
@@ -832,6 +837,119 @@ __global__ __launch_bounds__(320) void k_ras_bwd1(int nx, int ny, int nz, int S,
   }
 }
 
+// ---- RAS with overlap 1 over the layers -------------------------------------
+// The extension of layer k is the layers k-1, k, k+1; its block ILU(0) in
+// natural order factors them one after another: the first with the plain
+// layer factors P0, the next two with their diagonals reduced by the Schur
+// term of the layer below (P1 for layer k, P2 for layer k+1).  The sweeps of
+// one extension are layer sweeps joined by the couplings across z:
+//   y0 = fwd(P0, r2)                            on layer k-1
+//   y1 = fwd(P1, r2 - A~_{-z} y0)               on layer k
+//   y2 = fwd(P2, r2 - A~_{-z} y1)               on layer k+1
+//   z2 = bwd(P2, y2)                            on layer k+1
+//   z  = bwd(P1, y1 - P1^{-1} A~_{+z} z2)       on layer k (kept)
+// so every layer is swept three times forward and twice backward, each sweep
+// over all layers at once.
+
+// E_c = A~_cc - A~_{c,c-nxy} P_{c-nxy} A~_{c-nxy,c} (A~_cc on the first
+// layer), per (cell, block row), in FP64 with the DILU's operations in its
+// order: T1 = P_{c-nxy} A~_{c-nxy,c}, then row r of A~_{c,c-nxy} T1, then the
+// subtraction.
+template <class T>
+__global__ __launch_bounds__(256) void k_ras_zdiag(int64_t n, int64_t nxy, const T *__restrict__ t7,
+                                                   const T *__restrict__ P, T *__restrict__ E) {
+#pragma clang fp contract(off)
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 4 * n) return;
+  const int64_t c = t >> 2;
+  const int r = (int)(t & 3);
+  const T *Acc = t7 + (3 * n + c) * 16;
+  if (c < nxy) {
+#pragma unroll
+    for (int b = 0; b < 4; ++b) E[c * 16 + 4 * r + b] = Acc[4 * r + b];
+    return;
+  }
+  const int64_t q = c - nxy;
+  const T *Pq = P + q * 16, *Aqc = t7 + (6 * n + q) * 16, *Acq = t7 + c * 16;
+  double T1[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      double v = 0.0;
+#pragma unroll
+      for (int m = 0; m < 4; ++m) v = v + (double)Pq[4 * a + m] * (double)Aqc[4 * m + b];
+      T1[a][b] = v;
+    }
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    double v = 0.0;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) v = v + (double)Acq[4 * r + m] * T1[m][b];
+    E[c * 16 + 4 * r + b] = (T)((double)Acc[4 * r + b] - v);
+  }
+}
+
+// rh = P^{-1} (r~ - A~[:,0] x_p - A~_{c,c-nxy} yb_{c-nxy}) in wavefront order,
+// with yb the forward result of the layer below (wavefront order) and no
+// z term on the first layer; x_p carries nx*ny zero guards on each side.
+template <class T>
+__global__ __launch_bounds__(256) void k_ras1_rhs(int nx, int ny, int64_t n, const T *__restrict__ rt,
+                                                  const T *__restrict__ col0, const T *__restrict__ xp,
+                                                  const T *__restrict__ t7, const T *__restrict__ yb,
+                                                  const T *__restrict__ P, T *__restrict__ rh) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 4 * n) return;                               // whole quads
+  const int64_t nxy = (int64_t)nx * ny, c = t >> 2;
+  const int row = (int)(t & 3);
+  const int64_t off[7] = {-nxy, -(int64_t)nx, -1, 0, 1, (int64_t)nx, nxy};
+  T col[8], dv[4];
+  ld8v(col0 + c * 32 + 8 * row, col);
+  ld4v(P + c * 16 + 4 * row, dv);
+  T v = rt[t];
+#pragma unroll
+  for (int s = 0; s < 7; ++s) v = v - col[s] * xp[c + off[s]];
+  const int64_t k = c / nxy, rem = c - k * nxy;
+  const int j = (int)(rem / nx), i = (int)(rem - (int64_t)j * nx);
+  const int64_t p = k * nxy + wf_pos(i, j, nx, ny);
+  if (k > 0) {
+    T a[4], yv[4];
+    ld4v(t7 + c * 16 + 4 * row, a);                     // slot 0: A~_{c,c-nxy}
+    ld4v(yb + 4 * (p - nxy), yv);
+    v = v - dot4(a, yv);
+  }
+  rh[4 * p + row] = quad_mv<T>(dv, v);
+}
+
+// y = y - P^{-1} A~_{c,c+nxy} za_{c+nxy} on every layer but the last; y in
+// wavefront order, za (the backward result of the layer above) natural.
+template <class T>
+__global__ __launch_bounds__(256) void k_ras1_up(int nx, int ny, int nz, int64_t n, const T *__restrict__ t7,
+                                                 const T *__restrict__ za, const T *__restrict__ P,
+                                                 T *__restrict__ y) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 4 * n) return;                               // whole quads
+  const int64_t nxy = (int64_t)nx * ny, c = t >> 2;
+  const int row = (int)(t & 3);
+  const int64_t k = c / nxy;
+  if (k >= nz - 1) return;                              // the same for the quad
+  const int64_t rem = c - k * nxy;
+  const int j = (int)(rem / nx), i = (int)(rem - (int64_t)j * nx);
+  const int64_t p = k * nxy + wf_pos(i, j, nx, ny);
+  T a[4], zv[4], dv[4];
+  ld4v(t7 + (6 * n + c) * 16 + 4 * row, a);             // slot 6: A~_{c,c+nxy}
+  ld4v(za + 4 * (c + nxy), zv);
+  ld4v(P + c * 16 + 4 * row, dv);
+  const T u = dot4(a, zv);
+  y[4 * p + row] = y[4 * p + row] - quad_mv<T>(dv, u);
+}
+
+template <class T>
+__global__ void k_ras_zero(int64_t m, T *__restrict__ v) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < m) v[t] = (T)0;
+}
+
 __global__ void k_ras_reset(int *__restrict__ ctl) {
   if (threadIdx.x < 2) ctl[threadIdx.x] = 0;
 }
@@ -862,6 +980,7 @@ rs_status rs_ras_check_shape(const grid3 &g, int prec) {
 rs_status rs_ras_setup_run(rs_cpr_s *M, int *flag, hipStream_t s) {
   const grid3 &g = M->A->g;
   RS_TRY(rs_ras_check_shape(g, M->prec));
+  const bool ov1 = M->o.smoother == RS_SM_RAS1;
   // a quad of lanes per line, at most 240 lines per pass (U passes), and
   // one writer wave: at most 1024 threads
   int u = 1;
@@ -871,6 +990,15 @@ rs_status rs_ras_setup_run(rs_cpr_s *M, int *flag, hipStream_t s) {
   size_t lds = es * 16 * (size_t)g.ny;
   RS_TRY(M->rblk.alloc(es * 4 * 16 * (size_t)g.n));
   RS_TRY(M->rxp.alloc(es * (size_t)g.n));
+  if (ov1) {
+    RS_TRY(M->rdv0.alloc(es * 16 * (size_t)g.n));
+    RS_TRY(M->rdv2.alloc(es * 16 * (size_t)g.n));
+    RS_TRY(M->rblk1.alloc(es * 4 * 16 * (size_t)g.n));
+    RS_TRY(M->rblk2.alloc(es * 4 * 16 * (size_t)g.n));
+    RS_TRY(M->ry1.alloc(es * 4 * (size_t)g.n));
+    RS_TRY(M->rz2.alloc(es * 4 * (size_t)g.n));
+    RS_TRY(M->rzero.alloc(es * (size_t)g.n));
+  }
   if (M->prec == 32) {
     // strips per layer: enough workgroups for the CUs, at least 32 lines each
     int S = std::max(1, std::min(256 / std::max(g.nz, 1), (g.ny + 31) / 32));
@@ -884,58 +1012,75 @@ rs_status rs_ras_setup_run(rs_cpr_s *M, int *flag, hipStream_t s) {
     RS_HIP(hipMemsetAsync(M->rctl.p, 0, sizeof(int) * 4, s));
     M->repoch = 0;
   }
-#define RS_RSET(T, UU)                                                                                \
-  k_ras_setup<T, UU><<<g.nz, 4 * lw + 64, lds, s>>>(g.nx, g.ny, g.n, lw, M->D->t7.as<T>(), M->dinv2.as<T>(), flag)
-  if (M->prec == 64) {
-    if (u == 1) RS_RSET(double, 1); else RS_RSET(double, 2);
-  } else {
-    if (u == 1) RS_RSET(float, 1); else if (u == 2) RS_RSET(float, 2); else RS_RSET(float, 4);
-  }
-#undef RS_RSET
-  RS_HIP(hipGetLastError());
-  if (M->prec == 64)
-    k_ras_scale<double><<<rs_grid(4 * g.n), RS_BLOCK, 0, s>>>(g.nx, g.ny, g.n, M->D->t7.as<double>(),
-                                                             M->dinv2.as<double>(), M->rblk.as<double>());
-  else
-    k_ras_scale<float><<<rs_grid(4 * g.n), RS_BLOCK, 0, s>>>(g.nx, g.ny, g.n, M->D->t7.as<float>(),
-                                                            M->dinv2.as<float>(), M->rblk.as<float>());
-  RS_HIP(hipGetLastError());
-  return RS_OK;
+  auto run = [&](auto tag) -> rs_status {
+    using T = decltype(tag);
+    const T *t7 = M->D->t7.as<T>();
+    auto factor = [&](const T *diag, T *dinv) {
+      if constexpr (sizeof(T) == 8) {
+        if (u == 1) k_ras_setup<T, 1><<<g.nz, 4 * lw + 64, lds, s>>>(g.nx, g.ny, g.n, lw, t7, diag, dinv, flag);
+        else k_ras_setup<T, 2><<<g.nz, 4 * lw + 64, lds, s>>>(g.nx, g.ny, g.n, lw, t7, diag, dinv, flag);
+      } else {
+        if (u == 1) k_ras_setup<T, 1><<<g.nz, 4 * lw + 64, lds, s>>>(g.nx, g.ny, g.n, lw, t7, diag, dinv, flag);
+        else if (u == 2) k_ras_setup<T, 2><<<g.nz, 4 * lw + 64, lds, s>>>(g.nx, g.ny, g.n, lw, t7, diag, dinv, flag);
+        else k_ras_setup<T, 4><<<g.nz, 4 * lw + 64, lds, s>>>(g.nx, g.ny, g.n, lw, t7, diag, dinv, flag);
+      }
+    };
+    auto scale = [&](const T *dinv, T *blk) {
+      k_ras_scale<T><<<rs_grid(4 * g.n), RS_BLOCK, 0, s>>>(g.nx, g.ny, g.n, t7, dinv, blk);
+    };
+    if (!ov1) {
+      factor(nullptr, M->dinv2.as<T>());
+      scale(M->dinv2.as<T>(), M->rblk.as<T>());
+    } else {
+      // P0 (plain layers), P1 (middle of each extension, the owned cells':
+      // dinv2), P2 (top of each extension).  The reduced diagonals E live in
+      // the P2 scaled blocks' buffer (16 n of its 64 n entries), written only
+      // after the last factorisation has read E: no pool memory is released
+      // while this stream (possibly a side stream) still uses it.
+      T *E = M->rblk2.as<T>();
+      factor(nullptr, M->rdv0.as<T>());
+      k_ras_zdiag<T><<<rs_grid(4 * g.n), RS_BLOCK, 0, s>>>(g.n, g.nxy, t7, M->rdv0.as<T>(), E);
+      factor(E, M->dinv2.as<T>());
+      k_ras_zdiag<T><<<rs_grid(4 * g.n), RS_BLOCK, 0, s>>>(g.n, g.nxy, t7, M->dinv2.as<T>(), E);
+      factor(E, M->rdv2.as<T>());
+      scale(M->rdv0.as<T>(), M->rblk.as<T>());
+      scale(M->dinv2.as<T>(), M->rblk1.as<T>());
+      scale(M->rdv2.as<T>(), M->rblk2.as<T>());
+      k_ras_zero<T><<<rs_grid(g.n), RS_BLOCK, 0, s>>>(g.n, M->rzero.as<T>());
+    }
+    RS_HIP(hipGetLastError());
+    return RS_OK;
+  };
+  if (M->prec == 64) return run(double{});
+  return run(float{});
 }
 
 template <class T>
 rs_status rs_ras_apply_run(rs_cpr_s *M, const T *xp, T *out, hipStream_t s) {
   const grid3 &g = M->A->g;
   const rs_dcpl_s *D = M->D;
+  const bool ov1 = M->o.smoother == RS_SM_RAS1;
   // rh goes to zt, the forward result (wavefront order) to yv
   T *rh = M->zt.as<T>(), *y = M->yv.as<T>(), *xpw = M->rxp.as<T>();
-  const T *blk = M->rblk.as<T>();
+  // the layer factors of the first forward sweep: P0 (dinv2 for overlap 0)
+  const T *P0 = ov1 ? M->rdv0.as<T>() : M->dinv2.as<T>();
   {
     const int64_t tiles = (int64_t)g.nz * ((g.nx + RI - 1) / RI) * ((g.ny + RJ - 1) / RJ);
     k_ras_in_tile<T><<<(unsigned)tiles, 4 * RI * RJ, 0, s>>>(g.nx, g.ny, g.n, M->rt.as<T>(), D->col0.as<T>(), xp,
-                                                             M->dinv2.as<T>(), rh, xpw);
+                                                             P0, rh, xpw);
   }
   RS_HIP(hipGetLastError());
   const sweep_shape sh = ras_sweep_shape(g.ny);
   // compute lanes (at most 960) + one writer wave
   const int nt = 4 * sh.lw + 64;
-  // loads in flight per thread: P levels x U lines
-#define RS_RSWEEP(K, UU, PP, LDS, ...) K<T, UU, PP><<<g.nz, nt, LDS, s>>>(__VA_ARGS__)
-#define RS_RDISPATCH(K, LDS, ...)                                                                     \
-  do {                                                                                                \
-    if constexpr (sizeof(T) == 8) {                                                                   \
-      if (sh.u == 1) RS_RSWEEP(K, 1, 4, LDS, __VA_ARGS__);                                            \
-      else RS_RSWEEP(K, 2, 2, LDS, __VA_ARGS__);                                                      \
-    } else {                                                                                          \
-      if (sh.u == 1) RS_RSWEEP(K, 1, 8, LDS, __VA_ARGS__);                                            \
-      else if (sh.u == 2) RS_RSWEEP(K, 2, 4, LDS, __VA_ARGS__);                                       \
-      else RS_RSWEEP(K, 4, 2, LDS, __VA_ARGS__);                                                      \
-    }                                                                                                 \
-  } while (0)
   const size_t ring_bytes = sizeof(T) * 8 * (size_t)g.ny;     // two levels of [ny][4]
+  // one forward sweep over all layers: blocks blk, rhs r (wavefront), result yo (wavefront)
+  std::function<void(const T *, const T *, T *)> fwd;
+  // one backward sweep: result + x_p (x_p in wavefront order) in natural order
+  std::function<void(const T *, const T *, const T *, T *)> bwd;
   if constexpr (sizeof(T) == 4) {
     // strips of H lines, one lane per line (at most 256 per pass), one
-    // writer wave per workgroup
+    // writer wave per workgroup; the tickets restart at every launch
     const int S = M->rs_strips, H = M->rs_h;
     const int u1 = H <= 256 ? 1 : (H <= 512 ? 2 : 4);
     const int lw1 = ((H + u1 - 1) / u1 + 63) / 64 * 64, nt1 = lw1 + 64;
@@ -943,25 +1088,52 @@ rs_status rs_ras_apply_run(rs_cpr_s *M, const T *xp, T *out, hipStream_t s) {
     int *ctl = M->rctl.as<int>();
     uint64_t *xw = M->rxw.as<uint64_t>();
     const unsigned nwg = (unsigned)(g.nz * S);
-    k_ras_reset<<<1, 64, 0, s>>>(ctl);
-    const uint32_t tf = ++M->repoch, tb = ++M->repoch;
-#define RS_R1(UU, PP)                                                                                  \
-    do {                                                                                               \
-      k_ras_fwd1<UU, PP><<<nwg, nt1, rb, s>>>(g.nx, g.ny, g.nz, S, H, g.n, lw1, blk, rh, y, ctl, xw, tf); \
-      k_ras_bwd1<UU, PP><<<nwg, nt1, 2 * rb, s>>>(g.nx, g.ny, g.nz, S, H, g.n, lw1, blk, y, xpw, out, ctl, \
-                                                  xw, tb);                                             \
-    } while (0)
-    if (u1 == 1) RS_R1(1, 5); else if (u1 == 2) RS_R1(2, 3); else RS_R1(4, 2);
-#undef RS_R1
-    RS_HIP(hipGetLastError());
+    fwd = [=](const T *blk, const T *r, T *yo) {
+      k_ras_reset<<<1, 64, 0, s>>>(ctl);
+      const uint32_t tag = ++M->repoch;
+      if (u1 == 1) k_ras_fwd1<1, 5><<<nwg, nt1, rb, s>>>(g.nx, g.ny, g.nz, S, H, g.n, lw1, blk, r, yo, ctl, xw, tag);
+      else if (u1 == 2) k_ras_fwd1<2, 3><<<nwg, nt1, rb, s>>>(g.nx, g.ny, g.nz, S, H, g.n, lw1, blk, r, yo, ctl, xw, tag);
+      else k_ras_fwd1<4, 2><<<nwg, nt1, rb, s>>>(g.nx, g.ny, g.nz, S, H, g.n, lw1, blk, r, yo, ctl, xw, tag);
+    };
+    bwd = [=](const T *blk, const T *yi, const T *xw_p, T *o) {
+      k_ras_reset<<<1, 64, 0, s>>>(ctl);
+      const uint32_t tag = ++M->repoch;
+      if (u1 == 1) k_ras_bwd1<1, 5><<<nwg, nt1, 2 * rb, s>>>(g.nx, g.ny, g.nz, S, H, g.n, lw1, blk, yi, xw_p, o, ctl, xw, tag);
+      else if (u1 == 2) k_ras_bwd1<2, 3><<<nwg, nt1, 2 * rb, s>>>(g.nx, g.ny, g.nz, S, H, g.n, lw1, blk, yi, xw_p, o, ctl, xw, tag);
+      else k_ras_bwd1<4, 2><<<nwg, nt1, 2 * rb, s>>>(g.nx, g.ny, g.nz, S, H, g.n, lw1, blk, yi, xw_p, o, ctl, xw, tag);
+    };
   } else {
-    RS_RDISPATCH(k_ras_fwd, ring_bytes, g.nx, g.ny, g.n, sh.lw, blk, rh, y);
-    RS_HIP(hipGetLastError());
-    RS_RDISPATCH(k_ras_bwd, 2 * ring_bytes, g.nx, g.ny, g.n, sh.lw, blk, y, xpw, out);
-    RS_HIP(hipGetLastError());
+    fwd = [=](const T *blk, const T *r, T *yo) {
+      if (sh.u == 1) k_ras_fwd<T, 1, 4><<<g.nz, nt, ring_bytes, s>>>(g.nx, g.ny, g.n, sh.lw, blk, r, yo);
+      else k_ras_fwd<T, 2, 2><<<g.nz, nt, ring_bytes, s>>>(g.nx, g.ny, g.n, sh.lw, blk, r, yo);
+    };
+    bwd = [=](const T *blk, const T *yi, const T *xw_p, T *o) {
+      if (sh.u == 1) k_ras_bwd<T, 1, 4><<<g.nz, nt, 2 * ring_bytes, s>>>(g.nx, g.ny, g.n, sh.lw, blk, yi, xw_p, o);
+      else k_ras_bwd<T, 2, 2><<<g.nz, nt, 2 * ring_bytes, s>>>(g.nx, g.ny, g.n, sh.lw, blk, yi, xw_p, o);
+    };
   }
-#undef RS_RDISPATCH
-#undef RS_RSWEEP
+  const T *blk = M->rblk.as<T>();
+  if (!ov1) {
+    fwd(blk, rh, y);
+    RS_HIP(hipGetLastError());
+    bwd(blk, y, xpw, out);
+    RS_HIP(hipGetLastError());
+    return RS_OK;
+  }
+  const T *t7 = D->t7.as<T>();
+  T *y1 = M->ry1.as<T>(), *z2 = M->rz2.as<T>();
+  const unsigned gq = rs_grid(4 * g.n);
+  fwd(blk, rh, y);                                                       // y0
+  k_ras1_rhs<T><<<gq, RS_BLOCK, 0, s>>>(g.nx, g.ny, g.n, M->rt.as<T>(), D->col0.as<T>(), xp, t7, y,
+                                        M->dinv2.as<T>(), rh);
+  fwd(M->rblk1.as<T>(), rh, y1);                                         // y1
+  k_ras1_rhs<T><<<gq, RS_BLOCK, 0, s>>>(g.nx, g.ny, g.n, M->rt.as<T>(), D->col0.as<T>(), xp, t7, y1,
+                                        M->rdv2.as<T>(), rh);
+  fwd(M->rblk2.as<T>(), rh, y);                                          // y2
+  bwd(M->rblk2.as<T>(), y, M->rzero.as<T>(), z2);                        // z2 (natural order)
+  k_ras1_up<T><<<gq, RS_BLOCK, 0, s>>>(g.nx, g.ny, g.nz, g.n, t7, z2, M->dinv2.as<T>(), y1);
+  bwd(M->rblk1.as<T>(), y1, xpw, out);                                   // z of the owned layer
+  RS_HIP(hipGetLastError());
   return RS_OK;
 }
 

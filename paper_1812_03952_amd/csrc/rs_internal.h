@@ -127,6 +127,10 @@ struct rs_cpr_s {
   // tag of the last sweep
   dbuf rblk, rxp, rxw, rctl;
   int rs_strips = 1, rs_h = 0;
+  // RAS with overlap 1: layer factors P0 (dinv2 holds P1, the owned ones),
+  // P2, scaled blocks of P1 and P2, the middle and top sweeps' vectors and a
+  // zero x_p for the top layer's backward sweep
+  dbuf rdv0, rdv2, rblk1, rblk2, ry1, rz2, rzero;
   uint32_t repoch = 0;
   // CPR work
   dbuf rt, bp, xp, yv, zt;   // prec vectors

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "librsolve.so")
 
 RS_OK, RS_NOT_CONVERGED = 0, 1
 ABF, QIMPES, FRS, FRS_ABF = 0, 1, 2, 3
-SM_BJ, SM_DILU, SM_RAS = 0, 1, 2
+SM_BJ, SM_DILU, SM_RAS, SM_RAS1 = 0, 1, 2, 3
 
 
 class RsError(RuntimeError):

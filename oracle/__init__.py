@@ -20,7 +20,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
-_SRC = ["bsr.c", "decouple.c", "amg.c", "cpr.c", "ras.c"]
+_SRC = ["bsr.c", "decouple.c", "amg.c", "cpr.c", "ras.c", "thermal.c"]
 
 ABF, QIMPES, FRS, FRS_ABF = 0, 1, 2, 3
 SM_BJ, SM_DILU, SM_RAS, SM_RAS1 = 0, 1, 2, 3
@@ -43,6 +43,16 @@ _f64p = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
 class AmgOpts(C.Structure):
     _fields_ = [("theta", C.c_double), ("max_row_sum", C.c_double), ("coarse_n", C.c_int),
                 ("max_levels", C.c_int), ("lu_max", C.c_int), ("coarse_sweeps", C.c_int)]
+
+
+class ThermalParams(C.Structure):
+    _fields_ = [(nm, C.c_double) for nm in
+                ("dx", "dy", "dz", "dt", "ctrans", "p_ref", "t_ref", "rhow_ref", "cpw", "ct1w", "ct2w", "cptw",
+                 "rhoo_ref", "cpo", "ct1o", "ct2o", "cpto", "avisc_o", "bvisc_o", "cpl_o")] + \
+               [("cpg", C.c_double * 5)] + \
+               [(nm, C.c_double) for nm in
+                ("hvr_w", "ev_w", "tcrit_w", "por_ref", "cpor", "cp_rock", "kw", "ko", "kr", "pv_btu",
+                 "jmol_btu", "p_bh", "t_inj", "bbl_ft3")]
 
 
 class Info(C.Structure):
@@ -121,6 +131,23 @@ def lib():
         L.or_rasov_ext_dinv.restype = None
         L.or_rasov_free.argtypes = [C.c_void_p]
         L.or_rasov_free.restype = None
+        L.or_thermal_defaults.argtypes = [C.POINTER(ThermalParams)]
+        L.or_thermal_defaults.restype = None
+        L.or_thermal_assemble.argtypes = [C.c_int] * 3 + [C.POINTER(ThermalParams), _f64p, _f64p, _f64p,
+                                                         _f64p, _f64p, C.c_int, _i32p, _i32p, _f64p,
+                                                         _i32p, _i32p, C.c_void_p, C.c_void_p]
+        L.or_thermal_props.argtypes = [C.POINTER(ThermalParams), _f64p, _f64p]
+        L.or_thermal_props.restype = None
+        L.or_relperm.argtypes = [C.c_int, C.c_double, C.POINTER(C.c_double)]
+        L.or_relperm.restype = C.c_double
+        L.or_stone2.argtypes = [C.c_double, C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.or_stone2.restype = C.c_double
+        L.or_water_visc.argtypes = [C.c_double, C.POINTER(C.c_double)]
+        L.or_water_visc.restype = C.c_double
+        L.or_water_enthalpy.argtypes = [C.POINTER(ThermalParams), C.c_double, C.POINTER(C.c_double)]
+        L.or_water_enthalpy.restype = C.c_double
+        L.or_thermal_state.argtypes = [C.POINTER(ThermalParams), C.c_int, _f64p, _f64p, _f64p, _f64p, _f64p]
+        L.or_thermal_state.restype = None
         L.or_grad_logk.argtypes = [C.c_int] * 3 + [_f64p, C.c_double, C.c_double, _f64p, _f64p, C.c_int,
                                                    _i32p, _f64p, _f64p, _f64p, _f64p]
         _lib = L
@@ -459,3 +486,68 @@ def grad_logk(prob, lam, x, logk=None):
                               _c(prob.well_u, np.float64), _c(lam, np.float64),
                               _c(x, np.float64), g), "or_grad_logk")
     return g
+
+
+# ---------------------------------------------------------------------------
+# thermal model subset (thermal.c)
+
+def thermal_params(**kw) -> ThermalParams:
+    q = ThermalParams()
+    lib().or_thermal_defaults(C.byref(q))
+    for k, v in kw.items():
+        setattr(q, k, v)
+    return q
+
+
+def thermal_state(q: ThermalParams, p, sw, so, t):
+    """Unknowns (p, N_w, N_o, T) per cell from p, S_w, S_o, T."""
+    n = len(p)
+    u = np.zeros(4 * n)
+    lib().or_thermal_state(C.byref(q), n, _c(p, np.float64), _c(sw, np.float64), _c(so, np.float64),
+                           _c(t, np.float64), u)
+    return u
+
+
+def thermal_assemble(tp, q: ThermalParams, u, uold, jacobian=True):
+    """Residual (4n) and, if asked, the Jacobian as a BSR on the 7-point
+    pattern, for the thermal problem tp (synth.ThermalProblem)."""
+    n = tp.nx * tp.ny * tp.nz
+    rp, ci = pattern(tp.nx, tp.ny, tp.nz)
+    res = np.zeros(4 * n)
+    vals = np.zeros(16 * int(rp[-1])) if jacobian else None
+    st = lib().or_thermal_assemble(tp.nx, tp.ny, tp.nz, C.byref(q), _c(tp.kx, np.float64), _c(tp.ky, np.float64),
+                                   _c(tp.kz, np.float64), _c(u, np.float64), _c(uold, np.float64),
+                                   int(tp.wcell.shape[0]), _c(tp.wcell, np.int32), _c(tp.wkind, np.int32),
+                                   _c(tp.wval, np.float64), rp, ci,
+                                   None if vals is None else vals.ctypes.data, res.ctypes.data)
+    _check(st, "or_thermal_assemble")
+    J = None if vals is None else BSR(tp.nx, tp.ny, tp.nz, rp, ci, vals.reshape(-1, 4, 4))
+    return res, J
+
+
+def thermal_props(q: ThermalParams, u4):
+    out = np.zeros(9)
+    lib().or_thermal_props(C.byref(q), _c(u4, np.float64), out)
+    return dict(zip(("sw", "so", "lw", "lo", "hw", "ho", "e", "kt", "vol"), out))
+
+
+def relperm(which, s):
+    d = C.c_double(0.0)
+    v = lib().or_relperm(which, float(s), C.byref(d))
+    return v, d.value
+
+
+def stone2(sw, sg):
+    a, b = C.c_double(0.0), C.c_double(0.0)
+    v = lib().or_stone2(float(sw), float(sg), C.byref(a), C.byref(b))
+    return v, a.value, b.value
+
+
+def water_visc(t):
+    d = C.c_double(0.0)
+    return lib().or_water_visc(float(t), C.byref(d)), d.value
+
+
+def water_enthalpy(q, t):
+    d = C.c_double(0.0)
+    return lib().or_water_enthalpy(C.byref(q), float(t), C.byref(d)), d.value

@@ -124,6 +124,36 @@ int or_bicgstab(int n, const int *rp, const int *ci, const double *v, const or_c
                 const double *b, double *x, double rtol, int maxit, or_info *info,
                 double *hist, int hist_len);
 
+/* ---- thermal model subset: residual and Jacobian of one Newton step (thermal.c) */
+typedef struct {
+  double dx, dy, dz, dt;                  /* cell sizes (ft), time step (day)           */
+  double ctrans;                          /* transmissibility constant                  */
+  double p_ref, t_ref;                    /* reference pressure (psi), temperature (F)  */
+  double rhow_ref, cpw, ct1w, ct2w, cptw; /* water density correlation                  */
+  double rhoo_ref, cpo, ct1o, ct2o, cpto; /* oil component density correlation          */
+  double avisc_o, bvisc_o;                /* oil viscosity avisc exp(bvisc / T_abs)     */
+  double cpl_o;                           /* oil liquid heat capacity, Btu/(lbmole F)   */
+  double cpg[5], hvr_w, ev_w, tcrit_w;    /* water gas-based enthalpy (J/gmol, deg C)   */
+  double por_ref, cpor;                   /* linear porosity                            */
+  double cp_rock;                         /* rock heat capacity, Btu/(ft^3 F)           */
+  double kw, ko, kr;                      /* thermal conductivities, Btu/(ft day F)     */
+  double pv_btu, jmol_btu;                /* unit factors: psi ft^3 and J/gmol in Btu   */
+  double p_bh, t_inj;                     /* producer bottom-hole pressure, injection T */
+  double bbl_ft3;                         /* bbl -> ft^3                                */
+} or_thermal_params;
+void or_thermal_defaults(or_thermal_params *q);
+int or_thermal_assemble(int nx, int ny, int nz, const or_thermal_params *q, const double *kx,
+                        const double *ky, const double *kz, const double *u, const double *uold, int nw,
+                        const int *wcell, const int *wkind, const double *wval, const int *rp, const int *ci,
+                        double *vals, double *res);
+void or_thermal_props(const or_thermal_params *q, const double *u, double *out);
+double or_relperm(int which, double s, double *slope);
+double or_stone2(double sw, double sg, double *d_sw, double *d_sg);
+double or_water_visc(double t, double *dmu_dt);
+double or_water_enthalpy(const or_thermal_params *q, double t, double *dh_dt);
+void or_thermal_state(const or_thermal_params *q, int n, const double *p, const double *sw, const double *so,
+                      const double *t, double *u);
+
 /* ---- adjoint gradient with respect to log-permeability */
 int or_grad_logk(int nx, int ny, int nz, const double *logk, double kvkh, double tscale,
                  const double *Mf, const double *Mb, int nw, const int *wcell,

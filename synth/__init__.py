@@ -245,3 +245,58 @@ def small(nx, ny, nz, seed=7, sigma=1.0, kvkh=0.1, shale=0.0, wells=True) -> Pro
         w = wells_vertical_pair(nx, ny, nz, (0, 0), (nx - 1, ny - 1))
     return make(nx, ny, nz, seed=seed, sigma=sigma, kvkh=kvkh, shale=shale, wells=w,
                 name=f"small-{nx}x{ny}x{nz}")
+
+
+# ---------------------------------------------------------------------------
+# inputs of the thermal model subset: a grid, permeabilities, wells and two
+# states (this Newton iterate and the previous time step) as raw draws
+
+@dataclasses.dataclass
+class ThermalProblem:
+    nx: int
+    ny: int
+    nz: int
+    kx: np.ndarray            # (n,) md
+    ky: np.ndarray
+    kz: np.ndarray
+    wcell: np.ndarray         # (nw,) int32, ascending
+    wkind: np.ndarray         # (nw,) int32: +1 injector, -1 producer
+    wval: np.ndarray          # (nw,) injector: water rate bbl/day; producer: well index md ft
+    p: np.ndarray             # this iterate: pressure (psi), S_w, S_o, T (deg F)
+    sw: np.ndarray
+    so: np.ndarray
+    t: np.ndarray
+    p0: np.ndarray            # previous time step
+    sw0: np.ndarray
+    so0: np.ndarray
+    t0: np.ndarray
+
+
+_P_TSTATE, _P_TOLD = 8, 9
+
+
+def thermal_problem(nx, ny, nz, *, seed, sigma=1.0, kvkh=0.1, wells=None, wi=1.0e4, inj_bbl=None):
+    """Draws for one Newton step of the thermal subset, around the heavy-oil
+    example of the paper's validation section (initial p 75 psi, T 125 F,
+    S_w 0.45; injection at 450 F, producers' well index 1e4 md ft, injector
+    100 bbl/day per well): p ~ 75 + U[0,25], T ~ 125 + 325 U^2, S_w ~
+    U[0.46, 0.84] (inside the relative-permeability tables), S_o = 1 - S_w;
+    the previous step a little cooler and lower in pressure and S_w.  Each
+    injector perforation takes inj_bbl (default 100 / nz, a vertical well's
+    share)."""
+    base = make(nx, ny, nz, seed=seed, sigma=sigma, kvkh=kvkh, wells=wells)
+    n = nx * ny * nz
+    k = np.exp(base.logk)
+    r = _rng(seed, _P_TSTATE)
+    p = 75.0 + 25.0 * r.random(n)
+    t = 125.0 + 325.0 * r.random(n) ** 2
+    sw = 0.46 + 0.38 * r.random(n)
+    r0 = _rng(seed, _P_TOLD)
+    p0 = p - 5.0 * r0.random(n)
+    t0 = t - 10.0 * r0.random(n)
+    sw0 = sw - 0.01 * r0.random(n)
+    inj = 100.0 / nz if inj_bbl is None else inj_bbl
+    wk = base.well_kind.astype(np.int32)
+    wval = np.where(wk > 0, inj, wi).astype(np.float64)
+    return ThermalProblem(nx, ny, nz, k, k.copy(), kvkh * k, base.well_cell.astype(np.int32), wk, wval,
+                          p, sw, 1.0 - sw, t, p0, sw0, 1.0 - sw0, t0)

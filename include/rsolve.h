@@ -240,6 +240,86 @@ rs_status rs_assemble(int nx, int ny, int nz, const double *d_logk, double kvkh,
                       const double *d_wu, const int32_t *d_row_ptr, double *d_vals,
                       void *stream);
 
+/* ---- the system of one Newton step of the thermal model ------------------ */
+
+/* Constants of the water / oil / energy subset of the paper's thermal model
+ * (units: psi, deg F, ft, day, md, cp, lbmole, Btu).  The defaults hold the
+ * values the paper prints, and readings where it prints none:
+ *   printed: the heavy-oil example's cell sizes (29.17, 29.17, 10 ft),
+ *     porosity 0.3 and its coefficient 5e-4 1/psi, producers' bottom-hole
+ *     pressure 17 psi and injection temperature 450 F; the light-oil
+ *     component's density (0.2092 lbmole/ft^3, 5e-6 1/psi, 3.8e-4 1/F) and
+ *     viscosity (avisc 0.287352 cp, bvisc 3728.2, T absolute); the water
+ *     enthalpy constants (gas-based, cpg1..5, hvr 4820, ev 0.38, J/gmol, C);
+ *     the oil's liquid heat capacity (0.5 Btu/(lb F), M = 250 lb/lbmole);
+ *     the relative-permeability tables (Figs. rela-swt, rela-slt) and the
+ *     water viscosity table (Fig. fig-wat-vis), compiled in;
+ *   readings: water density 3.4605 lbmole/ft^3 at 14.696 psi and 60 F with
+ *     3e-6 1/psi and 1e-4 1/F; water T_crit 374.15 C; rock heat capacity
+ *     35 Btu/(ft^3 F); conductivities water 8.6, oil 1.8, rock 24
+ *     Btu/(ft day F); Darcy constant 1.127e-3 bbl/(day psi cp md ft) and
+ *     5.614583 ft^3/bbl. */
+typedef struct {
+  double dx, dy, dz, dt;                  /* cell sizes (ft), time step (day)            */
+  double ctrans;                          /* Darcy constant, ft^3 cp / (day psi md ft)   */
+  double p_ref, t_ref;                    /* reference pressure (psi) and temperature (F) */
+  double rhow_ref, cpw, ct1w, ct2w, cptw; /* water density correlation                   */
+  double rhoo_ref, cpo, ct1o, ct2o, cpto; /* oil component density correlation           */
+  double avisc_o, bvisc_o;                /* oil viscosity avisc exp(bvisc / (T + 459.67)) */
+  double cpl_o;                           /* oil heat capacity, Btu/(lbmole F)           */
+  double cpg[5], hvr_w, ev_w, tcrit_w;    /* water gas-based enthalpy, J/gmol and deg C  */
+  double por_ref, cpor;                   /* porosity phi_ref (1 + cpor (p - p_ref))     */
+  double cp_rock;                         /* rock heat capacity, Btu/(ft^3 F)            */
+  double kw, ko, kr;                      /* thermal conductivities, Btu/(ft day F)      */
+  double pv_btu, jmol_btu;                /* psi ft^3 in Btu; J/gmol in Btu/lbmole       */
+  double p_bh, t_inj;                     /* producers' bottom-hole pressure, injection T */
+  double bbl_ft3;                         /* ft^3 per bbl                                */
+} rs_thermal_params;
+
+void rs_thermal_params_default(rs_thermal_params *q);
+
+/* Residual R(u) and Jacobian dR/du of one backward-Euler Newton step
+ * (Section "Numerical Methods") of a water / oil / energy subset of the
+ * thermal model (Section "Mathematical Model", Eqs. eq4.1-eq4.3): water
+ * with the water component only, oil with one oil component only, no gas
+ * (S_g = 0, the switched constraint of the gas-free state), no capillary
+ * pressure, no gravity, no heat loss.
+ *   Unknowns per cell u = (p, N_w, N_o, T): pressure, moles of water and of
+ *   oil per unit bulk volume (S = N / (phi rho)), temperature.
+ *   Equations per cell, in this order: water and oil mole balance
+ *   V/dt (N - N_old) - sum of face flows in - wells; energy balance
+ *   V/dt (E - E_old) - ... with E = N_w U_w + N_o U_o + (1 - phi_ref) U_r;
+ *   the saturation constraint V/dt (phi - N_w/rho_w - N_o/rho_o).
+ *   Face flow of phase a into a cell: G lambda_a,up (p_nbr - p_cell), G the
+ *   Darcy constant times area/length times the harmonic mean of the two
+ *   cells' permeabilities along the face (zero on the boundary), lambda =
+ *   k_r rho / mu upstream (higher pressure; the lower-numbered cell on a
+ *   tie); energy flow sum_a F_a H_a,up plus conduction with the harmonic
+ *   mean of K_T = phi (S_w K_w + S_o K_o) + (1 - phi) K_r; k_ro by Stone's
+ *   model II; Peaceman wells: producers Q_a = -ctrans WI lambda_a
+ *   (p - p_bh) when p > p_bh, injectors a fixed water rate at t_inj.
+ * Arguments (device pointers, 16-byte aligned where vectors): per-cell
+ * permeabilities d_kx, d_ky, d_kz (md, n each); the iterate d_u and the
+ * previous time step's state d_uold (4n each, 4 unknowns per cell as
+ * above); nw well perforations: d_wcell (ascending, unique cells, else
+ * RS_E_ARG), d_wkind (+1 injector, -1 producer), d_wval (injector: water
+ * rate in bbl/day of cold water; producer: well index in md ft).
+ * Outputs: d_vals (16*nnzb doubles, the caller layout of the 7-point
+ * pattern described above: block (i,j) = dR_i/du_j, rows = equations,
+ * columns = unknowns; may be NULL) and d_res (4n, may be NULL; not both).
+ * The Newton step solves J du = -R. */
+rs_status rs_thermal_assemble(int nx, int ny, int nz, const rs_thermal_params *q, const double *d_kx,
+                              const double *d_ky, const double *d_kz, const double *d_u,
+                              const double *d_uold, int nw, const int32_t *d_wcell,
+                              const int32_t *d_wkind, const double *d_wval, double *d_vals,
+                              double *d_res, void *stream);
+
+/* u = (p, N_w, N_o, T) per cell from p, S_w, S_o, T (n each, device): N = phi
+ * rho S with the densities and porosity of rs_thermal_assemble, for states
+ * given in saturations. */
+rs_status rs_thermal_state(int64_t n, const rs_thermal_params *q, const double *d_p, const double *d_sw,
+                           const double *d_so, const double *d_t, double *d_u, void *stream);
+
 /* Write the 7-point block pattern of an nx x ny x nz grid (row pointers
  * n+1, column indices nnzb) into device buffers; *h_nnzb (host, may be NULL)
  * receives the number of stored blocks. */

@@ -8,7 +8,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 SO = os.path.join(HERE, "librsolve.so")
-SOURCES = ["bsr.hip", "decouple.hip", "amg.hip", "cpr.hip", "dilu.hip", "ras.hip", "gmres.hip", "bicgstab.hip", "assemble.hip", "pool.hip"]
+SOURCES = ["bsr.hip", "decouple.hip", "amg.hip", "cpr.hip", "dilu.hip", "ras.hip", "gmres.hip", "bicgstab.hip",
+           "assemble.hip", "thermal.hip", "pool.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          # packed FP32 instructions are kept out of every kernel
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

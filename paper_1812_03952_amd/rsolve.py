@@ -41,6 +41,17 @@ class BicgstabOpts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("maxit", C.c_int), ("zero_guess", C.c_int)]
 
 
+class ThermalParams(C.Structure):
+    """rs_thermal_params (rsolve.h)."""
+    _fields_ = [(nm, C.c_double) for nm in
+                ("dx", "dy", "dz", "dt", "ctrans", "p_ref", "t_ref", "rhow_ref", "cpw", "ct1w", "ct2w", "cptw",
+                 "rhoo_ref", "cpo", "ct1o", "ct2o", "cpto", "avisc_o", "bvisc_o", "cpl_o")] + \
+               [("cpg", C.c_double * 5)] + \
+               [(nm, C.c_double) for nm in
+                ("hvr_w", "ev_w", "tcrit_w", "por_ref", "cpor", "cp_rock", "kw", "ko", "kr", "pv_btu",
+                 "jmol_btu", "p_bh", "t_inj", "bbl_ft3")]
+
+
 class SolveInfo(C.Structure):
     _fields_ = [("iters", C.c_int), ("cycles", C.c_int), ("status", C.c_int),
                 ("relres", C.c_double), ("est_relres", C.c_double), ("ms", C.c_double)]
@@ -91,6 +102,10 @@ def lib():
             "rs_cpr_vcycle": (_i, [_vp, _vp, _vp, _vp]),
             "rs_dense_inverse": (_i, [_i, _vp, _vp, _vp]),
             "rs_dense_inverse_noalloc": (_i, [_i, _vp, _vp, _vp]),
+            "rs_thermal_params_default": (None, [C.POINTER(ThermalParams)]),
+            "rs_thermal_assemble": (_i, [_i, _i, _i, C.POINTER(ThermalParams), _vp, _vp, _vp, _vp, _vp, _i, _vp,
+                                         _vp, _vp, _vp, _vp, _vp]),
+            "rs_thermal_state": (_i, [_i64, C.POINTER(ThermalParams), _vp, _vp, _vp, _vp, _vp, _vp]),
             "rs_pool_trim": (None, []),
             "rs_pool_usage": (None, [C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
         }
@@ -366,6 +381,38 @@ def grad_logk(nx, ny, nz, logk, kvkh, tscale, Mf, Mb, wcell, wu, row_ptr, G, g, 
                               _ptr(wcell, torch.int32) if nw else None, _ptr(wu, torch.float64) if nw else None,
                               _ptr(row_ptr, torch.int32, n + 1), _ptr(G, torch.float64),
                               _ptr(g, torch.float64, n), _stream(stream)), "rs_grad_logk")
+
+
+# ---- the system of one Newton step of the thermal model subset -----------------
+def thermal_params(**kw) -> ThermalParams:
+    q = ThermalParams()
+    lib().rs_thermal_params_default(C.byref(q))
+    for k, v in kw.items():
+        setattr(q, k, v)
+    return q
+
+
+def thermal_assemble(nx, ny, nz, q: ThermalParams, kx, ky, kz, u, uold, wcell, wkind, wval, vals=None, res=None,
+                     stream=None):
+    """Jacobian values (caller layout, 16*nnzb) into `vals` and residual (4n)
+    into `res` (either may be None, not both)."""
+    n = nx * ny * nz
+    nw = wcell.numel()
+    _check(lib().rs_thermal_assemble(nx, ny, nz, C.byref(q), _ptr(kx, torch.float64, n), _ptr(ky, torch.float64, n),
+                                     _ptr(kz, torch.float64, n), _ptr(u, torch.float64, 4 * n),
+                                     _ptr(uold, torch.float64, 4 * n), nw,
+                                     _ptr(wcell, torch.int32) if nw else None, _ptr(wkind, torch.int32) if nw else None,
+                                     _ptr(wval, torch.float64) if nw else None,
+                                     None if vals is None else _ptr(vals, torch.float64),
+                                     None if res is None else _ptr(res, torch.float64, 4 * n), _stream(stream)),
+           "rs_thermal_assemble")
+
+
+def thermal_state(q: ThermalParams, p, sw, so, t, u, stream=None):
+    n = p.numel()
+    _check(lib().rs_thermal_state(n, C.byref(q), _ptr(p, torch.float64, n), _ptr(sw, torch.float64, n),
+                                  _ptr(so, torch.float64, n), _ptr(t, torch.float64, n),
+                                  _ptr(u, torch.float64, 4 * n), _stream(stream)), "rs_thermal_state")
 
 
 # ---- inspection ---------------------------------------------------------------

@@ -14,7 +14,10 @@
  * Conventions for every call
  *   - Pointers named d_* are device pointers (any allocator: hipMalloc,
  *     torch); h_* are host pointers.  Buffers passed in are borrowed for the
- *     duration of the call only; the library keeps no reference to them.
+ *     duration of the call only; the library keeps no reference to them,
+ *     with one exception: rs_bsr_attach_decouple keeps d_vals as the
+ *     matrix's values until the handle's next update or its destruction
+ *     (the caller keeps that buffer alive and unchanged meanwhile).
  *   - Handles (rs_bsr, rs_dcpl, rs_cpr) are opaque and owned by the library;
  *     free them with the matching *_destroy.  A handle may be used by one
  *     host thread at a time.

@@ -42,7 +42,8 @@ _f64p = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
 
 class AmgOpts(C.Structure):
     _fields_ = [("theta", C.c_double), ("max_row_sum", C.c_double), ("coarse_n", C.c_int),
-                ("max_levels", C.c_int), ("lu_max", C.c_int), ("coarse_sweeps", C.c_int)]
+                ("max_levels", C.c_int), ("lu_max", C.c_int), ("coarse_sweeps", C.c_int),
+                ("smooth", C.c_int), ("trunc", C.c_double)]
 
 
 class ThermalParams(C.Structure):
@@ -96,6 +97,8 @@ def lib():
         L.or_amg_coarsest_is_lu.argtypes = [C.c_void_p]
         L.or_amg_level_get.argtypes = [C.c_void_p, C.c_int] + [C.c_void_p] * 6
         L.or_amg_level_get.restype = None
+        L.or_amg_level_p.argtypes = [C.c_void_p, C.c_int] + [C.c_void_p] * 3
+        L.or_amg_level_p.restype = C.c_int64
         L.or_amg_vcycle.argtypes = [C.c_void_p, _f64p, _f64p]
         L.or_amg_vcycle.restype = None
         L.or_amg_free.argtypes = [C.c_void_p]
@@ -335,6 +338,18 @@ class AMG:
                            d.ctypes.data, agg.ctypes.data, st.ctypes.data)
         return dict(n=n, nnz=nnz, rp=rp, ci=ci[:nnz], a=a[:nnz], dl1=d[:n], agg=agg[:n],
                     strong=st[:nnz])
+
+    def prolongator(self, l):
+        """The smoothed prolongator of level l as (rp, ci, v), or None when
+        level l uses the piecewise-constant one (its agg array)."""
+        L = lib()
+        nnz = L.or_amg_level_p(self._h, l, None, None, None)
+        if nnz < 0:
+            return None
+        n = L.or_amg_level_n(self._h, l)
+        rp = np.zeros(n + 1, np.int32); ci = np.zeros(max(nnz, 1), np.int32); v = np.zeros(max(nnz, 1))
+        L.or_amg_level_p(self._h, l, rp.ctypes.data, ci.ctypes.data, v.ctypes.data)
+        return rp, ci[:nnz], v[:nnz]
 
     def vcycle(self, b):
         b = _c(b, np.float64)

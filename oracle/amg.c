@@ -23,12 +23,22 @@
  *   P, A_c     piecewise-constant P, R = P^T, A_c = P^T A P; each coarse
  *              entry summed over members in increasing fine index, each
  *              member's row in increasing column order.
+ *   smoothed   (option) the tentative P_t above smoothed by one damped
+ *              Jacobi step, P = (I - omega D^{-1} A) P_t, D = diag(A),
+ *              omega = 4 / (3 rho), rho = max_i sum_j |a_ij| / |a_ii| (a
+ *              bound of the spectral radius of D^{-1} A); then the
+ *              figure's interpolation truncation: in each row of P the
+ *              weights below trunc times the row's largest |weight| are
+ *              dropped and the kept ones scaled to the row's former sum.
+ *              A_c = P^T (A P), R = P^T.
  *   smoother   l1-Jacobi x += (b - A x) / d,  d_i = sgn(a_ii) sum_j |a_ij|;
  *              one sweep before and one after the coarse correction.
  *   coarsest   dense LU with partial pivoting in FP64.
  * Pinned by: strength and aggregation brute force on small graphs, the
  * Galerkin identity against dense P^T A P, and the V-cycle as a linear
- * operator against its dense two-level formula.  The convergence rate of the
+ * operator against its dense two-level formula; the smoothed prolongator by
+ * its dense definition, by P 1 = 1 when A 1 = 0, and by the truncation rule
+ * entry by entry.  The convergence rate of the
  * cycle is parity unpinned (the paper reports none).
  */
 #include <math.h>
@@ -46,6 +56,10 @@ typedef struct {
   double *dl1;
   int *strong;   /* per stored entry: symmetric strength edge (off-diagonal) */
   int *agg;      /* per row: aggregate (coarse row) or -1 */
+  /* smoothed prolongator (n x nc CSR, columns ascending); NULL when P is
+   * the piecewise-constant one given by agg */
+  int *prp, *pci;
+  double *pv;
 } level_t;
 
 struct or_amg {
@@ -64,6 +78,8 @@ void or_amg_defaults(or_amg_opts *o) {
   o->max_levels = 20;
   o->lu_max = 2048;
   o->coarse_sweeps = 4;
+  o->smooth = 0;
+  o->trunc = 1e-2;         /* Fig. fig-ds-amg-par: trunc error */
 }
 
 /* MurmurHash3 32-bit finaliser (Appleby), used as a fixed vertex priority. */
@@ -229,6 +245,176 @@ static void galerkin(const level_t *F, level_t *C) {
   free(cnt); free(mem); free(fill); free(mark); free(slot); free(pidx); free(tv);
 }
 
+/* Sort the m entries (cols, vals) of one sparse row by column. */
+static void sort_row(int m, int *cols, double *vals) {
+  for (int a = 1; a < m; ++a) {
+    int c = cols[a];
+    double v = vals[a];
+    int b = a - 1;
+    while (b >= 0 && cols[b] > c) { cols[b + 1] = cols[b]; vals[b + 1] = vals[b]; --b; }
+    cols[b + 1] = c; vals[b + 1] = v;
+  }
+}
+
+/* Smoothed prolongator of level L (aggregates in L->agg, L->nc of them):
+ *   row i of A P_t:  acc_J = sum of a_ij over the stored j (ascending) with
+ *                    agg[j] = J;
+ *   P_s[i][J] = [J == agg[i]] - omega * (acc_J / a_ii)   (P_t's row when
+ *                    a_ii = 0);
+ *   truncation:      with m_i = max_J |P_s[i][J]|, entries with
+ *                    |P_s[i][J]| < trunc * m_i are dropped; if any was, the
+ *                    kept ones are multiplied by s_all / s_kept (row sums
+ *                    over ascending J, s_kept != 0).
+ * Returns OR_OK. */
+static int smooth_prolongator(level_t *L, double trunc) {
+  const int n = L->n, nc = L->nc;
+  double rho = 0.0;
+  for (int i = 0; i < n; ++i) {
+    double s = 0.0, d = 0.0;
+    for (int64_t p = L->rp[i]; p < L->rp[i + 1]; ++p) {
+      s = s + fabs(L->a[p]);
+      if (L->ci[p] == i) d = L->a[p];
+    }
+    if (d != 0.0) { double q = s / fabs(d); if (q > rho) rho = q; }
+  }
+  const double omega = rho > 0.0 ? 4.0 / (3.0 * rho) : 0.0;
+  L->prp = (int *)malloc(sizeof(int) * ((size_t)n + 1));
+  /* at most one entry per stored column (the own aggregate comes through
+   * the diagonal) plus the own aggregate when the row has no diagonal */
+  int64_t cap = L->rp[n] + n;
+  L->pci = (int *)malloc(sizeof(int) * (size_t)(cap > 0 ? cap : 1));
+  L->pv = (double *)malloc(sizeof(double) * (size_t)(cap > 0 ? cap : 1));
+  int *mark = (int *)malloc(sizeof(int) * (size_t)(nc > 0 ? nc : 1));
+  int *slot = (int *)malloc(sizeof(int) * (size_t)(nc > 0 ? nc : 1));
+  for (int J = 0; J < nc; ++J) mark[J] = -1;
+  int64_t w = 0;
+  L->prp[0] = 0;
+  for (int i = 0; i < n; ++i) {
+    int *cols = L->pci + w;
+    double *vals = L->pv + w;
+    int m = 0;
+    double d = 0.0;
+    for (int64_t p = L->rp[i]; p < L->rp[i + 1]; ++p) {
+      const int j = L->ci[p];
+      if (j == i) d = L->a[p];
+      const int J = L->agg[j];
+      if (J < 0) continue;
+      if (mark[J] != i) { mark[J] = i; slot[J] = m; cols[m] = J; vals[m] = 0.0; ++m; }
+      vals[slot[J]] = vals[slot[J]] + L->a[p];
+    }
+    const int own = L->agg[i];
+    if (own >= 0 && mark[own] != i) { mark[own] = i; slot[own] = m; cols[m] = own; vals[m] = 0.0; ++m; }
+    for (int t = 0; t < m; ++t) {
+      const double delta = cols[t] == own ? 1.0 : 0.0;
+      vals[t] = d != 0.0 ? delta - omega * (vals[t] / d) : delta;
+    }
+    sort_row(m, cols, vals);
+    if (trunc > 0.0 && m > 0) {
+      double mx = 0.0, sall = 0.0, skeep = 0.0;
+      for (int t = 0; t < m; ++t) { if (fabs(vals[t]) > mx) mx = fabs(vals[t]); sall = sall + vals[t]; }
+      const double thr = trunc * mx;
+      int k = 0;
+      for (int t = 0; t < m; ++t)
+        if (fabs(vals[t]) >= thr) { cols[k] = cols[t]; vals[k] = vals[t]; skeep = skeep + vals[k]; ++k; }
+      if (k < m && skeep != 0.0) {
+        const double scale = sall / skeep;
+        for (int t = 0; t < k; ++t) vals[t] = vals[t] * scale;
+      }
+      m = k;
+    }
+    w += m;
+    L->prp[i + 1] = (int)w;
+  }
+  free(mark); free(slot);
+  return OR_OK;
+}
+
+/* A_c = P^T (A P) for a general P (the smoothed one):
+ *   row i of AP:   (AP)_iJ = sum over A's row i (ascending j) and P's row j
+ *                  of a_ij * p_jJ;
+ *   coarse row I:  (A_c)_IJ = sum over the fine rows i with p_iI != 0, in
+ *                  ascending i, of p_iI * (AP)_iJ;
+ * each row's entries in ascending column order. */
+static void galerkin_general(const level_t *F, level_t *C) {
+  const int n = F->n, nc = F->nc;
+  int *mark = (int *)malloc(sizeof(int) * (size_t)(nc > 0 ? nc : 1));
+  int *slot = (int *)malloc(sizeof(int) * (size_t)(nc > 0 ? nc : 1));
+  for (int J = 0; J < nc; ++J) mark[J] = -1;
+  /* AP, row by row (entries bounded by the sum of the P rows it touches) */
+  int64_t cap = 0;
+  for (int i = 0; i < n; ++i)
+    for (int64_t p = F->rp[i]; p < F->rp[i + 1]; ++p) cap += F->prp[F->ci[p] + 1] - F->prp[F->ci[p]];
+  int64_t *aprp = (int64_t *)malloc(sizeof(int64_t) * ((size_t)n + 1));
+  int *apci = (int *)malloc(sizeof(int) * (size_t)(cap > 0 ? cap : 1));
+  double *apv = (double *)malloc(sizeof(double) * (size_t)(cap > 0 ? cap : 1));
+  int64_t w = 0;
+  aprp[0] = 0;
+  for (int i = 0; i < n; ++i) {
+    int *cols = apci + w;
+    double *vals = apv + w;
+    int m = 0;
+    for (int64_t p = F->rp[i]; p < F->rp[i + 1]; ++p) {
+      const int j = F->ci[p];
+      for (int64_t q = F->prp[j]; q < F->prp[j + 1]; ++q) {
+        const int J = F->pci[q];
+        if (mark[J] != i) { mark[J] = i; slot[J] = m; cols[m] = J; vals[m] = 0.0; ++m; }
+        vals[slot[J]] = vals[slot[J]] + F->a[p] * F->pv[q];
+      }
+    }
+    sort_row(m, cols, vals);
+    w += m;
+    aprp[i + 1] = w;
+  }
+  /* P^T by columns: fine rows of each coarse row I in ascending i */
+  int64_t *trp = (int64_t *)calloc((size_t)nc + 1, sizeof(int64_t));
+  for (int64_t q = 0; q < F->prp[n]; ++q) trp[F->pci[q] + 1]++;
+  for (int I = 0; I < nc; ++I) trp[I + 1] += trp[I];
+  int *tri = (int *)malloc(sizeof(int) * (size_t)(F->prp[n] > 0 ? F->prp[n] : 1));
+  double *trv = (double *)malloc(sizeof(double) * (size_t)(F->prp[n] > 0 ? F->prp[n] : 1));
+  int64_t *fill = (int64_t *)calloc((size_t)nc + 1, sizeof(int64_t));
+  for (int i = 0; i < n; ++i)
+    for (int64_t q = F->prp[i]; q < F->prp[i + 1]; ++q) {
+      const int I = F->pci[q];
+      tri[trp[I] + fill[I]] = i; trv[trp[I] + fill[I]] = F->pv[q]; fill[I]++;
+    }
+  /* coarse rows: accumulate into scratch rows, then pack */
+  for (int J = 0; J < nc; ++J) mark[J] = -1;
+  int *rcols = (int *)malloc(sizeof(int) * (size_t)(nc > 0 ? nc : 1));
+  double *rvals = (double *)malloc(sizeof(double) * (size_t)(nc > 0 ? nc : 1));
+  C->n = nc;
+  C->rp = (int *)malloc(sizeof(int) * ((size_t)nc + 1));
+  int64_t ccap = 16 * (int64_t)(nc > 0 ? nc : 1);
+  C->ci = (int *)malloc(sizeof(int) * (size_t)ccap);
+  C->a = (double *)malloc(sizeof(double) * (size_t)ccap);
+  int64_t cw = 0;
+  C->rp[0] = 0;
+  for (int I = 0; I < nc; ++I) {
+    int m = 0;
+    for (int64_t t = trp[I]; t < trp[I + 1]; ++t) {
+      const int i = tri[t];
+      const double pi = trv[t];
+      for (int64_t q = aprp[i]; q < aprp[i + 1]; ++q) {
+        const int J = apci[q];
+        if (mark[J] != I) { mark[J] = I; slot[J] = m; rcols[m] = J; rvals[m] = 0.0; ++m; }
+        rvals[slot[J]] = rvals[slot[J]] + pi * apv[q];
+      }
+    }
+    sort_row(m, rcols, rvals);
+    if (cw + m > ccap) {
+      while (cw + m > ccap) ccap *= 2;
+      C->ci = (int *)realloc(C->ci, sizeof(int) * (size_t)ccap);
+      C->a = (double *)realloc(C->a, sizeof(double) * (size_t)ccap);
+    }
+    memcpy(C->ci + cw, rcols, sizeof(int) * (size_t)m);
+    memcpy(C->a + cw, rvals, sizeof(double) * (size_t)m);
+    cw += m;
+    C->rp[I + 1] = (int)cw;
+  }
+  C->nnz = cw;
+  free(mark); free(slot); free(aprp); free(apci); free(apv); free(trp); free(tri); free(trv); free(fill);
+  free(rcols); free(rvals);
+}
+
 static void l1diag(level_t *L) {
   for (int64_t i = 0; i < L->n; ++i) {
     double s = 0.0, aii = 0.0;
@@ -305,7 +491,12 @@ or_amg *or_amg_setup(int n, const int *rp, const int *ci, const double *a,
     int nc = aggregate(L, l);
     if (nc == 0 || nc >= L->n) { for (int i = 0; i < L->n; ++i) L->agg[i] = -1; break; }
     L->nc = nc;
-    galerkin(L, &h->L[l + 1]);
+    if (o->smooth) {
+      smooth_prolongator(L, o->trunc);
+      galerkin_general(L, &h->L[l + 1]);
+    } else {
+      galerkin(L, &h->L[l + 1]);
+    }
     h->nl++;
   }
   level_t *C = &h->L[h->nl - 1];
@@ -326,6 +517,16 @@ int or_amg_nlevels(const or_amg *h) { return h->nl; }
 int or_amg_level_n(const or_amg *h, int l) { return h->L[l].n; }
 int64_t or_amg_level_nnz(const or_amg *h, int l) { return h->L[l].nnz; }
 int or_amg_coarsest_is_lu(const or_amg *h) { return h->lu; }
+
+int64_t or_amg_level_p(const or_amg *h, int l, int *prp, int *pci, double *pv) {
+  if (l < 0 || l >= h->nl - 1 || !h->L[l].prp) return -1;
+  const level_t *L = &h->L[l];
+  const int64_t nnz = L->prp[L->n];
+  if (prp) memcpy(prp, L->prp, sizeof(int) * ((size_t)L->n + 1));
+  if (pci) memcpy(pci, L->pci, sizeof(int) * (size_t)nnz);
+  if (pv) memcpy(pv, L->pv, sizeof(double) * (size_t)nnz);
+  return nnz;
+}
 
 void or_amg_level_get(const or_amg *h, int l, int *rp, int *ci, double *a,
                       double *dl1, int *agg, int *strong) {
@@ -368,11 +569,25 @@ static void vcycle(const or_amg *h, int l, const double *b, double *x) {
   double *xc = (double *)malloc(sizeof(double) * (size_t)nc);
   for (int i = 0; i < n; ++i) x[i] = b[i] / L->dl1[i];            /* pre-smooth from 0 */
   csr_residual(L, b, x, r);
-  for (int i = 0; i < n; ++i)                                        /* restrict: P^T r */
-    if (L->agg[i] >= 0) bc[L->agg[i]] = bc[L->agg[i]] + r[i];
+  if (L->prp) {
+    for (int i = 0; i < n; ++i)                                      /* restrict: P^T r */
+      for (int64_t q = L->prp[i]; q < L->prp[i + 1]; ++q)
+        bc[L->pci[q]] = bc[L->pci[q]] + L->pv[q] * r[i];
+  } else {
+    for (int i = 0; i < n; ++i)                                      /* restrict: P^T r */
+      if (L->agg[i] >= 0) bc[L->agg[i]] = bc[L->agg[i]] + r[i];
+  }
   vcycle(h, l + 1, bc, xc);
-  for (int i = 0; i < n; ++i)                                        /* prolong: x += P xc */
-    if (L->agg[i] >= 0) x[i] = x[i] + xc[L->agg[i]];
+  if (L->prp) {
+    for (int i = 0; i < n; ++i) {                                    /* prolong: x += P xc */
+      double s = 0.0;
+      for (int64_t q = L->prp[i]; q < L->prp[i + 1]; ++q) s = s + L->pv[q] * xc[L->pci[q]];
+      x[i] = x[i] + s;
+    }
+  } else {
+    for (int i = 0; i < n; ++i)                                      /* prolong: x += P xc */
+      if (L->agg[i] >= 0) x[i] = x[i] + xc[L->agg[i]];
+  }
   csr_residual(L, b, x, r);                                          /* post-smooth */
   for (int i = 0; i < n; ++i) x[i] = x[i] + r[i] / L->dl1[i];
   free(r); free(bc); free(xc);
@@ -385,6 +600,7 @@ void or_amg_free(or_amg *h) {
   for (int l = 0; l < h->nl; ++l) {
     level_t *L = &h->L[l];
     free(L->rp); free(L->ci); free(L->a); free(L->dl1); free(L->strong); free(L->agg);
+    free(L->prp); free(L->pci); free(L->pv);
   }
   free(h->lu_a); free(h->lu_piv);
   free(h);

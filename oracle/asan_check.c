@@ -5,7 +5,8 @@
  * little-endian arrays written by the test) and calls every entry point of
  * oracle.h once or more: pattern and assembly, SpMV and transpose, the four
  * decouplings, the second-stage set-ups and applications, RAS with overlap,
- * the AMG hierarchy with a direct and an l1-Jacobi coarsest level, CPR in two
+ * the AMG hierarchy (piecewise-constant and smoothed prolongators) with a
+ * direct and an l1-Jacobi coarsest level, CPR in two
  * and three stages, GMRES (with restarts), BiCGSTAB, the gradient and the
  * thermal residual and Jacobian.  It does no arithmetic of its own beyond
  * checking return codes and finiteness; the sanitizers do the checking.
@@ -114,10 +115,11 @@ int main(int argc, char **argv) {
   or_extract_pressure(nnzb, vt, ap);
   double *bp = calloc(n, 8), *xp = calloc(n, 8);
   for (int i = 0; i < n; ++i) bp[i] = rhs[4 * i];
-  for (int variant = 0; variant < 2; ++variant) {
+  for (int variant = 0; variant < 4; ++variant) {
     or_amg_opts o;
     or_amg_defaults(&o);
-    if (variant) { o.lu_max = 1; o.coarse_n = 1; }
+    if (variant & 1) { o.lu_max = 1; o.coarse_n = 1; }
+    if (variant & 2) { o.smooth = 1; o.max_row_sum = 1e30; }
     int st = 0;
     or_amg *h = or_amg_setup(n, rp, ci, ap, &o, &st);
     CHECK(st);
@@ -130,6 +132,14 @@ int main(int argc, char **argv) {
         int *agg = malloc(sizeof(int) * nl), *strong = malloc(sizeof(int) * (nnz ? nnz : 1));
         or_amg_level_get(h, l, lrp, lci, la, ld, agg, strong);
         free(lrp); free(lci); free(la); free(ld); free(agg); free(strong);
+        int64_t pn = or_amg_level_p(h, l, NULL, NULL, NULL);
+        if (pn >= 0) {
+          int *prp = malloc(sizeof(int) * (nl + 1)), *pci = malloc(sizeof(int) * (pn ? pn : 1));
+          double *pv = malloc(sizeof(double) * (pn ? pn : 1));
+          or_amg_level_p(h, l, prp, pci, pv);
+          finite_or_fail("P", pv, (size_t)pn);
+          free(prp); free(pci); free(pv);
+        }
       }
       (void)or_amg_coarsest_is_lu(h);
       or_amg_vcycle(h, bp, xp);

@@ -80,6 +80,8 @@ typedef struct {
   int max_levels;       /* hierarchy depth limit                       */
   int lu_max;           /* largest coarsest level solved by dense LU   */
   int coarse_sweeps;    /* l1-Jacobi sweeps when the coarsest is larger */
+  int smooth;           /* 0: piecewise-constant P; 1: smoothed P        */
+  double trunc;         /* smoothed P: interpolation truncation factor   */
 } or_amg_opts;
 void or_amg_defaults(or_amg_opts *o);
 or_amg *or_amg_setup(int n, const int *rp, const int *ci, const double *a,
@@ -90,6 +92,10 @@ int64_t or_amg_level_nnz(const or_amg *h, int l);
 void or_amg_level_get(const or_amg *h, int l, int *rp, int *ci, double *a,
                       double *dl1, int *agg, int *strong);
 int or_amg_coarsest_is_lu(const or_amg *h);
+/* smoothed prolongator of level l (to level l+1): returns its number of
+ * entries; fills prp[n+1], pci, pv when they are not NULL.  -1 when level l
+ * has the piecewise-constant P (its agg array) or is the coarsest. */
+int64_t or_amg_level_p(const or_amg *h, int l, int *prp, int *pci, double *pv);
 void or_amg_vcycle(const or_amg *h, const double *b, double *x);
 void or_amg_free(or_amg *h);
 

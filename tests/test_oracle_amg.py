@@ -288,3 +288,156 @@ def test_coarsest_l1_jacobi_fallback(sweeps):
         rho = np.abs(np.linalg.eigvals(np.eye(F["n"]) - np.diag(1 / F["dl1"]) @ Af)).max()
         if rho < 0.95:
             assert np.allclose(h.vcycle(b), np.linalg.solve(Af, b), rtol=1e-6)
+
+
+# ---- smoothed aggregation (option smooth=1, the figure's trunc error) ----------
+
+def _chain(n):
+    """1-D Laplacian, tridiagonal (-1, 2, -1), Dirichlet ends."""
+    rows = []
+    for i in range(n):
+        r = {i: 2.0}
+        if i > 0:
+            r[i - 1] = -1.0
+        if i < n - 1:
+            r[i + 1] = -1.0
+        rows.append(r)
+    return _csr(rows)
+
+
+def _dense_p(h, l, n, nc):
+    rp, ci, v = h.prolongator(l)
+    P = np.zeros((n, nc))
+    P[np.repeat(np.arange(n), np.diff(rp)), ci] = v
+    return P
+
+
+def test_smoothed_prolongator_1d_hat():
+    """The textbook smoothed-aggregation prolongator of the 1-D Laplacian
+    (Vanek, Mandel, Brezina 1996): rho = max_i sum_j |a_ij| / a_ii = 2, so
+    omega = 2/3 and P = P_t - A P_t / 3, the piecewise-linear hat: weight 1
+    inside an aggregate, 2/3 on its end nodes, 1/3 on the nodes just outside
+    it.  No weight is below 1e-2 of its row's largest, so none is dropped."""
+    n = 31
+    rp, ci, a = _chain(n)
+    h = oracle.AMG(rp, ci, a, coarse_n=3, smooth=1)
+    F = h.level(0)
+    agg = F["agg"]
+    assert (agg >= 0).all()
+    nc = int(agg.max()) + 1
+    P = _dense_p(h, 0, n, nc)
+    for J in range(nc):
+        mem = np.flatnonzero(agg == J)
+        assert np.array_equal(mem, np.arange(mem[0], mem[-1] + 1))   # consecutive runs in 1-D
+        s, e = mem[0], mem[-1]
+        exp = np.zeros(n)
+        exp[s:e + 1] = 1.0
+        if e > s:
+            exp[s] = exp[e] = 2.0 / 3.0
+        else:
+            exp[s] = 1.0 / 3.0                      # a one-node aggregate: 1 - 2/3
+        if s > 0:
+            exp[s - 1] = 1.0 / 3.0
+        if e < n - 1:
+            exp[e + 1] = 1.0 / 3.0
+        # the Dirichlet end nodes have one neighbour only: 1 - (2 - 1)/3 = 2/3
+        # as own weight whatever their position in the aggregate
+        if s == 0 and e > 0:
+            exp[0] = 2.0 / 3.0
+        if e == n - 1 and s < n - 1:
+            exp[n - 1] = 2.0 / 3.0
+        assert np.allclose(P[:, J], exp, rtol=0, atol=1e-15), (J, P[:, J], exp)
+
+
+def test_truncation_recovers_tentative_on_1d():
+    """trunc = 0.6 on the 1-D Laplacian: every 1/3 weight is below 0.6 times
+    its row's largest (1 or 2/3), so it is dropped and the row's kept weight
+    is scaled to the former row sum: P becomes the piecewise-constant P_t
+    (rows with a single 2/3 at a Dirichlet end excepted, whose row sum was
+    2/3 and stays 2/3)."""
+    n = 31
+    rp, ci, a = _chain(n)
+    h = oracle.AMG(rp, ci, a, coarse_n=3, smooth=1, trunc=0.6)
+    agg = h.level(0)["agg"]
+    nc = int(agg.max()) + 1
+    P = _dense_p(h, 0, n, nc)
+    Pt = np.zeros((n, nc)); Pt[np.arange(n), agg] = 1.0
+    inner = np.ones(n, bool); inner[[0, n - 1]] = False
+    assert np.allclose(P[inner], Pt[inner], rtol=0, atol=1e-15)
+    assert np.count_nonzero(P[0]) == 1 and np.count_nonzero(P[n - 1]) == 1
+
+
+def test_smoothed_prolongator_preserves_constants():
+    """With A 1 = 0 (a periodic 2-D Laplacian: every row sums to zero) the
+    smoothing step maps 1 to 1 - omega D^{-1} A 1 = 1 and the truncation
+    keeps each row sum, so P 1 = 1 for every row at the default trunc."""
+    m = 9
+    rows = []
+    for j in range(m):
+        for i in range(m):
+            c = i + m * j
+            r = {c: 4.0}
+            for q in (((i + 1) % m) + m * j, ((i - 1) % m) + m * j, i + m * ((j + 1) % m), i + m * ((j - 1) % m)):
+                r[q] = r.get(q, 0.0) - 1.0
+            rows.append(r)
+    rp, ci, a = _csr(rows)
+    h = oracle.AMG(rp, ci, a, coarse_n=3, smooth=1, max_row_sum=1e30)
+    agg = h.level(0)["agg"]
+    assert (agg >= 0).all()
+    rp_, ci_, v = h.prolongator(0)
+    sums = np.add.reduceat(v, rp_[:-1])
+    assert np.allclose(sums, 1.0, rtol=0, atol=1e-14)
+
+
+def _sa_problem():
+    p = synth.make(9, 8, 4, seed=17, sigma=1.5)
+    A = oracle.assemble(p)
+    At, _ = oracle.decouple(A)
+    return A, oracle.extract_pressure(At)
+
+
+def test_smoothed_galerkin_identity():
+    """A_c = P^T A P with the returned smoothed P, level by level."""
+    A, ap = _sa_problem()
+    h = oracle.AMG(A.rp, A.ci, ap, coarse_n=5, smooth=1, max_row_sum=1e30)
+    assert h.nlevels >= 3
+    for l in range(h.nlevels - 1):
+        F = h.level(l); Cl = h.level(l + 1)
+        n, nc = F["n"], Cl["n"]
+        Af = np.zeros((n, n)); Af[np.repeat(np.arange(n), np.diff(F["rp"])), F["ci"]] = F["a"]
+        Ac = np.zeros((nc, nc)); Ac[np.repeat(np.arange(nc), np.diff(Cl["rp"])), Cl["ci"]] = Cl["a"]
+        P = _dense_p(h, l, n, nc)
+        assert np.allclose(Ac, P.T @ Af @ P, rtol=1e-12, atol=1e-13 * np.abs(Af).max())
+
+
+def test_smoothed_vcycle_is_two_level_operator():
+    """As the piecewise-constant case, with the smoothed P:
+      x1 = S b;  x2 = x1 + P Ac^{-1} P^T (b - A x1);  x3 = x2 + S (b - A x2)."""
+    p = synth.make(6, 5, 3, seed=19, sigma=1.0)
+    A = oracle.assemble(p)
+    At, _ = oracle.decouple(A)
+    ap = oracle.extract_pressure(At)
+    h = oracle.AMG(A.rp, A.ci, ap, coarse_n=40, smooth=1)
+    assert h.nlevels == 2 and h.coarsest_is_lu
+    F = h.level(0); Cl = h.level(1)
+    n, nc = F["n"], Cl["n"]
+    Af = np.zeros((n, n)); Af[np.repeat(np.arange(n), np.diff(F["rp"])), F["ci"]] = F["a"]
+    P = _dense_p(h, 0, n, nc)
+    Ac = P.T @ Af @ P
+    S = np.diag(1.0 / F["dl1"])
+    I = np.eye(n)
+    CG = P @ np.linalg.solve(Ac, P.T)
+    Bop = S + CG @ (I - Af @ S)
+    Bop = Bop + S @ (I - Af @ Bop)
+    Vd = np.stack([h.vcycle(e) for e in I], 1)
+    assert np.allclose(Vd, Bop, rtol=1e-10, atol=1e-12 * np.abs(Bop).max())
+
+
+def test_smoothed_cpr_gmres_converges():
+    """CPR-GMRES with the smoothed-aggregation pressure stage on config 0."""
+    p = synth.config(0)
+    A = oracle.assemble(p)
+    M = oracle.CPR(A, method=oracle.ABF, smoother=oracle.SM_RAS, smooth=1)
+    x, info = oracle.gmres(A, p.b, M, rtol=1e-8)
+    assert info["status"] == 0
+    assert np.linalg.norm(p.b - oracle.spmv(A, x)) / np.linalg.norm(p.b) <= 1e-8

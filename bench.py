@@ -92,7 +92,7 @@ def calibration_copy():
     del src, dst
 
 
-def run_variant(rs, dp, A, prec, steps, warmup, tag, smoother, solver="gmres", method=0, stages=2):
+def run_variant(rs, dp, A, prec, steps, warmup, tag, smoother, solver="gmres", method=0, stages=2, smooth=0):
     import torch
     times, infos, phases = [], [], []
     for it in range(warmup + steps):
@@ -100,7 +100,7 @@ def run_variant(rs, dp, A, prec, steps, warmup, tag, smoother, solver="gmres", m
         t0 = time.perf_counter()
         D = rs.bsr_attach_decouple(A, dp.vals, method, prec)   # new Jacobian values, decoupled
         t1 = time.perf_counter()
-        M = rs.cpr_setup(A, D, rs.cpr_opts(smoother=smoother, stages=stages))
+        M = rs.cpr_setup(A, D, rs.cpr_opts(smoother=smoother, stages=stages, smooth=smooth))
         t2 = time.perf_counter()
         x = torch.zeros_like(dp.b)
         # x0 = 0: the solvers take r0 = b without a product with A
@@ -163,6 +163,8 @@ def main():
     ap.add_argument("--decouple", choices=list(DECOUPLINGS), default="abf")
     ap.add_argument("--stages", type=int, choices=[2, 3], default=2,
                     help="CPR stages: 2 = pressure then full, 3 = CPR-FPF")
+    ap.add_argument("--amg", choices=["ua", "sa"], default="ua",
+                    help="pressure AMG prolongator: piecewise constant (ua) or smoothed and truncated (sa)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 1 GiB copy kernel (for counter calibration under rocprofv3 --pmc)")
     args = ap.parse_args()
@@ -199,7 +201,8 @@ def main():
             variants.append(("fp64", 64, "gmres"))
     for tag, prec, solver in variants:
         times, infos, phases = run_variant(rs, dp, A, prec, args.steps, args.warmup, tag, SMOOTHERS[args.smoother],
-                                           solver, DECOUPLINGS[args.decouple], args.stages)
+                                           solver, DECOUPLINGS[args.decouple], args.stages,
+                                           1 if args.amg == "sa" else 0)
         tmax = max(times)
         tmed = float(np.median(times))
         ph = np.median(np.array(phases), axis=0)
@@ -225,11 +228,11 @@ def main():
         "dtype": "fp32-preconditioner/fp64-gmres",
         "data": "synthetic",
         "config": {"workload": f"{prob.name}: 4x4-block 7-point Jacobian, {n} cells, {4 * n} unknowns, "
-                               f"nnzb {A.nnzb}; {args.decouple.upper()} + {'CPR-FPF' if args.stages == 3 else 'CPR'}(AMG V-cycle, "
+                               f"nnzb {A.nnzb}; {args.decouple.upper()} + {'CPR-FPF' if args.stages == 3 else 'CPR'}({'smoothed-aggregation ' if args.amg == 'sa' else ''}AMG V-cycle, "
                                f"{SMOOTHER_NAMES[args.smoother]}) + {'FGMRES(30)' if solvers[0] == 'gmres' else 'BiCGSTAB'}, rtol 1e-8",
                    "cells": n, "unknowns": 4 * n, "nnzb": A.nnzb, "restart": 30, "rtol": 1e-8,
                    "smoother": args.smoother, "headline_solver": solvers[0], "decouple": args.decouple,
-                   "cpr_stages": args.stages},
+                   "cpr_stages": args.stages, "amg": args.amg},
         "fp32_precond": res.get("fp32"),
         "fp64": res.get("fp64"),
         "bicgstab_fp32_precond": res.get("bicgstab_fp32"),

@@ -87,6 +87,13 @@ typedef struct {
   int coarse_sweeps;   /* l1-Jacobi sweeps if the coarsest is larger (default 4) */
   int stages;          /* 2: pressure then full (default); 3: CPR-FPF, full,
                           pressure, full (Algorithm pc-fpf)                       */
+  int smooth;          /* AMG prolongator: 0 piecewise constant over the
+                          aggregates (default); 1 smoothed by one damped Jacobi
+                          step, P = (I - omega D^{-1} A) P_t with omega = 4/(3 rho),
+                          rho = max_i sum_j |a_ij| / |a_ii|, then truncated      */
+  double trunc;        /* smoothed P: weights below trunc times the row's largest
+                          are dropped and the rest scaled to the row's former sum
+                          (default 1e-2, "trunc error" of Fig. fig-ds-amg-par)   */
 } rs_cpr_opts;
 
 typedef struct {
@@ -364,6 +371,12 @@ int rs_cpr_nlevels(rs_cpr M);
  * aggregated; the coarsest level has none). */
 rs_status rs_cpr_level(rs_cpr M, int l, int *h_n, int64_t *h_nnz, int32_t *h_rp,
                        int32_t *h_ci, double *h_a, double *h_dl1, int32_t *h_agg);
+/* Smoothed prolongator of level l (to level l+1) as CSR on the host:
+ * *h_nnz entries (always filled), then, when the arrays are given, row
+ * pointers h_rp[n+1], coarse columns h_ci (ascending in each row) and FP64
+ * values h_v.  RS_E_ARG when level l has the piecewise-constant prolongator
+ * (rs_cpr_opts.smooth = 0) or is the coarsest. */
+rs_status rs_cpr_level_p(rs_cpr M, int l, int64_t *h_nnz, int32_t *h_rp, int32_t *h_ci, double *h_v);
 /* Second-stage block inverses (16*n doubles, upcast if FP32). */
 rs_status rs_cpr_smoother_get(rs_cpr M, double *h_dinv2);
 /* Inverse of a dense n x n FP64 matrix (row-major, device) by the kernels

@@ -1231,6 +1231,279 @@ __global__ void k_dense_mv(int n, const double *__restrict__ Ci, const T *__rest
   if (lane == 0) x[row] = (T)s;
 }
 
+// ---- smoothed aggregation -----------------------------------------------------
+// Option of the pressure AMG (rs_cpr_opts.smooth): the piecewise-constant
+// prolongator P_t of the aggregates is smoothed by one damped Jacobi step,
+//   P = (I - omega D^{-1} A) P_t,  D = diag(A),  omega = 4 / (3 rho),
+//   rho = max_i sum_j |a_ij| / |a_ii|,
+// then truncated as Fig. fig-ds-amg-par's interpolation truncation ("trunc
+// error"): weights below trunc times the row's largest |weight| are dropped
+// and the kept ones scaled to the row's former sum.  A_c = P^T (A P).  Every
+// sum runs in the order of the FP64 oracle and no product is fused into an
+// addition, so the hierarchy is the oracle's bit for bit.  Rows of P, of AP
+// and of P^T are short (tens of entries), so each is built by one thread in
+// its own stretch of memory: P row i at rp[i] + i (a row has at most one
+// entry per stored column plus its own aggregate), AP row i at an offset from
+// the scan of its candidate count.
+#pragma clang fp contract(off)
+
+// rho as the bit pattern of a non-negative double: integer max is float max
+__global__ __launch_bounds__(256) void k_sa_rho(int n, const int32_t *__restrict__ rp,
+                                                 const int32_t *__restrict__ ci, const double *__restrict__ a,
+                                                 unsigned long long *__restrict__ rho_bits) {
+  __shared__ unsigned long long wm[4];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  double q = 0.0;
+  if (i < n) {
+    double sm = 0.0, d = 0.0;
+    for (int p = rp[i]; p < rp[i + 1]; ++p) {
+      sm = sm + fabs(a[p]);
+      if (ci[p] == i) d = a[p];
+    }
+    if (d != 0.0) q = sm / fabs(d);
+  }
+  unsigned long long b = (unsigned long long)__double_as_longlong(q);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    unsigned long long o = __shfl_xor(b, off, 64);
+    b = o > b ? o : b;
+  }
+  if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = b;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long m = wm[0];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = wm[w] > m ? wm[w] : m;
+    atomicMax(rho_bits, m);
+  }
+}
+
+__device__ __forceinline__ void sa_sort(int m, int32_t *__restrict__ k, double *__restrict__ v) {
+  for (int x = 1; x < m; ++x) {
+    const int32_t kk = k[x];
+    const double vv = v[x];
+    int y = x - 1;
+    while (y >= 0 && k[y] > kk) { k[y + 1] = k[y]; v[y + 1] = v[y]; --y; }
+    k[y + 1] = kk;
+    v[y + 1] = vv;
+  }
+}
+
+// Row i of the smoothed, truncated P, in place at pci/pv + rp[i] + i.
+__global__ __launch_bounds__(256) void k_sa_p(int n, const int32_t *__restrict__ rp,
+                                               const int32_t *__restrict__ ci, const double *__restrict__ a,
+                                               const int32_t *__restrict__ agg,
+                                               const unsigned long long *__restrict__ rho_bits, double trunc,
+                                               int32_t *__restrict__ pcnt, int32_t *__restrict__ pci,
+                                               double *__restrict__ pv) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double rho = __longlong_as_double((long long)*rho_bits);
+  const double omega = rho > 0.0 ? 4.0 / (3.0 * rho) : 0.0;
+  const int p0 = rp[i], p1 = rp[i + 1];
+  int32_t *cols = pci + p0 + i;
+  double *vals = pv + p0 + i;
+  int m = 0;
+  double d = 0.0;
+  for (int p = p0; p < p1; ++p) {
+    const int j = ci[p];
+    if (j == i) d = a[p];
+    const int J = agg[j];
+    if (J < 0) continue;
+    int t = 0;
+    while (t < m && cols[t] != J) ++t;
+    if (t == m) { cols[m] = J; vals[m] = 0.0; ++m; }
+    vals[t] = vals[t] + a[p];
+  }
+  const int own = agg[i];
+  if (own >= 0) {
+    int t = 0;
+    while (t < m && cols[t] != own) ++t;
+    if (t == m) { cols[m] = own; vals[m] = 0.0; ++m; }
+  }
+  for (int t = 0; t < m; ++t) {
+    const double delta = cols[t] == own ? 1.0 : 0.0;
+    vals[t] = d != 0.0 ? delta - omega * (vals[t] / d) : delta;
+  }
+  sa_sort(m, cols, vals);
+  if (trunc > 0.0 && m > 0) {
+    double mx = 0.0, sall = 0.0, skeep = 0.0;
+    for (int t = 0; t < m; ++t) {
+      if (fabs(vals[t]) > mx) mx = fabs(vals[t]);
+      sall = sall + vals[t];
+    }
+    const double thr = trunc * mx;
+    int k = 0;
+    for (int t = 0; t < m; ++t)
+      if (fabs(vals[t]) >= thr) {
+        cols[k] = cols[t];
+        vals[k] = vals[t];
+        skeep = skeep + vals[k];
+        ++k;
+      }
+    if (k < m && skeep != 0.0) {
+      const double scale = sall / skeep;
+      for (int t = 0; t < k; ++t) vals[t] = vals[t] * scale;
+    }
+    m = k;
+  }
+  pcnt[i] = m;
+}
+
+// candidates of AP row i: the sum of the P row lengths of its columns
+__global__ void k_sa_apcand(int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                            const int32_t *__restrict__ pcnt, int32_t *__restrict__ cand) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int c = 0;
+  for (int p = rp[i]; p < rp[i + 1]; ++p) c += pcnt[ci[p]];
+  cand[i] = c;
+}
+
+// Row i of AP: (AP)_iJ = sum over the row's columns j (ascending) of
+// a_ij * p_jJ, then sorted by J; at apci/apv + off[i], apcnt[i] entries.
+__global__ __launch_bounds__(256) void k_sa_ap(int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                                                const double *__restrict__ a, const int32_t *__restrict__ pcnt,
+                                                const int32_t *__restrict__ pci, const double *__restrict__ pv,
+                                                const int32_t *__restrict__ off, int32_t *__restrict__ apcnt,
+                                                int32_t *__restrict__ apci, double *__restrict__ apv) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int32_t *cols = apci + off[i];
+  double *vals = apv + off[i];
+  int m = 0;
+  for (int p = rp[i]; p < rp[i + 1]; ++p) {
+    const int j = ci[p];
+    const double aij = a[p];
+    const int q0 = rp[j] + j, q1 = q0 + pcnt[j];
+    for (int q = q0; q < q1; ++q) {
+      const int J = pci[q];
+      int t = 0;
+      while (t < m && cols[t] != J) ++t;
+      if (t == m) { cols[m] = J; vals[m] = 0.0; ++m; }
+      vals[t] = vals[t] + aij * pv[q];
+    }
+  }
+  sa_sort(m, cols, vals);
+  apcnt[i] = m;
+}
+
+// P^T: entry counts per coarse column, then a fill in arbitrary order and a
+// sort of each column by fine row (deterministic)
+__global__ void k_sa_tcount(int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ pcnt,
+                            const int32_t *__restrict__ pci, int32_t *__restrict__ tcnt) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int q0 = rp[i] + i;
+  for (int q = q0; q < q0 + pcnt[i]; ++q) atomicAdd(&tcnt[pci[q]], 1);
+}
+__global__ void k_sa_tfill(int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ pcnt,
+                           const int32_t *__restrict__ pci, const double *__restrict__ pv,
+                           const int32_t *__restrict__ tptr, int32_t *__restrict__ tfill,
+                           int32_t *__restrict__ tri, double *__restrict__ trv) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int q0 = rp[i] + i;
+  for (int q = q0; q < q0 + pcnt[i]; ++q) {
+    const int J = pci[q];
+    const int at = tptr[J] + atomicAdd(&tfill[J], 1);
+    tri[at] = i;
+    trv[at] = pv[q];
+  }
+}
+__global__ void k_sa_tsort(int nc, const int32_t *__restrict__ tptr, int32_t *__restrict__ tri,
+                           double *__restrict__ trv) {
+  const int I = blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= nc) return;
+  sa_sort(tptr[I + 1] - tptr[I], tri + tptr[I], trv + tptr[I]);
+}
+__global__ void k_iota(int m, int32_t *__restrict__ v) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < m) v[t] = t;
+}
+
+// candidates of coarse row I: the AP row lengths of its fine rows
+__global__ void k_sa_ccand(int nc, const int32_t *__restrict__ tptr, const int32_t *__restrict__ tri,
+                           const int32_t *__restrict__ apcnt, int32_t *__restrict__ cand) {
+  const int I = blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= nc) return;
+  int c = 0;
+  for (int x = tptr[I]; x < tptr[I + 1]; ++x) c += apcnt[tri[x]];
+  cand[I] = c;
+}
+
+// Row source of the smoothed Galerkin product for gal_row: "member" x is the
+// x-th entry of P^T (fine row tri[x], weight trv[x]); its entries are the
+// coarse columns of AP row tri[x] with values trv[x] * (AP)_iJ, so coarse row
+// I gets sum over its fine rows (ascending) of p_iI (AP)_iJ.
+struct rows_sa {
+  const int32_t *tri;
+  const double *trv;
+  const int32_t *apoff, *apcnt, *apci;
+  const double *apv;
+  template <class F> __device__ __forceinline__ bool each(int x, const int32_t *__restrict__, F &&f) const {
+    const int i = tri[x];
+    const double w = trv[x];
+    const int q0 = apoff[i], q1 = q0 + apcnt[i];
+    for (int q = q0; q < q1; ++q)
+      if (!f(apci[q], w * apv[q])) return false;
+    return true;
+  }
+};
+
+#pragma clang fp contract(fast)
+
+template <class T>
+__global__ void k_cast_t(int64_t m, const double *__restrict__ a, T *__restrict__ b) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < m) b[t] = (T)a[t];
+}
+
+// cycle: restriction b_c = P^T r, prolongation z = y + P x_c (y = b ./ d, or
+// the level's y when given), post-sweep x = z + (b - A z) ./ d
+template <class T>
+__global__ void k_sa_restrict(int nc, const int32_t *__restrict__ tptr, const int32_t *__restrict__ tri,
+                              const T *__restrict__ trv, const T *__restrict__ r, T *__restrict__ bc) {
+  const int I = blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= nc) return;
+  T s = 0;
+  for (int x = tptr[I]; x < tptr[I + 1]; ++x) s = fma(trv[x], r[tri[x]], s);
+  bc[I] = s;
+}
+template <class T>
+__global__ __launch_bounds__(256) void k_sa_prolong(int n, const int32_t *__restrict__ rp,
+                                                     const int32_t *__restrict__ pcnt, const int32_t *__restrict__ pci,
+                                                     const T *__restrict__ pv, const T *__restrict__ y,
+                                                     const T *__restrict__ b, const T *__restrict__ d,
+                                                     const T *__restrict__ xc, T *__restrict__ z) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int q0 = rp[i] + i, q1 = q0 + pcnt[i];
+  T s = 0;
+  for (int q = q0; q < q1; ++q) s = fma(pv[q], xc[pci[q]], s);
+  z[i] = (y ? y[i] : b[i] / d[i]) + s;
+}
+template <class T>
+__global__ __launch_bounds__(256) void k_vc_postz(int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                                                   const T *__restrict__ a, const T *__restrict__ d,
+                                                   const T *__restrict__ b, const T *__restrict__ z, T *__restrict__ x) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  T s = 0;
+  for (int p = rp[i]; p < rp[i + 1]; ++p) s = fma(a[p], z[ci[p]], s);
+  x[i] = z[i] + (b[i] - s) / d[i];
+}
+template <class T>
+__global__ __launch_bounds__(256) void k_vc_post7z(int n, int nx, int nxy, const T *__restrict__ s7,
+                                                    const T *__restrict__ d, const T *__restrict__ b,
+                                                    const T *__restrict__ z, T *__restrict__ x) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  T s = 0;
+#pragma unroll
+  for (int k = 0; k < 7; ++k) s = fma(s7[(int64_t)k * n + i], z[nbr7(i, k, n, nx, nxy)], s);
+  x[i] = z[i] + (b[i] - s) / d[i];
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -1382,40 +1655,121 @@ rs_status rs_amg_build(rs_cpr_s *M, hipStream_t s) {
     }
     RS_HIP(hipGetLastError());
     L->nc = nc;
-    // members of each aggregate, ascending
-    RS_TRY(L->mptr.alloc(sizeof(int32_t) * (nc + 1)));
-    dbuf cnt;
-    RS_TRY(cnt.alloc(sizeof(int32_t) * (nc + 1)));
-    RS_HIP(hipMemsetAsync(cnt.p, 0, sizeof(int32_t) * (nc + 1), s));
-    k_count_members<<<rs_grid(n), RS_BLOCK, 0, s>>>(n, L->agg.as<int32_t>(), cnt.as<int32_t>());
-    RS_HIP(hipGetLastError());
-    // members: at most n (no host read of the exact count)
-    RS_TRY(scan_i32(cnt.as<int32_t>(), L->mptr.as<int32_t>(), nc + 1, nullptr, s, nullptr));
-    RS_TRY(L->mem.alloc(sizeof(int32_t) * ((size_t)n + 1)));
-    RS_HIP(hipMemsetAsync(cnt.p, 0, sizeof(int32_t) * (nc + 1), s));
-    k_fill_members<<<rs_grid(n), RS_BLOCK, 0, s>>>(n, L->agg.as<int32_t>(), L->mptr.as<int32_t>(), cnt.as<int32_t>(), L->mem.as<int32_t>());
-    k_sort_members<<<rs_grid(nc), RS_BLOCK, 0, s>>>(nc, L->mptr.as<int32_t>(), L->mem.as<int32_t>());
-    RS_HIP(hipGetLastError());
-    // Galerkin product
-    dbuf off, skey, sval;
-    RS_TRY(off.alloc(sizeof(int32_t) * (nc + 1)));
-    if (st7) k_cand7<<<rs_grid(nc), RS_BLOCK, 0, s>>>(nc, g.nx, g.ny, g.nz, L->mptr.as<int32_t>(), L->mem.as<int32_t>(), cnt.as<int32_t>());
-    else k_cand<<<rs_grid(nc), RS_BLOCK, 0, s>>>(nc, L->mptr.as<int32_t>(), L->mem.as<int32_t>(), rp, cnt.as<int32_t>());
-    RS_HIP(hipGetLastError());
-    // candidates: the members' row entries, at most this level's nnz
-    RS_TRY(scan_i32(cnt.as<int32_t>(), off.as<int32_t>(), nc, nullptr, s, nullptr));
-    const int64_t ncand = L->nnz;
-    RS_TRY(skey.alloc(sizeof(int32_t) * (ncand + 1)));
-    RS_TRY(sval.alloc(sizeof(double) * (ncand + 1)));
-    if (st7)
-      k_galerkin<rows_7><<<rs_grid(nc, GAL_BLOCK), GAL_BLOCK, 0, s>>>(
-          nc, L->mptr.as<int32_t>(), L->mem.as<int32_t>(), rows_7{g.nx, g.ny, g.nz, ap7}, L->agg.as<int32_t>(),
-          off.as<int32_t>(), skey.as<int32_t>(), sval.as<double>(), cnt.as<int32_t>());
-    else
-      k_galerkin<rows_csr><<<rs_grid(nc, GAL_BLOCK), GAL_BLOCK, 0, s>>>(
-          nc, L->mptr.as<int32_t>(), L->mem.as<int32_t>(), rows_csr{rp, ci, L->a.as<double>()}, L->agg.as<int32_t>(),
-          off.as<int32_t>(), skey.as<int32_t>(), sval.as<double>(), cnt.as<int32_t>());
-    RS_HIP(hipGetLastError());
+    dbuf off, skey, sval, cnt;
+    // temporaries of the smoothed product, kept until the host read at the
+    // end of the level (the RAS set-up allocates on a side stream meanwhile)
+    dbuf rho, apoff, apcnt, apci, apv, tfill, trv, ident;
+    int64_t ncand = 0;
+    if (o.smooth) {
+      // smoothed prolongator: on the CSR form (built here for the fine level)
+      if (l == 0) RS_TRY(rs_amg_level0_csr(M, s));
+      const int32_t *crp = L->rp.as<int32_t>(), *cci = L->ci.as<int32_t>();
+      const double *ca = L->a.as<double>();
+      const int64_t pcap = L->nnz + n + 1;
+      RS_TRY(rho.alloc(sizeof(unsigned long long)));
+      RS_HIP(hipMemsetAsync(rho.p, 0, sizeof(unsigned long long), s));
+      k_sa_rho<<<rs_grid(n), RS_BLOCK, 0, s>>>(n, crp, cci, ca, rho.as<unsigned long long>());
+      RS_TRY(L->pcnt.alloc(sizeof(int32_t) * ((size_t)n + 1)));
+      RS_TRY(L->pci.alloc(sizeof(int32_t) * pcap));
+      RS_TRY(L->pv.alloc(sizeof(double) * pcap));
+      k_sa_p<<<rs_grid(n), RS_BLOCK, 0, s>>>(n, crp, cci, ca, L->agg.as<int32_t>(), rho.as<unsigned long long>(),
+                                             o.trunc, L->pcnt.as<int32_t>(), L->pci.as<int32_t>(), L->pv.as<double>());
+      RS_HIP(hipGetLastError());
+      // AP, each row at the scan of its candidate count
+      RS_TRY(apoff.alloc(sizeof(int32_t) * ((size_t)n + 1)));
+      RS_TRY(apcnt.alloc(sizeof(int32_t) * ((size_t)n + 1)));
+      k_sa_apcand<<<rs_grid(n), RS_BLOCK, 0, s>>>(n, crp, cci, L->pcnt.as<int32_t>(), apcnt.as<int32_t>());
+      RS_HIP(hipGetLastError());
+      int64_t apt = 0;
+      RS_TRY(scan_i32(apcnt.as<int32_t>(), apoff.as<int32_t>(), n, &apt, s, nullptr));
+      if (apt < 0) return RS_E_NOMEM;             // more than 2^31 candidates
+      RS_TRY(apci.alloc(sizeof(int32_t) * (apt + 1)));
+      RS_TRY(apv.alloc(sizeof(double) * (apt + 1)));
+      k_sa_ap<<<rs_grid(n), RS_BLOCK, 0, s>>>(n, crp, cci, ca, L->pcnt.as<int32_t>(), L->pci.as<int32_t>(),
+                                              L->pv.as<double>(), apoff.as<int32_t>(), apcnt.as<int32_t>(),
+                                              apci.as<int32_t>(), apv.as<double>());
+      RS_HIP(hipGetLastError());
+      // P^T: fine rows of each coarse column, ascending
+      RS_TRY(L->tptr.alloc(sizeof(int32_t) * ((size_t)nc + 1)));
+      RS_TRY(cnt.alloc(sizeof(int32_t) * ((size_t)nc + 1)));
+      RS_TRY(tfill.alloc(sizeof(int32_t) * ((size_t)nc + 1)));
+      RS_HIP(hipMemsetAsync(cnt.p, 0, sizeof(int32_t) * (nc + 1), s));
+      RS_HIP(hipMemsetAsync(tfill.p, 0, sizeof(int32_t) * (nc + 1), s));
+      k_sa_tcount<<<rs_grid(n), RS_BLOCK, 0, s>>>(n, crp, L->pcnt.as<int32_t>(), L->pci.as<int32_t>(), cnt.as<int32_t>());
+      RS_HIP(hipGetLastError());
+      RS_TRY(scan_i32(cnt.as<int32_t>(), L->tptr.as<int32_t>(), nc + 1, nullptr, s, nullptr));
+      RS_TRY(L->tri.alloc(sizeof(int32_t) * pcap));
+      RS_TRY(trv.alloc(sizeof(double) * pcap));
+      k_sa_tfill<<<rs_grid(n), RS_BLOCK, 0, s>>>(n, crp, L->pcnt.as<int32_t>(), L->pci.as<int32_t>(), L->pv.as<double>(),
+                                                 L->tptr.as<int32_t>(), tfill.as<int32_t>(), L->tri.as<int32_t>(),
+                                                 trv.as<double>());
+      k_sa_tsort<<<rs_grid(nc), RS_BLOCK, 0, s>>>(nc, L->tptr.as<int32_t>(), L->tri.as<int32_t>(), trv.as<double>());
+      RS_TRY(ident.alloc(sizeof(int32_t) * pcap));
+      k_iota<<<rs_grid(pcap), RS_BLOCK, 0, s>>>((int)pcap, ident.as<int32_t>());
+      RS_HIP(hipGetLastError());
+      // A_c = P^T (A P) by the Galerkin row builder, each "member" a P^T entry
+      RS_TRY(off.alloc(sizeof(int32_t) * ((size_t)nc + 1)));
+      k_sa_ccand<<<rs_grid(nc), RS_BLOCK, 0, s>>>(nc, L->tptr.as<int32_t>(), L->tri.as<int32_t>(), apcnt.as<int32_t>(),
+                                                  cnt.as<int32_t>());
+      RS_HIP(hipGetLastError());
+      RS_TRY(scan_i32(cnt.as<int32_t>(), off.as<int32_t>(), nc, &ncand, s, nullptr));
+      if (ncand < 0) return RS_E_NOMEM;
+      RS_TRY(skey.alloc(sizeof(int32_t) * (ncand + 1)));
+      RS_TRY(sval.alloc(sizeof(double) * (ncand + 1)));
+      k_galerkin<rows_sa><<<rs_grid(nc, GAL_BLOCK), GAL_BLOCK, 0, s>>>(
+          nc, L->tptr.as<int32_t>(), ident.as<int32_t>(),
+          rows_sa{L->tri.as<int32_t>(), trv.as<double>(), apoff.as<int32_t>(), apcnt.as<int32_t>(), apci.as<int32_t>(),
+                  apv.as<double>()},
+          L->agg.as<int32_t>(), off.as<int32_t>(), skey.as<int32_t>(), sval.as<double>(), cnt.as<int32_t>());
+      RS_HIP(hipGetLastError());
+      // P and P^T values in the apply precision
+      const size_t es = prec == 64 ? sizeof(double) : sizeof(float);
+      RS_TRY(L->pvt.alloc(es * pcap));
+      RS_TRY(L->trt.alloc(es * pcap));
+      RS_TRY(L->z.alloc(es * ((size_t)n + 1)));
+      if (prec == 64) {
+        k_cast_t<double><<<rs_grid(pcap), RS_BLOCK, 0, s>>>(pcap, L->pv.as<double>(), L->pvt.as<double>());
+        k_cast_t<double><<<rs_grid(pcap), RS_BLOCK, 0, s>>>(pcap, trv.as<double>(), L->trt.as<double>());
+      } else {
+        k_cast_t<float><<<rs_grid(pcap), RS_BLOCK, 0, s>>>(pcap, L->pv.as<double>(), L->pvt.as<float>());
+        k_cast_t<float><<<rs_grid(pcap), RS_BLOCK, 0, s>>>(pcap, trv.as<double>(), L->trt.as<float>());
+      }
+      RS_HIP(hipGetLastError());
+      L->sa = true;
+    } else {
+      // members of each aggregate, ascending
+      RS_TRY(L->mptr.alloc(sizeof(int32_t) * (nc + 1)));
+      RS_TRY(cnt.alloc(sizeof(int32_t) * (nc + 1)));
+      RS_HIP(hipMemsetAsync(cnt.p, 0, sizeof(int32_t) * (nc + 1), s));
+      k_count_members<<<rs_grid(n), RS_BLOCK, 0, s>>>(n, L->agg.as<int32_t>(), cnt.as<int32_t>());
+      RS_HIP(hipGetLastError());
+      // members: at most n (no host read of the exact count)
+      RS_TRY(scan_i32(cnt.as<int32_t>(), L->mptr.as<int32_t>(), nc + 1, nullptr, s, nullptr));
+      RS_TRY(L->mem.alloc(sizeof(int32_t) * ((size_t)n + 1)));
+      RS_HIP(hipMemsetAsync(cnt.p, 0, sizeof(int32_t) * (nc + 1), s));
+      k_fill_members<<<rs_grid(n), RS_BLOCK, 0, s>>>(n, L->agg.as<int32_t>(), L->mptr.as<int32_t>(), cnt.as<int32_t>(), L->mem.as<int32_t>());
+      k_sort_members<<<rs_grid(nc), RS_BLOCK, 0, s>>>(nc, L->mptr.as<int32_t>(), L->mem.as<int32_t>());
+      RS_HIP(hipGetLastError());
+      // Galerkin product
+      RS_TRY(off.alloc(sizeof(int32_t) * (nc + 1)));
+      if (st7) k_cand7<<<rs_grid(nc), RS_BLOCK, 0, s>>>(nc, g.nx, g.ny, g.nz, L->mptr.as<int32_t>(), L->mem.as<int32_t>(), cnt.as<int32_t>());
+      else k_cand<<<rs_grid(nc), RS_BLOCK, 0, s>>>(nc, L->mptr.as<int32_t>(), L->mem.as<int32_t>(), rp, cnt.as<int32_t>());
+      RS_HIP(hipGetLastError());
+      // candidates: the members' row entries, at most this level's nnz
+      RS_TRY(scan_i32(cnt.as<int32_t>(), off.as<int32_t>(), nc, nullptr, s, nullptr));
+      ncand = L->nnz;
+      RS_TRY(skey.alloc(sizeof(int32_t) * (ncand + 1)));
+      RS_TRY(sval.alloc(sizeof(double) * (ncand + 1)));
+      if (st7)
+        k_galerkin<rows_7><<<rs_grid(nc, GAL_BLOCK), GAL_BLOCK, 0, s>>>(
+            nc, L->mptr.as<int32_t>(), L->mem.as<int32_t>(), rows_7{g.nx, g.ny, g.nz, ap7}, L->agg.as<int32_t>(),
+            off.as<int32_t>(), skey.as<int32_t>(), sval.as<double>(), cnt.as<int32_t>());
+      else
+        k_galerkin<rows_csr><<<rs_grid(nc, GAL_BLOCK), GAL_BLOCK, 0, s>>>(
+            nc, L->mptr.as<int32_t>(), L->mem.as<int32_t>(), rows_csr{rp, ci, L->a.as<double>()}, L->agg.as<int32_t>(),
+            off.as<int32_t>(), skey.as<int32_t>(), sval.as<double>(), cnt.as<int32_t>());
+      RS_HIP(hipGetLastError());
+    }
     amg_level *C = new amg_level();
     M->lev.push_back(C);
     C->n = nc;
@@ -1482,8 +1836,12 @@ static rs_status vcycle_t(rs_cpr_s *M, hipStream_t s) {
       k_vc_pre<T><<<rs_grid(L->n), RS_BLOCK, 0, s>>>(L->n, L->rp.as<int32_t>(), L->ci.as<int32_t>(), a,
                                                     L->dl1.as<T>(), L->b.as<T>(), L->r.as<T>());
     }
-    k_vc_restrict<T><<<rs_grid(L->nc), RS_BLOCK, 0, s>>>(L->nc, L->mptr.as<int32_t>(), L->mem.as<int32_t>(),
-                                                         L->r.as<T>(), C->b.as<T>());
+    if (L->sa)
+      k_sa_restrict<T><<<rs_grid(L->nc), RS_BLOCK, 0, s>>>(L->nc, L->tptr.as<int32_t>(), L->tri.as<int32_t>(),
+                                                           L->trt.as<T>(), L->r.as<T>(), C->b.as<T>());
+    else
+      k_vc_restrict<T><<<rs_grid(L->nc), RS_BLOCK, 0, s>>>(L->nc, L->mptr.as<int32_t>(), L->mem.as<int32_t>(),
+                                                           L->r.as<T>(), C->b.as<T>());
   }
   // coarsest
   amg_level *C = M->lev[nl - 1];
@@ -1504,7 +1862,22 @@ static rs_status vcycle_t(rs_cpr_s *M, hipStream_t s) {
   for (int l = nl - 2; l >= 0; --l) {
     amg_level *L = M->lev[l], *Cl = M->lev[l + 1];
     const T *a = (M->prec == 64) ? (const T *)L->a.p : (const T *)L->ap.p;
-    if (l == 0 && L->s7.p) {
+    if (L->sa) {
+      // z = y + P x_c, then the post-sweep from z
+      const bool st = l == 0 && L->s7.p;
+      k_sa_prolong<T><<<rs_grid(L->n), RS_BLOCK, 0, s>>>(L->n, L->rp.as<int32_t>(), L->pcnt.as<int32_t>(),
+                                                         L->pci.as<int32_t>(), L->pvt.as<T>(),
+                                                         st ? L->y.as<T>() : nullptr, L->b.as<T>(), L->dl1.as<T>(),
+                                                         Cl->xp<T>(), L->z.as<T>());
+      if (st) {
+        const grid3 &g = M->A->g;
+        k_vc_post7z<T><<<rs_grid(L->n), RS_BLOCK, 0, s>>>(L->n, g.nx, (int)g.nxy, L->s7.as<T>(), L->dl1.as<T>(),
+                                                          L->b.as<T>(), L->z.as<T>(), L->xp<T>());
+      } else {
+        k_vc_postz<T><<<rs_grid(L->n), RS_BLOCK, 0, s>>>(L->n, L->rp.as<int32_t>(), L->ci.as<int32_t>(), a,
+                                                         L->dl1.as<T>(), L->b.as<T>(), L->z.as<T>(), L->xp<T>());
+      }
+    } else if (l == 0 && L->s7.p) {
       const grid3 &g = M->A->g;
       k_vc_post7<T><<<rs_grid(L->n), RS_BLOCK, 0, s>>>(L->n, g.nx, (int)g.nxy, L->s7.as<T>(), L->dl1.as<T>(),
                                                        L->agg.as<int32_t>(), L->b.as<T>(), L->y.as<T>(),
@@ -1549,6 +1922,35 @@ extern "C" rs_status rs_cpr_level(rs_cpr M, int l, int *h_n, int64_t *h_nnz, int
       for (int i = 0; i < L->n; ++i) h_dl1[i] = t[i];
     }
   }
+  return RS_OK;
+}
+
+extern "C" rs_status rs_cpr_level_p(rs_cpr M, int l, int64_t *h_nnz, int32_t *h_rp, int32_t *h_ci, double *h_v) {
+  if (!M || !h_nnz || l < 0 || l >= M->nlev - 1 || !M->lev[l]->sa) return RS_E_ARG;
+  RS_HIP(hipDeviceSynchronize());
+  amg_level *L = M->lev[l];
+  const int n = L->n;
+  std::vector<int32_t> rp(n + 1), cnt(n + 1);
+  RS_HIP(hipMemcpy(rp.data(), L->rp.p, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToHost));
+  RS_HIP(hipMemcpy(cnt.data(), L->pcnt.p, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
+  int64_t nnz = 0;
+  for (int i = 0; i < n; ++i) nnz += cnt[i];
+  *h_nnz = nnz;
+  if (!h_rp && !h_ci && !h_v) return RS_OK;
+  const int64_t cap = (int64_t)rp[n] + n;
+  std::vector<int32_t> ci(cap > 0 ? cap : 1);
+  std::vector<double> v(cap > 0 ? cap : 1);
+  RS_HIP(hipMemcpy(ci.data(), L->pci.p, sizeof(int32_t) * cap, hipMemcpyDeviceToHost));
+  RS_HIP(hipMemcpy(v.data(), L->pv.p, sizeof(double) * cap, hipMemcpyDeviceToHost));
+  int64_t w = 0;
+  for (int i = 0; i < n; ++i) {
+    if (h_rp) h_rp[i] = (int32_t)w;
+    for (int k = 0; k < cnt[i]; ++k, ++w) {
+      if (h_ci) h_ci[w] = ci[(int64_t)rp[i] + i + k];
+      if (h_v) h_v[w] = v[(int64_t)rp[i] + i + k];
+    }
+  }
+  if (h_rp) h_rp[n] = (int32_t)w;
   return RS_OK;
 }
 

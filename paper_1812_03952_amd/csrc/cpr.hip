@@ -208,6 +208,8 @@ extern "C" void rs_cpr_opts_default(rs_cpr_opts *o) {
   o->lu_max = 2048;
   o->coarse_sweeps = 4;
   o->stages = 2;
+  o->smooth = 0;
+  o->trunc = 1e-2;
 }
 
 rs_cpr_s::~rs_cpr_s() {
@@ -246,7 +248,8 @@ extern "C" rs_status rs_cpr_setup(rs_bsr A, rs_dcpl D, const rs_cpr_opts *o, voi
   if ((opts.smoother != RS_SM_BJ && opts.smoother != RS_SM_DILU && !ras) ||
       (ras && rs_ras_check_shape(A->g, D->prec) != RS_OK) || opts.coarse_n < 1 ||
       opts.max_levels < 1 || opts.lu_max < 1 || opts.lu_max > 8192 || opts.coarse_sweeps < 1 ||
-      (opts.stages != 2 && opts.stages != 3))
+      (opts.stages != 2 && opts.stages != 3) || (opts.smooth != 0 && opts.smooth != 1) ||
+      !(opts.trunc >= 0.0 && opts.trunc <= 1.0))
     return RS_E_ARG;
   hipStream_t s = rs_stream(stream);
   hipStream_t ss = opts.smoother == RS_SM_DILU ? nullptr : side_stream();

@@ -104,6 +104,12 @@ struct amg_level {
   // level 0 only: values by stencil slot [7][n] (zero off the grid) and
   // y = b ./ d, apply precision, for the structured cycle kernels
   dbuf s7, y;
+  // smoothed prolongator (rs_cpr_opts.smooth): row i of P at rp[i] + i,
+  // pcnt[i] entries (coarse columns pci, FP64 values pv, apply-precision
+  // values pvt); P^T by coarse row (tptr, fine rows tri ascending, values
+  // trt in apply precision); z = y + P x_c in the cycle
+  bool sa = false;
+  dbuf pcnt, pci, pv, pvt, tptr, tri, trt, z;
   template <class T> T *xp() const { return x.as<T>() + xoff; }
 };
 

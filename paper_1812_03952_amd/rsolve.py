@@ -30,7 +30,7 @@ class RsError(RuntimeError):
 class CprOpts(C.Structure):
     _fields_ = [("smoother", C.c_int), ("theta", C.c_double), ("max_row_sum", C.c_double),
                 ("coarse_n", C.c_int), ("max_levels", C.c_int), ("lu_max", C.c_int),
-                ("coarse_sweeps", C.c_int), ("stages", C.c_int)]
+                ("coarse_sweeps", C.c_int), ("stages", C.c_int), ("smooth", C.c_int), ("trunc", C.c_double)]
 
 
 class GmresOpts(C.Structure):
@@ -98,6 +98,7 @@ def lib():
             "rs_dcpl_get": (_i, [_vp, _vp, _vp]),
             "rs_cpr_nlevels": (_i, [_vp]),
             "rs_cpr_level": (_i, [_vp, _i, C.POINTER(_i), C.POINTER(_i64), _vp, _vp, _vp, _vp, _vp]),
+            "rs_cpr_level_p": (_i, [_vp, _i, C.POINTER(_i64), _vp, _vp, _vp]),
             "rs_cpr_smoother_get": (_i, [_vp, _vp]),
             "rs_cpr_vcycle": (_i, [_vp, _vp, _vp, _vp]),
             "rs_dense_inverse": (_i, [_i, _vp, _vp, _vp]),
@@ -438,6 +439,17 @@ def cpr_level(M: Cpr, l: int) -> dict:
     _check(L.rs_cpr_level(M.h, l, None, None, rp.ctypes.data, ci.ctypes.data, a.ctypes.data,
                           d.ctypes.data, agg.ctypes.data), "rs_cpr_level")
     return dict(n=n, nnz=nnz, rp=rp, ci=ci[:nnz], a=a[:nnz], dl1=d[:n], agg=agg[:n])
+
+
+def cpr_level_p(M: Cpr, l: int):
+    """Smoothed prolongator of level l as (rp, ci, v) host arrays."""
+    L = lib()
+    nnz = C.c_int64(0)
+    _check(L.rs_cpr_level_p(M.h, l, C.byref(nnz), None, None, None), "rs_cpr_level_p")
+    n = cpr_level(M, l)["n"]
+    rp = np.zeros(n + 1, np.int32); ci = np.zeros(max(nnz.value, 1), np.int32); v = np.zeros(max(nnz.value, 1))
+    _check(L.rs_cpr_level_p(M.h, l, C.byref(nnz), rp.ctypes.data, ci.ctypes.data, v.ctypes.data), "rs_cpr_level_p")
+    return rp, ci[:nnz.value], v[:nnz.value]
 
 
 def cpr_smoother_get(M: Cpr):

@@ -81,9 +81,12 @@ typedef struct {
   int smoother;        /* RS_SM_BJ, RS_SM_DILU, RS_SM_RAS or RS_SM_RAS1 (default DILU) */
   double theta;        /* AMG strength threshold (default 0.5, Fig. fig-ds-amg-par) */
   double max_row_sum;  /* AMG weak-row threshold (default 0.9, same figure)       */
-  int coarse_n;        /* stop coarsening at <= this many rows (default 500)     */
+  int coarse_n;        /* stop coarsening at <= this many rows (default 256)     */
   int max_levels;      /* AMG depth limit (default 20)                           */
-  int lu_max;          /* largest coarsest level inverted densely (default 2048) */
+  int lu_max;          /* largest coarsest level inverted densely (default 256; a
+                          larger coarsest level, one on which no aggregate forms,
+                          is relaxed by coarse_sweeps l1-Jacobi sweeps; at most
+                          8192)                                                 */
   int coarse_sweeps;   /* l1-Jacobi sweeps if the coarsest is larger (default 4) */
   int stages;          /* 2: pressure then full (default); 3: CPR-FPF, full,
                           pressure, full (Algorithm pc-fpf)                       */

@@ -33,7 +33,10 @@
  *              A_c = P^T (A P), R = P^T.
  *   smoother   l1-Jacobi x += (b - A x) / d,  d_i = sgn(a_ii) sum_j |a_ij|;
  *              one sweep before and one after the coarse correction.
- *   coarsest   dense LU with partial pivoting in FP64.
+ *   coarsest   dense LU with partial pivoting in FP64 up to lu_max rows;
+ *              a larger coarsest level (one that no aggregate forms on,
+ *              since all its rows are weak) is relaxed by coarse_sweeps
+ *              l1-Jacobi sweeps from zero, as the figure relaxes there.
  * Pinned by: strength and aggregation brute force on small graphs, the
  * Galerkin identity against dense P^T A P, and the V-cycle as a linear
  * operator against its dense two-level formula; the smoothed prolongator by
@@ -74,9 +77,12 @@ struct or_amg {
 void or_amg_defaults(or_amg_opts *o) {
   o->theta = 0.5;          /* Fig. fig-ds-amg-par: strength    */
   o->max_row_sum = 0.9;    /* Fig. fig-ds-amg-par: max_row_sum */
-  o->coarse_n = 500;
+  /* the figure relaxes on the coarsest level (coarsest_relax_type); here a
+   * coarsest level of at most lu_max rows is solved exactly and a larger one
+   * (a level whose rows are all weak, so no aggregate forms) is relaxed */
+  o->coarse_n = 256;
   o->max_levels = 20;
-  o->lu_max = 2048;
+  o->lu_max = 256;
   o->coarse_sweeps = 4;
   o->smooth = 0;
   o->trunc = 1e-2;         /* Fig. fig-ds-amg-par: trunc error */

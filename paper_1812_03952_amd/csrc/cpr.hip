@@ -203,9 +203,9 @@ extern "C" void rs_cpr_opts_default(rs_cpr_opts *o) {
   o->smoother = RS_SM_DILU;
   o->theta = 0.5;
   o->max_row_sum = 0.9;
-  o->coarse_n = 500;
+  o->coarse_n = 256;
   o->max_levels = 20;
-  o->lu_max = 2048;
+  o->lu_max = 256;
   o->coarse_sweeps = 4;
   o->stages = 2;
   o->smooth = 0;

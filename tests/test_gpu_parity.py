@@ -162,9 +162,10 @@ def test_vcycle(coarse_n, max_levels):
     launch-per-column one (larger coarsest level)."""
     p = _prob((33, 17, 9), sigma=2.0, shale=0.1)
     A = oracle.assemble(p)
-    Mo = oracle.CPR(A, coarse_n=coarse_n, max_levels=max_levels)
+    Mo = oracle.CPR(A, coarse_n=coarse_n, max_levels=max_levels, lu_max=8192)
     B = upload(A)
-    Mg = rs.cpr_setup(B, rs.decouple(B, rs.ABF, 64), rs.cpr_opts(coarse_n=coarse_n, max_levels=max_levels))
+    Mg = rs.cpr_setup(B, rs.decouple(B, rs.ABF, 64),
+                      rs.cpr_opts(coarse_n=coarse_n, max_levels=max_levels, lu_max=8192))
     nc = rs.cpr_level(Mg, rs.cpr_nlevels(Mg) - 1)["n"]
     assert (nc > 256) == (coarse_n == 5000)
     b = np.random.default_rng(5).standard_normal(A.n)
@@ -472,7 +473,7 @@ def test_coarsest_inverse_paths(dims, lo, hi):
     LU."""
     p = _prob(dims, sigma=2.0, shale=0.1)
     A = oracle.assemble(p)
-    opts = dict(coarse_n=A.n - 1, max_levels=2)
+    opts = dict(coarse_n=A.n - 1, max_levels=2, lu_max=2048)
     Mo = oracle.CPR(A, **opts)
     B = upload(A)
     Mg = rs.cpr_setup(B, rs.decouple(B, rs.ABF, 64), rs.cpr_opts(**opts))

@@ -21,3 +21,17 @@ def upload(A: "oracle.BSR"):
 def relerr(a, b):
     a = np.asarray(a); b = np.asarray(b)
     return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def maxrel(a, b):
+    """Largest entry error relative to the largest reference entry: catches a
+    local error that the 2-norm of the whole vector would average away."""
+    a = np.asarray(a); b = np.asarray(b)
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+def assert_close(got, ref, tol):
+    """2-norm relative error within tol and every entry within 10 tol of the
+    reference's largest entry."""
+    e2, emax = relerr(got, ref), maxrel(got, ref)
+    assert e2 <= tol and emax <= 10 * tol, (e2, emax, tol)

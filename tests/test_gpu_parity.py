@@ -12,7 +12,7 @@ import torch
 import oracle
 import synth
 from paper_1812_03952_amd import rsolve as rs
-from gpu_util import dev, relerr, upload
+from gpu_util import assert_close, dev, relerr, upload
 
 pytestmark = pytest.mark.gpu
 
@@ -172,7 +172,7 @@ def test_vcycle(coarse_n, max_levels):
     x = torch.empty(A.n, dtype=torch.float64, device="cuda")
     rs.cpr_vcycle(Mg, dev(b), x)
     ref = Mo.amg().vcycle(b)
-    assert relerr(x.cpu().numpy(), ref) <= 1e-11
+    assert_close(x.cpu().numpy(), ref, 1e-11)
 
 
 @pytest.mark.parametrize("smoother", [rs.SM_BJ, rs.SM_DILU, rs.SM_RAS])
@@ -187,7 +187,7 @@ def test_cpr_apply(method, smoother, dims):
     r = np.random.default_rng(7).standard_normal(4 * A.n)
     z = torch.empty(4 * A.n, dtype=torch.float64, device="cuda")
     rs.cpr_apply(Mg, dev(r), z)
-    assert relerr(z.cpu().numpy(), Mo.apply(r)) <= 1e-10
+    assert_close(z.cpu().numpy(), Mo.apply(r), 1e-10)
 
 
 @pytest.mark.parametrize("dims,prec", [((5, 300, 2), 64), ((3, 480, 2), 64), ((3, 520, 2), 32),
@@ -205,7 +205,7 @@ def test_ras_wide_layers(dims, prec):
     r = np.random.default_rng(9).standard_normal(4 * A.n)
     z = torch.empty(4 * A.n, dtype=torch.float64, device="cuda")
     rs.cpr_apply(Mg, dev(r), z)
-    assert relerr(z.cpu().numpy(), Mo.apply(r)) <= (1e-10 if prec == 64 else 1e-4)
+    assert_close(z.cpu().numpy(), Mo.apply(r), 1e-10 if prec == 64 else 1e-4)
 
 
 def test_ras_layer_limit():
@@ -233,10 +233,10 @@ def test_cpr_apply_fpf(method, smoother, dims):
     r = np.random.default_rng(7).standard_normal(4 * A.n)
     z = torch.empty(4 * A.n, dtype=torch.float64, device="cuda")
     rs.cpr_apply(Mg, dev(r), z)
-    assert relerr(z.cpu().numpy(), Mo.apply(r)) <= 1e-10
+    assert_close(z.cpu().numpy(), Mo.apply(r), 1e-10)
     Mg32 = rs.cpr_setup(B, rs.decouple(B, method, 32), rs.cpr_opts(smoother=smoother, stages=3))
     rs.cpr_apply(Mg32, dev(r), z)
-    assert relerr(z.cpu().numpy(), Mo.apply(r)) <= 1e-4
+    assert_close(z.cpu().numpy(), Mo.apply(r), 1e-4)
 
 
 @pytest.mark.parametrize("prec", [64, 32])
@@ -279,7 +279,7 @@ def test_cpr_apply_fp32_close_to_fp64():
     r = np.random.default_rng(7).standard_normal(4 * A.n)
     z = torch.empty(4 * A.n, dtype=torch.float64, device="cuda")
     rs.cpr_apply(Mg, dev(r), z)
-    assert relerr(z.cpu().numpy(), Mo.apply(r)) <= 1e-4
+    assert_close(z.cpu().numpy(), Mo.apply(r), 1e-4)
 
 
 @pytest.mark.parametrize("smoother", [rs.SM_DILU, rs.SM_RAS])
@@ -380,7 +380,7 @@ def test_dilu_pipeline_repeatable(prec):
     if prec == 64:
         Mo = oracle.CPR(A)
         assert np.array_equal(rs.cpr_smoother_get(Mg), Mo.dinv2())
-        assert relerr(z0.cpu().numpy(), Mo.apply(r.cpu().numpy())) <= 1e-10
+        assert_close(z0.cpu().numpy(), Mo.apply(r.cpu().numpy()), 1e-10)
 
 
 def test_pool_reuse_is_transparent():
@@ -482,4 +482,4 @@ def test_coarsest_inverse_paths(dims, lo, hi):
     b = np.random.default_rng(11).standard_normal(A.n)
     x = torch.empty(A.n, dtype=torch.float64, device="cuda")
     rs.cpr_vcycle(Mg, dev(b), x)
-    assert relerr(x.cpu().numpy(), Mo.amg().vcycle(b)) <= 1e-11
+    assert_close(x.cpu().numpy(), Mo.amg().vcycle(b), 1e-11)

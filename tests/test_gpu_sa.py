@@ -1,7 +1,8 @@
 """Smoothed-aggregation pressure AMG (rs_cpr_opts.smooth = 1) against the
 oracle's, through the C-ABI: the hierarchy (every level's matrix, l1
 diagonal, aggregates and the smoothed, truncated prolongator) bit for bit in
-FP64; the V-cycle, the CPR apply and CPR-GMRES solves against the oracle."""
+FP64; the V-cycle, the CPR apply, CPR-GMRES, BiCGSTAB, the three-stage CPR-FPF
+and the adjoint solve against the oracle or a dense solve."""
 import numpy as np
 import pytest
 import torch
@@ -135,3 +136,49 @@ def test_sa_options_rejected():
                dict(smooth=1, trunc=float("nan"))):
         with pytest.raises(rs.RsError):
             rs.cpr_setup(B, D, rs.cpr_opts(**kw))
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+def test_sa_bicgstab_and_fpf(prec):
+    """The smoothed pressure stage inside BiCGSTAB and inside the three-stage
+    CPR-FPF: true residual to 1e-8, solution within 1e-6 of the oracle's tight
+    solve with the same preconditioner, FP64 iteration counts equal."""
+    p = synth.config(0)
+    A = oracle.assemble(p)
+    B = upload(A)
+    for solver, stages in (("bicgstab", 2), ("gmres", 3)):
+        Mo = oracle.CPR(A, smoother=oracle.SM_RAS, smooth=1, stages=stages)
+        run = oracle.bicgstab if solver == "bicgstab" else oracle.gmres
+        _, io = run(A, p.b, Mo, rtol=1e-8)
+        xt, _ = oracle.gmres(A, p.b, Mo, rtol=1e-13)
+        Mg = rs.cpr_setup(B, rs.decouple(B, rs.ABF, prec), rs.cpr_opts(smoother=rs.SM_RAS, smooth=1, stages=stages))
+        x = torch.zeros(4 * A.n, dtype=torch.float64, device="cuda")
+        if solver == "bicgstab":
+            info = rs.bicgstab_solve(B, Mg, dev(p.b), x, rs.bicgstab_opts(zero_guess=1))
+        else:
+            info = rs.gmres_solve(B, Mg, dev(p.b), x, rs.gmres_opts(zero_guess=1))
+        xg = x.cpu().numpy()
+        res = np.linalg.norm(p.b - oracle.spmv(A, xg)) / np.linalg.norm(p.b)
+        assert info["return"] == 0 and res <= 1e-8, (solver, stages, res)
+        if prec == 64:
+            assert info["iters"] == io["iters"], (solver, stages)
+        assert relerr(xg, xt) <= 1e-6, (solver, stages)
+
+
+def test_sa_adjoint():
+    """The adjoint solve builds its own CPR on A^T with the caller's options:
+    with the smoothed pressure stage, lambda solves A^T lambda = w (checked
+    against a dense solve on a small grid)."""
+    p = _prob((6, 5, 4), sigma=1.5)
+    A = oracle.assemble(p)
+    Ad = A.dense()
+    B = upload(A)
+    w = np.random.default_rng(3).standard_normal(4 * A.n)
+    lam = torch.zeros(4 * A.n, dtype=torch.float64, device="cuda")
+    info = rs.adjoint_solve(B, dev(w), lam, rs.ABF, 64, rs.cpr_opts(smoother=rs.SM_RAS, smooth=1, coarse_n=20),
+                            rs.gmres_opts(rtol=1e-12, maxit=600))
+    assert info["return"] == 0 and info["relres"] <= 1e-12
+    lg = lam.cpu().numpy()
+    ref = np.linalg.solve(Ad.T, w)
+    assert relerr(lg, ref) <= max(1e-12 * np.linalg.cond(Ad), 1e-10)
+    assert np.linalg.norm(w - Ad.T @ lg) <= 1.0001e-12 * np.linalg.norm(w)

@@ -940,18 +940,11 @@ __global__ __launch_bounds__(256) void k_vc_post(int n, const int32_t *__restric
 // its values are stored by stencil slot and the neighbours follow from the
 // cell index (no column indices).  Slots run in column order and off-grid
 // slots hold zeros, so each sum is the same sequence of operations as the
-// row of the CSR form.  y = b ./ d is formed once instead of at every use.
+// row of the CSR form.
 template <class T>
 __global__ __launch_bounds__(256) void k_cast7(int64_t m, const double *__restrict__ a, T *__restrict__ o) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t < m) o[t] = (T)a[t];
-}
-
-template <class T>
-__global__ __launch_bounds__(256) void k_vc_y(int n, const T *__restrict__ b, const T *__restrict__ d,
-                                               T *__restrict__ y) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) y[i] = b[i] / d[i];
 }
 
 __device__ __forceinline__ int nbr7(int i, int s, int n, int nx, int nxy) {
@@ -960,16 +953,23 @@ __device__ __forceinline__ int nbr7(int i, int s, int n, int nx, int nxy) {
   return (q < 0 || q >= n) ? i : q;             // off-grid slots hold zero values
 }
 
+// pre-smoothing from x = 0 and the residual: y = b ./ d (kept for the
+// post-smoothing), r = b - A y with each neighbour's y_q = b_q / d_q formed
+// where it is used (the same division, so the same value as a stored y)
 template <class T>
 __global__ __launch_bounds__(256) void k_vc_pre7(int n, int nx, int nxy, const T *__restrict__ s7,
-                                                  const T *__restrict__ y, const T *__restrict__ b,
-                                                  T *__restrict__ r) {
+                                                  const T *__restrict__ d, const T *__restrict__ b,
+                                                  T *__restrict__ y, T *__restrict__ r) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   T s = 0;
 #pragma unroll
-  for (int k = 0; k < 7; ++k) s = fma(s7[(int64_t)k * n + i], y[nbr7(i, k, n, nx, nxy)], s);
+  for (int k = 0; k < 7; ++k) {
+    const int q = nbr7(i, k, n, nx, nxy);
+    s = fma(s7[(int64_t)k * n + i], b[q] / d[q], s);
+  }
   r[i] = b[i] - s;
+  y[i] = b[i] / d[i];
 }
 
 template <class T>
@@ -1829,9 +1829,8 @@ static rs_status vcycle_t(rs_cpr_s *M, hipStream_t s) {
     const T *a = (M->prec == 64) ? (const T *)L->a.p : (const T *)L->ap.p;
     if (l == 0 && L->s7.p) {
       const grid3 &g = M->A->g;
-      k_vc_y<T><<<rs_grid(L->n), RS_BLOCK, 0, s>>>(L->n, L->b.as<T>(), L->dl1.as<T>(), L->y.as<T>());
-      k_vc_pre7<T><<<rs_grid(L->n), RS_BLOCK, 0, s>>>(L->n, g.nx, (int)g.nxy, L->s7.as<T>(), L->y.as<T>(),
-                                                      L->b.as<T>(), L->r.as<T>());
+      k_vc_pre7<T><<<rs_grid(L->n), RS_BLOCK, 0, s>>>(L->n, g.nx, (int)g.nxy, L->s7.as<T>(), L->dl1.as<T>(),
+                                                      L->b.as<T>(), L->y.as<T>(), L->r.as<T>());
     } else {
       k_vc_pre<T><<<rs_grid(L->n), RS_BLOCK, 0, s>>>(L->n, L->rp.as<int32_t>(), L->ci.as<int32_t>(), a,
                                                     L->dl1.as<T>(), L->b.as<T>(), L->r.as<T>());

@@ -53,42 +53,21 @@ __device__ __forceinline__ int64_t wf_pos(int i, int j, int nx, int ny) {
 // rh = D^{-1} (r~ - A~[:,0] x_p) in wavefront order, and x_p permuted alike.
 // x_p carries nx*ny zero guard entries on each side, so every stencil
 // neighbour is in bounds, and off-grid column-0 entries are zero.
-template <class T>
-__global__ __launch_bounds__(256) void k_ras_in(int nx, int ny, int64_t n, const T *__restrict__ rt,
-                                                const T *__restrict__ col0, const T *__restrict__ xp,
-                                                const T *__restrict__ dinv2, T *__restrict__ rh,
-                                                T *__restrict__ xpw) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= 4 * n) return;                               // whole quads (4n and the block are multiples of 4)
-  const int64_t nxy = (int64_t)nx * ny, c = t >> 2;
-  const int row = (int)(t & 3);
-  const int64_t off[7] = {-nxy, -(int64_t)nx, -1, 0, 1, (int64_t)nx, nxy};
-  T col[8], dv[4];
-  ld8v(col0 + c * 32 + 8 * row, col);
-  ld4v(dinv2 + c * 16 + 4 * row, dv);
-  T v = rt[t];
-#pragma unroll
-  for (int s = 0; s < 7; ++s) v = v - col[s] * xp[c + off[s]];
-  const T o = quad_mv<T>(dv, v);
-  const int64_t k = c / nxy, rem = c - k * nxy;
-  const int j = (int)(rem / nx), i = (int)(rem - (int64_t)j * nx);
-  const int64_t p = k * nxy + wf_pos(i, j, nx, ny);
-  rh[4 * p + row] = o;
-  if (row == 0) xpw[p] = xp[c];
-}
-
-// The same per tile of RI x RJ cells of a layer (4 lanes per cell, one
-// workgroup of 4*RI*RJ threads): the results are staged in LDS in the tile's
-// own wavefront order, in which the cells of one anti-diagonal of the tile
-// are consecutive in the layer's wavefront order too, and written back as
-// runs of up to min(RI, RJ) cells instead of one scattered cell per quad.
+// Per tile of RI x RJ cells of a layer (4 lanes per cell, one workgroup of
+// 4*RI*RJ threads): the results are staged in LDS in the tile's own
+// wavefront order, in which the cells of one anti-diagonal of the tile are
+// consecutive in the layer's wavefront order too, and written back as runs
+// of up to min(RI, RJ) cells instead of one scattered cell per quad.
+// tickets (optional): the FP32 sweeps' two ticket counters, zeroed here for
+// the forward and backward sweeps that follow on the stream.
 constexpr int RI = 16, RJ = 16;
 template <class T>
 __global__ __launch_bounds__(4 * RI * RJ) void k_ras_in_tile(int nx, int ny, int64_t n, const T *__restrict__ rt,
                                                              const T *__restrict__ col0, const T *__restrict__ xp,
                                                              const T *__restrict__ dinv2, T *__restrict__ rh,
-                                                             T *__restrict__ xpw) {
+                                                             T *__restrict__ xpw, int *__restrict__ tickets) {
   __shared__ T so[RI * RJ][4];
+  if (tickets && blockIdx.x == 0 && threadIdx.x < 2) tickets[threadIdx.x] = 0;
   __shared__ T sx[RI * RJ];
   __shared__ int sab[RI * RJ];
   const int tx = (nx + RI - 1) / RI, ty = (ny + RJ - 1) / RJ;
@@ -1406,8 +1385,11 @@ rs_status rs_ras_apply_run(rs_cpr_s *M, const T *xp, T *out, hipStream_t s) {
   const T *P0 = ov1 ? M->rdv0.as<T>() : M->dinv2.as<T>();
   {
     const int64_t tiles = (int64_t)g.nz * ((g.nx + RI - 1) / RI) * ((g.ny + RJ - 1) / RJ);
+    // the tickets of the sweeps below are zeroed here (overlap 0); the
+    // overlapping form sweeps several times and zeroes them before each
+    int *tk = (sizeof(T) == 4 && !ov1) ? M->rctl.as<int>() : nullptr;
     k_ras_in_tile<T><<<(unsigned)tiles, 4 * RI * RJ, 0, s>>>(g.nx, g.ny, g.n, M->rt.as<T>(), D->col0.as<T>(), xp,
-                                                             P0, rh, xpw);
+                                                             P0, rh, xpw, tk);
   }
   RS_HIP(hipGetLastError());
   const sweep_shape sh = ras_sweep_shape(g.ny);
@@ -1433,7 +1415,7 @@ rs_status rs_ras_apply_run(rs_cpr_s *M, const T *xp, T *out, hipStream_t s) {
     if (H <= 128) {
       const size_t rb2 = sizeof(float) * 8 * (size_t)(H + 2);
       fwd = [=](const T *blk, const T *r, T *yo) {
-        k_ras_reset<<<1, 64, 0, s>>>(ctl);
+        if (ov1) k_ras_reset<<<1, 64, 0, s>>>(ctl);
         const uint32_t tag = ++M->repoch;
         switch (nb) {
 #define RS_F2(NB) case NB: k_ras_fwd2<NB><<<nwg, nt2, RAS_SLOTS * ras_fwd2_slot(NB) + rb2, s>>>(g.nx, g.ny, g.nz, S, H, g.n, lw2, blk, r, yo, ctl, xw, tag); break;
@@ -1442,7 +1424,7 @@ rs_status rs_ras_apply_run(rs_cpr_s *M, const T *xp, T *out, hipStream_t s) {
         }
       };
       bwd = [=](const T *blk, const T *yi, const T *xw_p, T *o) {
-        k_ras_reset<<<1, 64, 0, s>>>(ctl);
+        if (ov1) k_ras_reset<<<1, 64, 0, s>>>(ctl);
         const uint32_t tag = ++M->repoch;
         switch (nb) {
 #define RS_B2(NB) case NB: k_ras_bwd2<NB><<<nwg, nt2, RAS_SLOTS * ras_bwd2_slot(NB) + 2 * rb2, s>>>(g.nx, g.ny, g.nz, S, H, g.n, lw2, blk, yi, xw_p, o, ctl, xw, tag); break;
@@ -1452,14 +1434,14 @@ rs_status rs_ras_apply_run(rs_cpr_s *M, const T *xp, T *out, hipStream_t s) {
       };
     } else {
     fwd = [=](const T *blk, const T *r, T *yo) {
-      k_ras_reset<<<1, 64, 0, s>>>(ctl);
+      if (ov1) k_ras_reset<<<1, 64, 0, s>>>(ctl);
       const uint32_t tag = ++M->repoch;
       if (u1 == 1) k_ras_fwd1<1, 5><<<nwg, nt1, rb, s>>>(g.nx, g.ny, g.nz, S, H, g.n, lw1, blk, r, yo, ctl, xw, tag);
       else if (u1 == 2) k_ras_fwd1<2, 3><<<nwg, nt1, rb, s>>>(g.nx, g.ny, g.nz, S, H, g.n, lw1, blk, r, yo, ctl, xw, tag);
       else k_ras_fwd1<4, 2><<<nwg, nt1, rb, s>>>(g.nx, g.ny, g.nz, S, H, g.n, lw1, blk, r, yo, ctl, xw, tag);
     };
     bwd = [=](const T *blk, const T *yi, const T *xw_p, T *o) {
-      k_ras_reset<<<1, 64, 0, s>>>(ctl);
+      if (ov1) k_ras_reset<<<1, 64, 0, s>>>(ctl);
       const uint32_t tag = ++M->repoch;
       if (u1 == 1) k_ras_bwd1<1, 5><<<nwg, nt1, 2 * rb, s>>>(g.nx, g.ny, g.nz, S, H, g.n, lw1, blk, yi, xw_p, o, ctl, xw, tag);
       else if (u1 == 2) k_ras_bwd1<2, 3><<<nwg, nt1, 2 * rb, s>>>(g.nx, g.ny, g.nz, S, H, g.n, lw1, blk, yi, xw_p, o, ctl, xw, tag);

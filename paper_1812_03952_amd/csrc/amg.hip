@@ -99,8 +99,7 @@ rs_status scan_i32(const int32_t *in, int32_t *out, int64_t n, int64_t *total, h
     if (dtotal) RS_HIP(hipMemcpyAsync(dtotal, bs.p, sizeof(int32_t), hipMemcpyDeviceToDevice, s));
     if (total) {
       int32_t t = 0;
-      RS_HIP(hipMemcpyAsync(&t, bs.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-      RS_HIP(hipStreamSynchronize(s));
+      RS_TRY(rs_wait_read(&t, bs.p, sizeof(int32_t), s));
       *total = t;
     }
     return RS_OK;
@@ -1626,8 +1625,7 @@ rs_status rs_amg_build(rs_cpr_s *M, hipStream_t s) {
       }
       RS_HIP(hipGetLastError());
       int h = 0;
-      RS_HIP(hipMemcpyAsync(&h, und.as<int>() + MIS_BATCH - 1, sizeof(int), hipMemcpyDeviceToHost, s));
-      RS_HIP(hipStreamSynchronize(s));
+      RS_TRY(rs_wait_read(&h, und.as<int>() + MIS_BATCH - 1, sizeof(int), s));
       if (h == 0) break;
     }
     // aggregates
@@ -1792,8 +1790,7 @@ rs_status rs_amg_build(rs_cpr_s *M, hipStream_t s) {
                                                               C->a.as<double>(), C->ap.as<float>(), C->dl1.as<float>());
     RS_HIP(hipGetLastError());
     int h[2] = {0, 0};
-    RS_HIP(hipMemcpyAsync(h, flag.p, sizeof(int) * 2, hipMemcpyDeviceToHost, s));
-    RS_HIP(hipStreamSynchronize(s));
+    RS_TRY(rs_wait_read(h, flag.p, sizeof(int) * 2, s));
     if (h[0]) return RS_E_HIP;
     C->nnz = h[1];
   }
@@ -1812,11 +1809,10 @@ rs_status rs_amg_build(rs_cpr_s *M, hipStream_t s) {
     k_densify<<<rs_grid(nC), RS_BLOCK, 0, s>>>(nC, C->rp.as<int32_t>(), C->ci.as<int32_t>(), C->a.as<double>(), G.as<double>());
     RS_TRY(dense_inverse_run(nC, G.as<double>(), M->cinv.as<double>(), flag.as<int>(), s));
     int h = 0;
-    RS_HIP(hipMemcpyAsync(&h, flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
-    RS_HIP(hipStreamSynchronize(s));
+    RS_TRY(rs_wait_read(&h, flag.p, sizeof(int), s));
     if (h) return RS_E_SINGULAR;
   }
-  RS_HIP(hipStreamSynchronize(s));
+  RS_TRY(rs_wait(s));
   return RS_OK;
 }
 

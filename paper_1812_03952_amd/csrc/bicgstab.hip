@@ -237,9 +237,8 @@ static void bcg_reduce(int K, int nparts, int stride, const double *part, double
 }
 
 static rs_status bcg_read(double *h, const double *d, int cnt, hipStream_t s) {
-  RS_HIP(hipMemcpyAsync(h, d, sizeof(double) * cnt, hipMemcpyDeviceToHost, s));
-  RS_HIP(hipStreamSynchronize(s));
-  return RS_OK;
+  RS_HIP(hipMemcpyAsync(h, d, sizeof(double) * cnt, hipMemcpyDeviceToHost, s));   // h is pinned
+  return rs_wait(s);
 }
 
 template <class TZ>

@@ -267,8 +267,7 @@ static rs_status load_values(rs_bsr_s *A, const double *d_vals, hipStream_t s) {
   RS_HIP(hipGetLastError());
   int h = 0;
   A->ref = nullptr;                     // A holds its own copy again
-  RS_HIP(hipMemcpyAsync(&h, flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
-  RS_HIP(hipStreamSynchronize(s));
+  RS_TRY(rs_wait_read(&h, flag.p, sizeof(int), s));
   return h ? RS_E_NONFINITE : RS_OK;
 }
 

@@ -300,16 +300,14 @@ extern "C" rs_status rs_cpr_setup(rs_bsr A, rs_dcpl D, const rs_cpr_opts *o, voi
     // join: the caller's stream waits for the side stream, and the side
     // stream is drained before any buffer can go back to the pool
     if (hipEventRecord(ev, ss) != hipSuccess || hipStreamWaitEvent(s, ev, 0) != hipSuccess ||
-        hipStreamSynchronize(ss) != hipSuccess) {
+        rs_wait(ss) != RS_OK) {
       if (st == RS_OK) st = RS_E_HIP;
     }
   }
   if (ev) (void)hipEventDestroy(ev);
   if (st == RS_OK) {
     int h = 0;
-    if (hipGetLastError() != hipSuccess ||
-        hipMemcpyAsync(&h, flag.p, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess) st = RS_E_HIP;
+    if (hipGetLastError() != hipSuccess || rs_wait_read(&h, flag.p, sizeof(int), s) != RS_OK) st = RS_E_HIP;
     else if (h & RSF_NONFINITE) st = RS_E_NONFINITE;
     else if (h & RSF_SINGULAR) st = RS_E_SINGULAR;
     else st = rs_dilu_check(M, s);

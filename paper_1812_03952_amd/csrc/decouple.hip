@@ -358,9 +358,10 @@ static rs_status decouple_impl(rs_bsr_s *A, const double *vals, bool attach, int
     } else {
       launch_decouple(method, prec, n, src7{A->a7.as<double>(), n}, D, flag.as<int>(), s);
     }
-    if (hipGetLastError() != hipSuccess ||
-        hipMemcpyAsync(&h, flag.p, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess) { st = RS_E_HIP; break; }
+    if (hipGetLastError() != hipSuccess || rs_wait_read(&h, flag.p, sizeof(int), s) != RS_OK) {
+      st = RS_E_HIP;
+      break;
+    }
     if (h & RSF_NONFINITE) st = RS_E_NONFINITE;
     else if (h & RSF_SINGULAR) st = RS_E_SINGULAR;
   } while (0);

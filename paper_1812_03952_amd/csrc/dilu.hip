@@ -553,8 +553,7 @@ template rs_status rs_dilu_apply_run<float>(rs_cpr_s *, const float *, float *, 
 // wait that timed out leaves a non-zero word
 rs_status rs_dilu_check(rs_cpr_s *M, hipStream_t s) {
   int h = 0, r = 0;
-  if (M->pctl.p) RS_HIP(hipMemcpyAsync(&h, M->pctl.as<int>() + 1, sizeof(int), hipMemcpyDeviceToHost, s));
-  if (M->rctl.p) RS_HIP(hipMemcpyAsync(&r, M->rctl.as<int>() + 2, sizeof(int), hipMemcpyDeviceToHost, s));
-  if (M->pctl.p || M->rctl.p) RS_HIP(hipStreamSynchronize(s));
+  if (M->pctl.p) RS_TRY(rs_wait_read(&h, M->pctl.as<int>() + 1, sizeof(int), s));
+  if (M->rctl.p) RS_TRY(rs_wait_read(&r, M->rctl.as<int>() + 2, sizeof(int), s));
   return (h || r) ? RS_E_HIP : RS_OK;
 }

@@ -275,9 +275,8 @@ static rs_status run_axpy(int64_t N, int K, const double *V, const double *h1, c
 }
 
 static rs_status read_host(double *h, const double *d, int cnt, hipStream_t s) {
-  RS_HIP(hipMemcpyAsync(h, d, sizeof(double) * cnt, hipMemcpyDeviceToHost, s));
-  RS_HIP(hipStreamSynchronize(s));
-  return RS_OK;
+  RS_HIP(hipMemcpyAsync(h, d, sizeof(double) * cnt, hipMemcpyDeviceToHost, s));   // h is pinned
+  return rs_wait(s);
 }
 
 template <class TZ>

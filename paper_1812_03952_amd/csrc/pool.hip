@@ -14,6 +14,7 @@
 #include <map>
 #include <mutex>
 #include <unordered_map>
+#include <string.h>
 
 namespace {
 
@@ -105,4 +106,50 @@ extern "C" void rs_pool_usage(size_t *live_bytes, size_t *cached_bytes) {
   std::lock_guard<std::mutex> lk(P.mu);
   if (live_bytes) *live_bytes = P.live;
   if (cached_bytes) *cached_bytes = P.cached;
+}
+
+// ---- short host waits --------------------------------------------------------
+// The set-up reads a few counts and flags back (an aggregate count, an error
+// word) and waits for the stream at each.  A blocking stream synchronisation
+// leaves the device idle for tens of microseconds after such a read while the
+// host thread wakes up; these waits poll an event instead.  Each host thread
+// keeps one event per device and a small pinned staging buffer (never freed:
+// no HIP calls at exit).
+namespace {
+constexpr int WAIT_MAX_DEV = 64;
+constexpr size_t WAIT_STAGE = 256;
+struct host_wait {
+  hipEvent_t ev[WAIT_MAX_DEV] = {};
+  void *stage = nullptr;
+};
+thread_local host_wait tw;
+}  // namespace
+
+rs_status rs_wait(hipStream_t s) {
+  int dev = 0;
+  RS_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= WAIT_MAX_DEV) {
+    RS_HIP(hipStreamSynchronize(s));
+    return RS_OK;
+  }
+  if (!tw.ev[dev]) RS_HIP(hipEventCreateWithFlags(&tw.ev[dev], hipEventDisableTiming));
+  RS_HIP(hipEventRecord(tw.ev[dev], s));
+  for (;;) {
+    const hipError_t e = hipEventQuery(tw.ev[dev]);
+    if (e == hipSuccess) return RS_OK;
+    if (e != hipErrorNotReady) return RS_E_HIP;
+  }
+}
+
+rs_status rs_wait_read(void *h, const void *d, size_t bytes, hipStream_t s) {
+  if (bytes > WAIT_STAGE) {
+    RS_HIP(hipMemcpyAsync(h, d, bytes, hipMemcpyDeviceToHost, s));
+    RS_HIP(hipStreamSynchronize(s));
+    return RS_OK;
+  }
+  if (!tw.stage) RS_HIP(hipHostMalloc(&tw.stage, WAIT_STAGE, hipHostMallocPortable));
+  RS_HIP(hipMemcpyAsync(tw.stage, d, bytes, hipMemcpyDeviceToHost, s));
+  RS_TRY(rs_wait(s));
+  memcpy(h, tw.stage, bytes);
+  return RS_OK;
 }

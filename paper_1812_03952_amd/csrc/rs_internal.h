@@ -25,6 +25,10 @@ static inline hipStream_t rs_stream(void *s) { return (hipStream_t)s; }
 // cached and reused by later requests of a similar size.
 void *rs_pool_get(size_t bytes, size_t *got);   // nullptr when out of memory
 void rs_pool_put(void *p, size_t bytes);
+// Wait for the work queued on s (rs_wait), or copy bytes (at most 256) from
+// device memory to h and wait for them (rs_wait_read), polling an event.
+rs_status rs_wait(hipStream_t s);
+rs_status rs_wait_read(void *h, const void *d, size_t bytes, hipStream_t s);
 
 // A device allocation owned by a handle.  `bytes` is the size of the block
 // actually held (at least what was asked for).

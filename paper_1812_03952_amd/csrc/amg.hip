@@ -210,10 +210,12 @@ __device__ __forceinline__ uint64_t keyof(uint8_t st, int v, int level) {
 // predecessor left no vertex undecided (*prev == 0) has nothing to change
 // and returns at once.  prev == nullptr: the predecessor is known to have
 // left some.
+// und0 (first round of a batch only): the batch's flags, zeroed here
 __global__ void k_mis_m1(int n, int level, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
                          const uint8_t *__restrict__ strong, const uint8_t *__restrict__ state,
-                         uint64_t *__restrict__ m1, const int *__restrict__ prev) {
+                         uint64_t *__restrict__ m1, const int *__restrict__ prev, int *__restrict__ und0) {
   int u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (und0 && u < MIS_BATCH) und0[u] = 0;
   if (u >= n || (prev && *prev == 0)) return;
   const uint8_t su = state[u];
   uint64_t m = keyof(su, u, level);
@@ -229,33 +231,24 @@ __global__ void k_mis_m1(int n, int level, const int32_t *__restrict__ rp, const
   if (und) m1[u] = m;                            // as in k_mis7_m1
 }
 
-__global__ void k_mis_m2(int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
-                         const uint8_t *__restrict__ strong, const uint64_t *__restrict__ m1,
-                         uint64_t *__restrict__ m2, const int *__restrict__ prev) {
-  int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= n || (prev && *prev == 0)) return;
-  uint64_t m = m1[v];
-  for (int p = rp[v]; p < rp[v + 1]; ++p)
-    if (strong[p]) {
-      uint64_t k = m1[ci[p]];
-      m = k > m ? k : m;
-    }
-  m2[v] = m;
-}
-
-__global__ void k_mis_decide(int n, int level, const uint64_t *__restrict__ m2, uint8_t *__restrict__ state,
-                             int *__restrict__ undecided, const int *__restrict__ prev) {
+// the distance-2 maximum of an undecided vertex (the largest m1 over its
+// closed strong neighbourhood) and its decision; m1 is not written in this
+// pass, so the decisions of one round all see the same m1
+__global__ void k_mis_m2d(int n, int level, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                          const uint8_t *__restrict__ strong, const uint64_t *__restrict__ m1,
+                          uint8_t *__restrict__ state, int *__restrict__ undecided, const int *__restrict__ prev) {
   if (prev && *prev == 0) return;             // *undecided stays 0
   int v = blockIdx.x * blockDim.x + threadIdx.x;
   int left = 0;
   uint8_t st = ST_ISO;
-  uint64_t m = 0;
-  if (v < n) {
-    st = state[v];
-    m = m2[v];
-    asm volatile("" : "+v"(m));   // both loads issue before the test of st
-  }
+  if (v < n) st = state[v];
   if (st == ST_UND) {
+    uint64_t m = m1[v];
+    for (int p = rp[v]; p < rp[v + 1]; ++p)
+      if (strong[p]) {
+        uint64_t k = m1[ci[p]];
+        m = k > m ? k : m;
+      }
     if (m == ~0ull) state[v] = ST_OUT;
     else if (m == prio(v, level)) state[v] = ST_ROOT;
     else left = 1;
@@ -264,15 +257,20 @@ __global__ void k_mis_decide(int n, int level, const uint64_t *__restrict__ m2, 
   if (__syncthreads_or(left) && threadIdx.x == 0) *undecided = 1;
 }
 
-__global__ void k_root_flag(int n, const uint8_t *__restrict__ state, int32_t *__restrict__ f) {
+// (also zeroes the word *zero1: the aggregation's error flag)
+__global__ void k_root_flag(int n, const uint8_t *__restrict__ state, int32_t *__restrict__ f,
+                            int *__restrict__ zero1) {
   int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v == 0) *zero1 = 0;
   if (v < n) f[v] = state[v] == ST_ROOT ? 1 : 0;
 }
 
+// (also zeroes z[0 .. nz): the coarse level's per-row counters, nz <= n)
 __global__ void k_agg1(int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
                        const uint8_t *__restrict__ strong, const uint8_t *__restrict__ state,
-                       const int32_t *__restrict__ id, int32_t *__restrict__ agg1) {
+                       const int32_t *__restrict__ id, int32_t *__restrict__ agg1, int32_t *__restrict__ z, int nz) {
   int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < nz) z[v] = 0;
   if (v >= n) return;
   int g = -1;
   uint8_t st = state[v];
@@ -304,8 +302,11 @@ __global__ void k_agg2(int n, const int32_t *__restrict__ rp, const int32_t *__r
   agg[v] = g;
 }
 
-__global__ void k_count_members(int n, const int32_t *__restrict__ agg, int32_t *__restrict__ cnt) {
+// (also zeroes z[0 .. nz), the fill counters of k_fill_members, nz <= n)
+__global__ void k_count_members(int n, const int32_t *__restrict__ agg, int32_t *__restrict__ cnt,
+                                int32_t *__restrict__ z, int nz) {
   int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < nz) z[v] = 0;
   if (v < n && agg[v] >= 0) atomicAdd(&cnt[agg[v]], 1);
 }
 
@@ -1088,12 +1089,14 @@ __global__ void k_strength7_sym(int nx, int ny, int nz, const uint8_t *__restric
   state[c] = m ? ST_UND : ST_ISO;
 }
 
-// Distance-2 MIS round on the grid: m1 as k_mis_m1; m2 and the decision
-// (k_mis_m2 and k_mis_decide) in one kernel that reads only m1 and the cell's
-// own state, so the state is updated in place.  Decided cells skip m2.
+// Distance-2 MIS round on the grid: m1 as k_mis_m1; m2 and the decision as
+// k_mis_m2d, in one kernel that reads only m1 and the cell's own state, so the
+// state is updated in place.  Decided cells skip m2.
 __global__ void k_mis7_m1(int nx, int ny, int nz, int level, const uint8_t *__restrict__ smask,
-                          const uint8_t *__restrict__ state, uint64_t *__restrict__ m1, const int *__restrict__ prev) {
+                          const uint8_t *__restrict__ state, uint64_t *__restrict__ m1, const int *__restrict__ prev,
+                          int *__restrict__ und0) {
   const int64_t n = (int64_t)nx * ny * nz, c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (und0 && c < MIS_BATCH) und0[c] = 0;
   if (c >= n || (prev && *prev == 0)) return;
   const cell7 e = cell7_of(c, nx, ny, nz);
   const uint8_t sm = smask[c];
@@ -1151,9 +1154,11 @@ __global__ void k_mis7_m2d(int nx, int ny, int nz, int level, const uint8_t *__r
   if (__syncthreads_or(left) && threadIdx.x == 0) *undecided = 1;
 }
 
+// (z, nz as in k_agg1)
 __global__ void k_agg1_7(int nx, int ny, int nz, const uint8_t *__restrict__ smask, const uint8_t *__restrict__ state,
-                         const int32_t *__restrict__ id, int32_t *__restrict__ agg1) {
+                         const int32_t *__restrict__ id, int32_t *__restrict__ agg1, int32_t *__restrict__ z, int nzr) {
   const int64_t n = (int64_t)nx * ny * nz, c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < nzr) z[c] = 0;
   if (c >= n) return;
   const cell7 e = cell7_of(c, nx, ny, nz);
   int g = -1;
@@ -1587,11 +1592,10 @@ rs_status rs_amg_build(rs_cpr_s *M, hipStream_t s) {
     RS_HIP(hipMemsetAsync(L->agg.p, 0xff, sizeof(int32_t) * (n + 1), s));
     if (last) break;
     // strength: per CSR entry, or a 7-bit mask per cell on the fine level
-    dbuf strong, state, m1, m2, und;
+    dbuf strong, state, m1, und;
     if (!st7) RS_TRY(dir.alloc(L->nnz));
     RS_TRY(strong.alloc(st7 ? n : L->nnz)); RS_TRY(state.alloc(n));
     RS_TRY(m1.alloc(sizeof(uint64_t) * n));
-    if (!st7) RS_TRY(m2.alloc(sizeof(uint64_t) * n));
     RS_TRY(und.alloc(sizeof(int) * MIS_BATCH));
     const int32_t *rp = L->rp.as<int32_t>(), *ci = L->ci.as<int32_t>();
     if (st7) {
@@ -1606,21 +1610,19 @@ rs_status rs_amg_build(rs_cpr_s *M, hipStream_t s) {
     // of the batch left undecided vertices
     for (int round = 0;; round += MIS_BATCH) {
       if (round > n + 2) return RS_E_HIP;     // progress is guaranteed; guard anyway
-      RS_HIP(hipMemsetAsync(und.p, 0, sizeof(int) * MIS_BATCH, s));
       for (int b = 0; b < MIS_BATCH; ++b) {
         const int *prev = b ? und.as<int>() + b - 1 : nullptr;
+        int *und0 = b ? nullptr : und.as<int>();    // zeroed by the batch's first pass
         if (st7) {
           k_mis7_m1<<<rs_grid(n), RS_BLOCK, 0, s>>>(g.nx, g.ny, g.nz, l, strong.as<uint8_t>(), state.as<uint8_t>(),
-                                                    m1.as<uint64_t>(), prev);
+                                                    m1.as<uint64_t>(), prev, und0);
           k_mis7_m2d<<<rs_grid(n), RS_BLOCK, 0, s>>>(g.nx, g.ny, g.nz, l, strong.as<uint8_t>(), m1.as<uint64_t>(),
                                                      state.as<uint8_t>(), und.as<int>() + b, prev);
         } else {
           k_mis_m1<<<rs_grid(n), RS_BLOCK, 0, s>>>(n, l, rp, ci, strong.as<uint8_t>(), state.as<uint8_t>(),
-                                                   m1.as<uint64_t>(), prev);
-          k_mis_m2<<<rs_grid(n), RS_BLOCK, 0, s>>>(n, rp, ci, strong.as<uint8_t>(), m1.as<uint64_t>(),
-                                                   m2.as<uint64_t>(), prev);
-          k_mis_decide<<<rs_grid(n), RS_BLOCK, 0, s>>>(n, l, m2.as<uint64_t>(), state.as<uint8_t>(),
-                                                       und.as<int>() + b, prev);
+                                                   m1.as<uint64_t>(), prev, und0);
+          k_mis_m2d<<<rs_grid(n), RS_BLOCK, 0, s>>>(n, l, rp, ci, strong.as<uint8_t>(), m1.as<uint64_t>(),
+                                                    state.as<uint8_t>(), und.as<int>() + b, prev);
         }
       }
       RS_HIP(hipGetLastError());
@@ -1631,7 +1633,7 @@ rs_status rs_amg_build(rs_cpr_s *M, hipStream_t s) {
     // aggregates
     dbuf id, agg1;
     RS_TRY(id.alloc(sizeof(int32_t) * n)); RS_TRY(agg1.alloc(sizeof(int32_t) * n));
-    k_root_flag<<<rs_grid(n), RS_BLOCK, 0, s>>>(n, state.as<uint8_t>(), id.as<int32_t>());
+    k_root_flag<<<rs_grid(n), RS_BLOCK, 0, s>>>(n, state.as<uint8_t>(), id.as<int32_t>(), flag.as<int>());
     RS_HIP(hipGetLastError());
     int64_t nc64 = 0;
     RS_TRY(scan_i32(id.as<int32_t>(), id.as<int32_t>(), n, &nc64, s, nullptr));
@@ -1640,20 +1642,22 @@ rs_status rs_amg_build(rs_cpr_s *M, hipStream_t s) {
       if (st7) RS_TRY(level0_as_coarsest(M, s));
       break;
     }
-    RS_HIP(hipMemsetAsync(flag.p, 0, sizeof(int), s));
+    // per coarse row counters (nc + 1 <= n), zeroed by the first aggregation pass
+    dbuf off, skey, sval, cnt;
+    RS_TRY(cnt.alloc(sizeof(int32_t) * ((size_t)nc + 1)));
     if (st7) {
       k_agg1_7<<<rs_grid(n), RS_BLOCK, 0, s>>>(g.nx, g.ny, g.nz, strong.as<uint8_t>(), state.as<uint8_t>(),
-                                               id.as<int32_t>(), agg1.as<int32_t>());
+                                               id.as<int32_t>(), agg1.as<int32_t>(), cnt.as<int32_t>(), nc + 1);
       k_agg2_7<<<rs_grid(n), RS_BLOCK, 0, s>>>(g.nx, g.ny, g.nz, strong.as<uint8_t>(), ap7, state.as<uint8_t>(),
                                                agg1.as<int32_t>(), L->agg.as<int32_t>(), flag.as<int>());
     } else {
-      k_agg1<<<rs_grid(n), RS_BLOCK, 0, s>>>(n, rp, ci, strong.as<uint8_t>(), state.as<uint8_t>(), id.as<int32_t>(), agg1.as<int32_t>());
+      k_agg1<<<rs_grid(n), RS_BLOCK, 0, s>>>(n, rp, ci, strong.as<uint8_t>(), state.as<uint8_t>(), id.as<int32_t>(),
+                                             agg1.as<int32_t>(), cnt.as<int32_t>(), nc + 1);
       k_agg2<<<rs_grid(n), RS_BLOCK, 0, s>>>(n, rp, ci, strong.as<uint8_t>(), L->a.as<double>(), state.as<uint8_t>(),
                                              agg1.as<int32_t>(), L->agg.as<int32_t>(), flag.as<int>());
     }
     RS_HIP(hipGetLastError());
     L->nc = nc;
-    dbuf off, skey, sval, cnt;
     // temporaries of the smoothed product, kept until the host read at the
     // end of the level (the RAS set-up allocates on a side stream meanwhile)
     dbuf rho, apoff, apcnt, apci, apv, tfill, trv, ident;
@@ -1689,9 +1693,7 @@ rs_status rs_amg_build(rs_cpr_s *M, hipStream_t s) {
       RS_HIP(hipGetLastError());
       // P^T: fine rows of each coarse column, ascending
       RS_TRY(L->tptr.alloc(sizeof(int32_t) * ((size_t)nc + 1)));
-      RS_TRY(cnt.alloc(sizeof(int32_t) * ((size_t)nc + 1)));
       RS_TRY(tfill.alloc(sizeof(int32_t) * ((size_t)nc + 1)));
-      RS_HIP(hipMemsetAsync(cnt.p, 0, sizeof(int32_t) * (nc + 1), s));
       RS_HIP(hipMemsetAsync(tfill.p, 0, sizeof(int32_t) * (nc + 1), s));
       k_sa_tcount<<<rs_grid(n), RS_BLOCK, 0, s>>>(n, crp, L->pcnt.as<int32_t>(), L->pci.as<int32_t>(), cnt.as<int32_t>());
       RS_HIP(hipGetLastError());
@@ -1737,15 +1739,15 @@ rs_status rs_amg_build(rs_cpr_s *M, hipStream_t s) {
     } else {
       // members of each aggregate, ascending
       RS_TRY(L->mptr.alloc(sizeof(int32_t) * (nc + 1)));
-      RS_TRY(cnt.alloc(sizeof(int32_t) * (nc + 1)));
-      RS_HIP(hipMemsetAsync(cnt.p, 0, sizeof(int32_t) * (nc + 1), s));
-      k_count_members<<<rs_grid(n), RS_BLOCK, 0, s>>>(n, L->agg.as<int32_t>(), cnt.as<int32_t>());
+      RS_TRY(tfill.alloc(sizeof(int32_t) * ((size_t)nc + 1)));
+      k_count_members<<<rs_grid(n), RS_BLOCK, 0, s>>>(n, L->agg.as<int32_t>(), cnt.as<int32_t>(), tfill.as<int32_t>(),
+                                                      nc + 1);
       RS_HIP(hipGetLastError());
       // members: at most n (no host read of the exact count)
       RS_TRY(scan_i32(cnt.as<int32_t>(), L->mptr.as<int32_t>(), nc + 1, nullptr, s, nullptr));
       RS_TRY(L->mem.alloc(sizeof(int32_t) * ((size_t)n + 1)));
-      RS_HIP(hipMemsetAsync(cnt.p, 0, sizeof(int32_t) * (nc + 1), s));
-      k_fill_members<<<rs_grid(n), RS_BLOCK, 0, s>>>(n, L->agg.as<int32_t>(), L->mptr.as<int32_t>(), cnt.as<int32_t>(), L->mem.as<int32_t>());
+      k_fill_members<<<rs_grid(n), RS_BLOCK, 0, s>>>(n, L->agg.as<int32_t>(), L->mptr.as<int32_t>(), tfill.as<int32_t>(),
+                                                     L->mem.as<int32_t>());
       k_sort_members<<<rs_grid(nc), RS_BLOCK, 0, s>>>(nc, L->mptr.as<int32_t>(), L->mem.as<int32_t>());
       RS_HIP(hipGetLastError());
       // Galerkin product

@@ -816,117 +816,36 @@ __global__ __launch_bounds__(320) void k_ras_bwd1(int nx, int ny, int nz, int S,
   }
 }
 
-// ---- sweeps with loader waves (FP32, strips of at most 128 lines) ----------
-// The strips, tickets and boundary words of the sweeps above, with the waves
-// given one kind of memory traffic each:
-//   - compute waves (one lane per line) issue no global memory instruction:
-//     a level's operands come from an LDS slot, its result goes to the LDS
-//     ring;
-//   - two loader waves copy the operands of a level (rh, or y and x_p, and
-//     two scaled blocks per cell; a level's cells are contiguous in
-//     wavefront order, so these are a few contiguous runs) into its slot
-//     with global_load_lds, RAS_LA levels ahead; the waves take alternate
-//     levels, so that each keeps at most three levels of copies in flight and
-//     waits for its oldest one alone;
-//   - the writer wave only stores (outputs and published boundary words);
-//   - a poller wave only loads the neighbour strip's boundary words, so no
-//     wait for a load ever waits for a store.
-// A level then costs the LDS reads, the 4x4 products and one barrier; what
-// remains is each CU's memory throughput over the levels' bytes.
-// Slots: 1 KB pieces for strips of up to 16 NB lines, NR per vector of 16
-// bytes per cell, NB per block array (x_p: NR quarter pieces).
-constexpr int RAS_LA = 6, RAS_SLOTS = RAS_LA + 1;
-constexpr int ras2_nr(int nb) { return (nb + 3) / 4; }
-constexpr int ras_fwd2_slot(int nb) { return (ras2_nr(nb) + 2 * nb) * 1024; }
-constexpr int ras_bwd2_slot(int nb) { return (ras2_nr(nb) + 2 * nb) * 1024 + ras2_nr(nb) * 256; }
-
-typedef __attribute__((address_space(3))) void ras_lds_t;
-typedef __attribute__((address_space(1))) void ras_glb_t;
-
-// wait until at most N of this wave's vector memory instructions are in flight
-template <int N> __device__ __forceinline__ void ras_wait_vm() {
-  static_assert(N >= 0 && N < 64, "vmcnt holds 6 bits");
-  __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
-}
-// lane l copies 16 (or 4) bytes from src to dst + 16 l (4 l); dst is the
-// same for the whole wave
-__device__ __forceinline__ void ras_copy16(const float *src, unsigned char *dst) {
-  __builtin_amdgcn_global_load_lds((ras_glb_t *)src, (ras_lds_t *)dst, 16, 0, 0);
-}
-__device__ __forceinline__ void ras_copy4(const float *src, unsigned char *dst) {
-  __builtin_amdgcn_global_load_lds((ras_glb_t *)src, (ras_lds_t *)dst, 4, 0, 0);
-}
-
-// the cells of level lam of a strip [j0, j1): lines jlo .. jlo+cnt-1, from
-// wavefront position p0; a level outside the layer gives cnt = 0 and an
-// in-bounds p0
-struct ras_lvl { int jlo, cnt; int64_t p0; };
-__device__ __forceinline__ ras_lvl ras_level(int64_t cl, int lam, int j0, int j1, int nx, int ny) {
-  const int lc = min(max(lam, 0), nx + ny - 2);
-  ras_lvl v;
-  v.jlo = min(max(j0, lc - nx + 1), lc);
-  const int jhi = min(j1 - 1, lc);
-  v.cnt = lam == lc ? max(jhi - v.jlo + 1, 0) : 0;
-  v.p0 = cl + wf_off(lc, nx, ny) + (v.jlo - wf_jlo(lc, nx));
-  return v;
-}
-
-// slot of a forward level: rh [NR KB], Lh_y [NB KB], Lh_x [NB KB]; cell e of
-// the level at e*16 and NR KB + e*64 (+ NB KB)
-template <int NB>
-__global__ __launch_bounds__(384) void k_ras_fwd2(int nx, int ny, int nz, int S, int H, int64_t n, int LW,
-                                                  const float *__restrict__ blk, const float *__restrict__ rh,
-                                                  float *__restrict__ y, int *__restrict__ ctl,
-                                                  uint64_t *__restrict__ xw, uint32_t tag) {
-  constexpr int NR = ras2_nr(NB), NI = NR + 2 * NB, SLOT = ras_fwd2_slot(NB);
-  constexpr int WAITN = (RAS_LA / 2 - 1) * NI;
+// ---- sweeps with a quad of lanes per cell on strips (FP32) ------------------
+// The strips, tickets and boundary words of the sweeps above, with the
+// compute of the one-workgroup-per-layer sweeps: lane r of a cell's quad owns
+// block row r and keeps its rows of the next P levels in flight in registers
+// (three loads per level: its rh or y entry and its rows of the two scaled
+// blocks, plus x_p backward), so a level's loads are spread over four times
+// as many lanes as with one lane per line.  The waves each have one kind of
+// memory traffic: compute waves only load; the writer wave only stores
+// (outputs and published boundary words); a poller wave only loads the
+// neighbour strip's words, so no wait for a load ever waits for a store.
+// Strips of up to 224 lines (one pass).
+template <int P>
+__global__ __launch_bounds__(1024) void k_ras_fwd3(int nx, int ny, int nz, int S, int H, int64_t n, int LWq,
+                                                   const float *__restrict__ blk, const float *__restrict__ rh,
+                                                   float *__restrict__ y, int *__restrict__ ctl,
+                                                   uint64_t *__restrict__ xw, uint32_t tag) {
   extern __shared__ __align__(16) unsigned char smem[];
-  unsigned char *data = smem;                           // [RAS_SLOTS][SLOT]
-  float *ring = (float *)(smem + RAS_SLOTS * SLOT);     // [2][H+2][4]
+  float *ring = (float *)smem;                          // [2][H+2][4]
   __shared__ int s_t;
   __shared__ float gh[32][4];                           // ghost line j0-1, by level mod 32
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, NC = 4 * LWq;
   if (tid == 0) s_t = atomicAdd(&ctl[0], 1);
   __syncthreads();
   const int s = s_t / nz, k = s_t - (s_t / nz) * nz;
   const int j0 = s * H, j1 = min(ny, j0 + H), RS = H + 2;
   const int64_t nxy = (int64_t)nx * ny, cl = nxy * k;
-  const int Lw = nx + (j1 - j0) - 1;
-  const float *By = blk, *Bx = blk + n * 16;
-  if (tid >= LW + 128) {
-    // loader wave w (0 or 1) copies the levels m with m % 2 == w
-    const int w = (tid - LW - 128) >> 6, lane = tid & 63;
-    auto issue = [&](int m) {
-      const ras_lvl v = ras_level(cl, j0 + m, j0, j1, nx, ny);
-      const int cmax = max(v.cnt, 1) - 1;
-      unsigned char *sl = data + (m % RAS_SLOTS) * SLOT;
-#pragma unroll
-      for (int q = 0; q < NR; ++q) ras_copy16(rh + 4 * (v.p0 + min(q * 64 + lane, cmax)), sl + q * 1024);
-#pragma unroll
-      for (int q = 0; q < NB; ++q) {
-        const int64_t e = v.p0 + min(q * 16 + (lane >> 2), cmax);
-        ras_copy16(By + 16 * e + 4 * (lane & 3), sl + (NR + q) * 1024);
-        ras_copy16(Bx + 16 * e + 4 * (lane & 3), sl + (NR + NB + q) * 1024);
-      }
-    };
-    // the barriers without a fence: a fence would wait for every copy in
-    // flight; each level's copies are waited for explicitly instead
-    for (int m = w; m < RAS_LA; m += 2) issue(m);
-    if (w == 0) ras_wait_vm<WAITN>();                  // level 0 has landed
-    __builtin_amdgcn_s_barrier();
-    for (int m = 0; m < Lw; ++m) {
-      if ((m & 1) == w) issue(m + RAS_LA);
-      else ras_wait_vm<WAITN>();                       // level m+1 has landed
-      __builtin_amdgcn_s_barrier();
-    }
-    ras_wait_vm<0>();                                   // no copy outlives the workgroup
-    return;
-  }
-  if (tid >= LW + 64) {
-    // poller wave: the ghost line j0-1 for local level m (cell i = m) goes
-    // to gh[m % 32], loaded 16 levels at a time as in k_ras_fwd1; this wave
-    // issues no store, so waiting for a load never waits for stores
-    const int w = tid - LW - 64;
+  const int Lw = nx + (j1 - j0) - 1, Lpad = (Lw + P - 1) / P * P;
+  if (tid >= NC + 64) {
+    // poller wave
+    const int w = tid - NC - 64;
     bool failed = false;
     auto issue16 = [&](int m16, uint64_t &slot) {
       const int m = m16 + (w >> 2), r = w & 3;
@@ -945,16 +864,16 @@ __global__ __launch_bounds__(384) void k_ras_fwd2(int nx, int ny, int nz, int S,
     issue16(0, pend);
     finish16(0, pend);
     __syncthreads();
-    for (int m = 0; m < Lw; ++m) {
+    for (int m = 0; m < Lpad; ++m) {
       if ((m & 15) == 8) issue16(m + 8, pend);
       if ((m & 15) == 15) finish16(m + 1, pend);
       __syncthreads();
     }
     return;
   }
-  if (tid >= LW) {
+  if (tid >= NC) {
     // writer wave: stores only
-    const int w = tid - LW, nw = 64;
+    const int w = tid - NC, nw = 64;
     auto publish = [&](int m) {
       if (s == S - 1 || w >= 4 || m < 0) return;
       const int i = m + j0 - (j1 - 1);
@@ -962,112 +881,71 @@ __global__ __launch_bounds__(384) void k_ras_fwd2(int nx, int ny, int nz, int S,
       ras_put(xw + ras_xword(k, s, S, nx, i) + w, ring[(m & 1) * RS * 4 + (j1 - j0) * 4 + w], tag);
     };
     __syncthreads();
-    for (int m = 0; m < Lw; ++m) {
+    for (int m = 0; m < Lpad; ++m) {
       ras_write_strip<true>(j0 + m - 1, nx, ny, j0, j1, cl, ring + ((m + 1) & 1) * RS * 4, y, w, nw);
       publish(m - 1);
       __syncthreads();
     }
-    ras_write_strip<true>(j0 + Lw - 1, nx, ny, j0, j1, cl, ring + ((Lw + 1) & 1) * RS * 4, y, w, nw);
-    publish(Lw - 1);
+    ras_write_strip<true>(j0 + Lpad - 1, nx, ny, j0, j1, cl, ring + ((Lpad + 1) & 1) * RS * 4, y, w, nw);
+    publish(Lpad - 1);
     return;
   }
   __syncthreads();
-  const int j = j0 + tid, sl = min(j, j1 - 1) - j0 + 1;  // slot of line j in the ring
-  for (int m = 0; m < Lw; ++m) {
-    const int lam = j0 + m, i = lam - j;
-    const ras_lvl v = ras_level(cl, lam, j0, j1, nx, ny);
-    const bool act = j < j1 && i >= 0 && i < nx;
-    const int e = min(max(j - v.jlo, 0), H - 1);
-    const unsigned char *d = data + (m % RAS_SLOTS) * SLOT;
-    float *cur = ring + (m & 1) * RS * 4;
-    const float *prv = ring + ((m + 1) & 1) * RS * 4;
-    float r[4], a1[16], a2[16], yy[4], yx[4], o[4];
-    ld4v(sl == 1 ? &gh[m & 31][0] : prv + 4 * (sl - 1), yy);   // line j0-1: the ghost
-    ld4v(prv + 4 * sl, yx);
-    ld4v((const float *)(d + e * 16), r);
+  const int row = tid & 3, j = j0 + (tid >> 2);
+  const int sl = min(j, j1 - 1) - j0 + 1;               // slot of line j in the ring
+  const float *By = blk, *Bx = blk + n * 16;
+  ras_fpre<float> R[P];
+  auto load = [&](int m, ras_fpre<float> &p, float tok) {
+    int jj = j;
+    order_after(jj, tok);
+    const int64_t c = wf_clamped(cl, j0 + m, jj, nx, ny);
+    p.r = rh[4 * c + row];
+    ld4v(By + c * 16 + 4 * row, p.a1);
+    ld4v(Bx + c * 16 + 4 * row, p.a2);
+  };
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      float t4[4];
-      ld4v((const float *)(d + NR * 1024 + e * 64 + 16 * q), t4);
+  for (int d = 0; d < P; ++d) load(d, R[d], 0.f);
+  for (int m0 = 0; m0 < Lpad; m0 += P) {
 #pragma unroll
-      for (int c = 0; c < 4; ++c) a1[4 * q + c] = t4[c];
-      ld4v((const float *)(d + (NR + NB) * 1024 + e * 64 + 16 * q), t4);
-#pragma unroll
-      for (int c = 0; c < 4; ++c) a2[4 * q + c] = t4[c];
+    for (int d = 0; d < P; ++d) {
+      const int m = m0 + d, i = j0 + m - j;
+      const bool act = j < j1 && i >= 0 && i < nx;
+      float *cur = ring + (m & 1) * RS * 4;
+      const float *prv = ring + ((m + 1) & 1) * RS * 4;
+      float yy[4], yx[4];
+      ld4v(sl == 1 ? &gh[m & 31][0] : prv + 4 * (sl - 1), yy);   // line j0-1: the ghost
+      ld4v(prv + 4 * sl, yx);
+      const float ty = dot4(R[d].a1, yy), tx = dot4(R[d].a2, yx);
+      float v = R[d].r;
+      v = (act && j > 0) ? v - ty : v;
+      v = (act && i > 0) ? v - tx : v;
+      if (act) cur[4 * sl + row] = v;
+      load(m + P, R[d], v);
+      __syncthreads();
     }
-#pragma unroll
-    for (int rr = 0; rr < 4; ++rr) {
-      float a1r[4] = {a1[4 * rr], a1[4 * rr + 1], a1[4 * rr + 2], a1[4 * rr + 3]};
-      float a2r[4] = {a2[4 * rr], a2[4 * rr + 1], a2[4 * rr + 2], a2[4 * rr + 3]};
-      const float ty = dot4(a1r, yy), tx = dot4(a2r, yx);
-      float vr = r[rr];
-      vr = (act && j > 0) ? vr - ty : vr;
-      vr = (act && i > 0) ? vr - tx : vr;
-      o[rr] = vr;
-    }
-    if (act) *(float4 *)(cur + 4 * sl) = make_float4(o[0], o[1], o[2], o[3]);
-    __syncthreads();
   }
 }
 
-// slot of a backward level: y [NR KB], Uh_x [NB KB], Uh_y [NB KB], x_p [NR
-// quarter KB]
-template <int NB>
-__global__ __launch_bounds__(384) void k_ras_bwd2(int nx, int ny, int nz, int S, int H, int64_t n, int LW,
-                                                  const float *__restrict__ blk, const float *__restrict__ y,
-                                                  const float *__restrict__ xpw, float *__restrict__ out,
-                                                  int *__restrict__ ctl, uint64_t *__restrict__ xw, uint32_t tag) {
-  constexpr int NR = ras2_nr(NB), NI = 2 * NR + 2 * NB, SLOT = ras_bwd2_slot(NB);
-  constexpr int WAITN = (RAS_LA / 2 - 1) * NI;
+template <int P>
+__global__ __launch_bounds__(1024) void k_ras_bwd3(int nx, int ny, int nz, int S, int H, int64_t n, int LWq,
+                                                   const float *__restrict__ blk, const float *__restrict__ y,
+                                                   const float *__restrict__ xpw, float *__restrict__ out,
+                                                   int *__restrict__ ctl, uint64_t *__restrict__ xw, uint32_t tag) {
   extern __shared__ __align__(16) unsigned char smem[];
-  unsigned char *data = smem;                           // [RAS_SLOTS][SLOT]
-  float *ring = (float *)(smem + RAS_SLOTS * SLOT);     // [2][H+2][4]: z
+  float *ring = (float *)smem;                          // [2][H+2][4]: z
   __shared__ int s_t;
   __shared__ float gh[32][4];                           // ghost line j1, by step mod 32
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, NC = 4 * LWq;
   if (tid == 0) s_t = atomicAdd(&ctl[1], 1);
   __syncthreads();
   const int st = s_t / nz, k = s_t - st * nz, s = S - 1 - st;   // last strip first
   const int j0 = s * H, j1 = min(ny, j0 + H), RS = H + 2, nl = j1 - j0;
   float *oring = ring + 2 * RS * 4;                     // [2][H+2][4]: output
   const int64_t nxy = (int64_t)nx * ny, cl = nxy * k;
-  const int Lw = nx + nl - 1;
+  const int Lw = nx + nl - 1, Lpad = (Lw + P - 1) / P * P;
   const int ltop = j1 - 1 + nx - 1;                     // step m handles level ltop - m
-  const float *Bx = blk + 2 * n * 16, *By = blk + 3 * n * 16;
-  if (tid >= LW + 128) {
-    const int w = (tid - LW - 128) >> 6, lane = tid & 63;
-    auto issue = [&](int m) {
-      const ras_lvl v = ras_level(cl, ltop - m, j0, j1, nx, ny);
-      const int cmax = max(v.cnt, 1) - 1;
-      unsigned char *sl = data + (m % RAS_SLOTS) * SLOT;
-#pragma unroll
-      for (int q = 0; q < NR; ++q) {
-        const int64_t e = v.p0 + min(q * 64 + lane, cmax);
-        ras_copy16(y + 4 * e, sl + q * 1024);
-        ras_copy4(xpw + e, sl + (NR + 2 * NB) * 1024 + q * 256);
-      }
-#pragma unroll
-      for (int q = 0; q < NB; ++q) {
-        const int64_t e = v.p0 + min(q * 16 + (lane >> 2), cmax);
-        ras_copy16(Bx + 16 * e + 4 * (lane & 3), sl + (NR + q) * 1024);
-        ras_copy16(By + 16 * e + 4 * (lane & 3), sl + (NR + NB + q) * 1024);
-      }
-    };
-    for (int m = w; m < RAS_LA; m += 2) issue(m);
-    if (w == 0) ras_wait_vm<WAITN>();
-    __builtin_amdgcn_s_barrier();
-    for (int m = 0; m < Lw; ++m) {
-      if ((m & 1) == w) issue(m + RAS_LA);
-      else ras_wait_vm<WAITN>();
-      __builtin_amdgcn_s_barrier();
-    }
-    ras_wait_vm<0>();
-    return;
-  }
-  if (tid >= LW + 64) {
-    // poller wave: the ghost line j1 for step m (cell i = ltop - m - (j1-1))
-    // goes to gh[m % 32], loaded 16 steps at a time
-    const int w = tid - LW - 64;
+  if (tid >= NC + 64) {
+    const int w = tid - NC - 64;
     bool failed = false;
     auto issue16 = [&](int m16, uint64_t &slot) {
       const int m = m16 + (w >> 2), r = w & 3;
@@ -1088,16 +966,15 @@ __global__ __launch_bounds__(384) void k_ras_bwd2(int nx, int ny, int nz, int S,
     issue16(0, pend);
     finish16(0, pend);
     __syncthreads();
-    for (int m = 0; m < Lw; ++m) {
+    for (int m = 0; m < Lpad; ++m) {
       if ((m & 15) == 8) issue16(m + 8, pend);
       if ((m & 15) == 15) finish16(m + 1, pend);
       __syncthreads();
     }
     return;
   }
-  if (tid >= LW) {
-    // writer wave: stores only
-    const int w = tid - LW, nw = 64;
+  if (tid >= NC) {
+    const int w = tid - NC, nw = 64;
     auto publish = [&](int m) {
       if (s == 0 || w >= 4 || m < 0) return;
       const int i = ltop - m - j0;
@@ -1105,54 +982,51 @@ __global__ __launch_bounds__(384) void k_ras_bwd2(int nx, int ny, int nz, int S,
       ras_put(xw + ras_xword(k, s, S, nx, i) + w, ring[(m & 1) * RS * 4 + 4 + w], tag);
     };
     __syncthreads();
-    for (int m = 0; m < Lw; ++m) {
+    for (int m = 0; m < Lpad; ++m) {
       if (m >= 1) ras_write_strip<false>(ltop - m + 1, nx, ny, j0, j1, cl, oring + ((m + 1) & 1) * RS * 4, out, w, nw);
       publish(m - 1);
       __syncthreads();
     }
-    ras_write_strip<false>(ltop - Lw + 1, nx, ny, j0, j1, cl, oring + ((Lw + 1) & 1) * RS * 4, out, w, nw);
-    publish(Lw - 1);
+    ras_write_strip<false>(ltop - Lpad + 1, nx, ny, j0, j1, cl, oring + ((Lpad + 1) & 1) * RS * 4, out, w, nw);
+    publish(Lpad - 1);
     return;
   }
   __syncthreads();
-  const int j = j0 + tid, sl = min(j, j1 - 1) - j0 + 1;
-  for (int m = 0; m < Lw; ++m) {
-    const int lam = ltop - m, i = lam - j;
-    const ras_lvl v = ras_level(cl, lam, j0, j1, nx, ny);
-    const bool act = j < j1 && i >= 0 && i < nx;
-    const int e = min(max(j - v.jlo, 0), H - 1);
-    const unsigned char *d = data + (m % RAS_SLOTS) * SLOT;
-    const int cb = (m & 1) * RS * 4, pb = ((m + 1) & 1) * RS * 4;
-    float yc[4], a4[16], a5[16], zx[4], zy[4], z[4];
-    ld4v(ring + pb + 4 * sl, zx);
-    ld4v(sl == nl ? &gh[m & 31][0] : ring + pb + 4 * (sl + 1), zy);   // line j1: the ghost
-    ld4v((const float *)(d + e * 16), yc);
-    const float xpc = *(const float *)(d + (NR + 2 * NB) * 1024 + e * 4);
+  const int row = tid & 3, j = j0 + (tid >> 2);
+  const int sl = min(j, j1 - 1) - j0 + 1;
+  const float *Bx = blk + 2 * n * 16, *By = blk + 3 * n * 16;
+  ras_bpre<float> R[P];
+  auto load = [&](int m, ras_bpre<float> &p, float tok) {
+    int jj = j;
+    order_after(jj, tok);
+    const int64_t c = wf_clamped(cl, ltop - m, jj, nx, ny);
+    p.yc = y[4 * c + row];
+    p.xpc = xpw[c];
+    ld4v(Bx + c * 16 + 4 * row, p.a4);
+    ld4v(By + c * 16 + 4 * row, p.a5);
+  };
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      float t4[4];
-      ld4v((const float *)(d + NR * 1024 + e * 64 + 16 * q), t4);
+  for (int d = 0; d < P; ++d) load(d, R[d], 0.f);
+  for (int m0 = 0; m0 < Lpad; m0 += P) {
 #pragma unroll
-      for (int c = 0; c < 4; ++c) a4[4 * q + c] = t4[c];
-      ld4v((const float *)(d + (NR + NB) * 1024 + e * 64 + 16 * q), t4);
-#pragma unroll
-      for (int c = 0; c < 4; ++c) a5[4 * q + c] = t4[c];
+    for (int d = 0; d < P; ++d) {
+      const int m = m0 + d, i = ltop - m - j;
+      const bool act = j < j1 && i >= 0 && i < nx;
+      const int cb = (m & 1) * RS * 4, pb = ((m + 1) & 1) * RS * 4;
+      float zx[4], zy[4];
+      ld4v(ring + pb + 4 * sl, zx);
+      ld4v(sl == nl ? &gh[m & 31][0] : ring + pb + 4 * (sl + 1), zy);   // line j1: the ghost
+      const float tx = dot4(R[d].a4, zx), ty = dot4(R[d].a5, zy);
+      float zc = R[d].yc;
+      zc = (act && i < nx - 1) ? zc - tx : zc;
+      zc = (act && j < ny - 1) ? zc - ty : zc;
+      if (act) {
+        ring[cb + 4 * sl + row] = zc;
+        oring[cb + 4 * sl + row] = row == 0 ? zc + R[d].xpc : zc;
+      }
+      load(m + P, R[d], zc);
+      __syncthreads();
     }
-#pragma unroll
-    for (int rr = 0; rr < 4; ++rr) {
-      float a4r[4] = {a4[4 * rr], a4[4 * rr + 1], a4[4 * rr + 2], a4[4 * rr + 3]};
-      float a5r[4] = {a5[4 * rr], a5[4 * rr + 1], a5[4 * rr + 2], a5[4 * rr + 3]};
-      const float tx = dot4(a4r, zx), ty = dot4(a5r, zy);
-      float zr = yc[rr];
-      zr = (act && i < nx - 1) ? zr - tx : zr;
-      zr = (act && j < ny - 1) ? zr - ty : zr;
-      z[rr] = zr;
-    }
-    if (act) {
-      *(float4 *)(ring + cb + 4 * sl) = make_float4(z[0], z[1], z[2], z[3]);
-      *(float4 *)(oring + cb + 4 * sl) = make_float4(z[0] + xpc, z[1], z[2], z[3]);
-    }
-    __syncthreads();
   }
 }
 
@@ -1410,43 +1284,36 @@ rs_status rs_ras_apply_run(rs_cpr_s *M, const T *xp, T *out, hipStream_t s) {
     int *ctl = M->rctl.as<int>();
     uint64_t *xw = M->rxw.as<uint64_t>();
     const unsigned nwg = (unsigned)(g.nz * S);
-    // strips of at most 128 lines: operands copied to LDS by loader waves
-    const int nb = (H + 15) / 16, lw2 = (H + 63) / 64 * 64, nt2 = lw2 + 256;
-    if (H <= 128) {
-      const size_t rb2 = sizeof(float) * 8 * (size_t)(H + 2);
+    // strips of at most 224 lines: a quad of lanes per cell (one pass)
+    const int lwq = (H + 15) / 16 * 16, ntq = 4 * lwq + 128;
+    if (H <= 224) {
+      const size_t rb3 = sizeof(float) * 8 * (size_t)(H + 2);
       fwd = [=](const T *blk, const T *r, T *yo) {
         if (ov1) k_ras_reset<<<1, 64, 0, s>>>(ctl);
         const uint32_t tag = ++M->repoch;
-        switch (nb) {
-#define RS_F2(NB) case NB: k_ras_fwd2<NB><<<nwg, nt2, RAS_SLOTS * ras_fwd2_slot(NB) + rb2, s>>>(g.nx, g.ny, g.nz, S, H, g.n, lw2, blk, r, yo, ctl, xw, tag); break;
-          RS_F2(1) RS_F2(2) RS_F2(3) RS_F2(4) RS_F2(5) RS_F2(6) RS_F2(7) RS_F2(8)
-#undef RS_F2
-        }
+        k_ras_fwd3<4><<<nwg, ntq, rb3, s>>>(g.nx, g.ny, g.nz, S, H, g.n, lwq, blk, r, yo, ctl, xw, tag);
       };
       bwd = [=](const T *blk, const T *yi, const T *xw_p, T *o) {
         if (ov1) k_ras_reset<<<1, 64, 0, s>>>(ctl);
         const uint32_t tag = ++M->repoch;
-        switch (nb) {
-#define RS_B2(NB) case NB: k_ras_bwd2<NB><<<nwg, nt2, RAS_SLOTS * ras_bwd2_slot(NB) + 2 * rb2, s>>>(g.nx, g.ny, g.nz, S, H, g.n, lw2, blk, yi, xw_p, o, ctl, xw, tag); break;
-          RS_B2(1) RS_B2(2) RS_B2(3) RS_B2(4) RS_B2(5) RS_B2(6) RS_B2(7) RS_B2(8)
-#undef RS_B2
-        }
+        k_ras_bwd3<4><<<nwg, ntq, 2 * rb3, s>>>(g.nx, g.ny, g.nz, S, H, g.n, lwq, blk, yi, xw_p, o, ctl, xw, tag);
       };
     } else {
-    fwd = [=](const T *blk, const T *r, T *yo) {
-      if (ov1) k_ras_reset<<<1, 64, 0, s>>>(ctl);
-      const uint32_t tag = ++M->repoch;
-      if (u1 == 1) k_ras_fwd1<1, 5><<<nwg, nt1, rb, s>>>(g.nx, g.ny, g.nz, S, H, g.n, lw1, blk, r, yo, ctl, xw, tag);
-      else if (u1 == 2) k_ras_fwd1<2, 3><<<nwg, nt1, rb, s>>>(g.nx, g.ny, g.nz, S, H, g.n, lw1, blk, r, yo, ctl, xw, tag);
-      else k_ras_fwd1<4, 2><<<nwg, nt1, rb, s>>>(g.nx, g.ny, g.nz, S, H, g.n, lw1, blk, r, yo, ctl, xw, tag);
-    };
-    bwd = [=](const T *blk, const T *yi, const T *xw_p, T *o) {
-      if (ov1) k_ras_reset<<<1, 64, 0, s>>>(ctl);
-      const uint32_t tag = ++M->repoch;
-      if (u1 == 1) k_ras_bwd1<1, 5><<<nwg, nt1, 2 * rb, s>>>(g.nx, g.ny, g.nz, S, H, g.n, lw1, blk, yi, xw_p, o, ctl, xw, tag);
-      else if (u1 == 2) k_ras_bwd1<2, 3><<<nwg, nt1, 2 * rb, s>>>(g.nx, g.ny, g.nz, S, H, g.n, lw1, blk, yi, xw_p, o, ctl, xw, tag);
-      else k_ras_bwd1<4, 2><<<nwg, nt1, 2 * rb, s>>>(g.nx, g.ny, g.nz, S, H, g.n, lw1, blk, yi, xw_p, o, ctl, xw, tag);
-    };
+      // taller strips: one lane per line, U passes
+      fwd = [=](const T *blk, const T *r, T *yo) {
+        if (ov1) k_ras_reset<<<1, 64, 0, s>>>(ctl);
+        const uint32_t tag = ++M->repoch;
+        if (u1 == 1) k_ras_fwd1<1, 5><<<nwg, nt1, rb, s>>>(g.nx, g.ny, g.nz, S, H, g.n, lw1, blk, r, yo, ctl, xw, tag);
+        else if (u1 == 2) k_ras_fwd1<2, 3><<<nwg, nt1, rb, s>>>(g.nx, g.ny, g.nz, S, H, g.n, lw1, blk, r, yo, ctl, xw, tag);
+        else k_ras_fwd1<4, 2><<<nwg, nt1, rb, s>>>(g.nx, g.ny, g.nz, S, H, g.n, lw1, blk, r, yo, ctl, xw, tag);
+      };
+      bwd = [=](const T *blk, const T *yi, const T *xw_p, T *o) {
+        if (ov1) k_ras_reset<<<1, 64, 0, s>>>(ctl);
+        const uint32_t tag = ++M->repoch;
+        if (u1 == 1) k_ras_bwd1<1, 5><<<nwg, nt1, 2 * rb, s>>>(g.nx, g.ny, g.nz, S, H, g.n, lw1, blk, yi, xw_p, o, ctl, xw, tag);
+        else if (u1 == 2) k_ras_bwd1<2, 3><<<nwg, nt1, 2 * rb, s>>>(g.nx, g.ny, g.nz, S, H, g.n, lw1, blk, yi, xw_p, o, ctl, xw, tag);
+        else k_ras_bwd1<4, 2><<<nwg, nt1, 2 * rb, s>>>(g.nx, g.ny, g.nz, S, H, g.n, lw1, blk, yi, xw_p, o, ctl, xw, tag);
+      };
     }
   } else {
     fwd = [=](const T *blk, const T *r, T *yo) {

@@ -208,14 +208,15 @@ def test_ras_wide_layers(dims, prec):
     assert_close(z.cpu().numpy(), Mo.apply(r), 1e-10 if prec == 64 else 1e-4)
 
 
-@pytest.mark.parametrize("dims", [(6, 256, 128), (6, 258, 128), (5, 75, 100), (4, 40, 300), (7, 112, 64),
-                                  (3, 16, 20)])
+@pytest.mark.parametrize("dims", [(3, 448, 128), (3, 450, 128), (6, 256, 128), (5, 75, 100), (4, 40, 300),
+                                  (7, 112, 64), (3, 16, 20)])
 def test_ras_fp32_strip_shapes(dims):
-    """The FP32 sweeps at the edges of their launch shapes: strips of 128
-    lines (the largest the LDS-slot sweeps take), 129 (the register-prefetch
-    sweeps), uneven strips (38 + 37 lines), more layers than CUs (one strip
-    each), four strips, one 16-line strip.  Both sweeps are compared through
-    the CPR apply, twice in a row (the tickets and tags of a second launch)."""
+    """The FP32 sweeps at the edges of their launch shapes: strips of 224
+    lines (the largest the quad-per-cell sweeps take), 225 (the one-lane-per-
+    line sweeps), 128, uneven strips (38 + 37 lines), more layers than CUs
+    (one strip each), four strips, one 16-line strip.  Both sweeps are
+    compared through the CPR apply, twice in a row (the tickets and tags of a
+    second launch)."""
     p = _prob(dims, sigma=1.5)
     A = oracle.assemble(p)
     Mo = oracle.CPR(A, smoother=oracle.SM_RAS)

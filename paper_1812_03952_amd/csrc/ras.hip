@@ -6,12 +6,15 @@
 // ILU(0) only modifies the diagonal blocks, so it is DILU; restricted to a
 // layer the stencil is the in-plane 5-point one.
 //
-// Layers are independent, so each is one workgroup and no workgroup ever
-// waits on another.  Inside a layer the recurrences run over the lines
+// Layers are independent.  Inside a layer the recurrences run over the lines
 // i + j = lambda (nx + ny - 1 levels): the thread group of line j handles
 // cell (lambda - j, j) at level lambda, reads the previous level's values of
 // its own line and of line j-1 (j+1 backward) from LDS, and one barrier
-// separates the levels.  The factorisation uses one thread per cell in FP64.
+// separates the levels.  The factorisation and the FP64 sweeps give each
+// layer one workgroup, which never waits on another; the FP32 sweeps split a
+// layer into strips of lines, one workgroup each, that hand the boundary
+// line's values to the next strip level by level (see the strip sweeps).
+// The factorisation uses a quad of lanes per cell in FP64.
 //
 // The sweeps are written with D^{-1} folded in, which is the same operator
 // in exact arithmetic:

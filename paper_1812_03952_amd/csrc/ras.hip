@@ -547,18 +547,51 @@ __device__ __forceinline__ bool ras_get(const uint64_t *p, uint32_t tag, float &
   }
 }
 
+// A value in FP64 crosses strips as two such words, high half first, each
+// with the tag: words of value r of line i: [W r, W r + W), W = 1 or 2.
+template <class T> struct ras_nw { static constexpr int W = sizeof(T) / 4; };
+__device__ __forceinline__ void ras_put_v(uint64_t *p, float v, uint32_t tag) { ras_put(p, v, tag); }
+__device__ __forceinline__ void ras_put_v(uint64_t *p, double v, uint32_t tag) {
+  const uint64_t b = (uint64_t)__double_as_longlong(v);
+  __hip_atomic_store(p, ((uint64_t)tag << 32) | (b >> 32), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(p + 1, ((uint64_t)tag << 32) | (b & 0xffffffffull), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// value from its words once every tag is `tag`; w holds the words as loaded
+// earlier, re-read (bounded) until they match; false on time-out
+__device__ __forceinline__ bool ras_get_v(const uint64_t *p, const uint64_t (&w)[1], uint32_t tag, float &v,
+                                          bool &failed) {
+  if ((uint32_t)(w[0] >> 32) == tag) { v = __uint_as_float((uint32_t)w[0]); return true; }
+  return ras_get(p, tag, v, failed);
+}
+__device__ __forceinline__ bool ras_get_v(const uint64_t *p, const uint64_t (&w)[2], uint32_t tag, double &v,
+                                          bool &failed) {
+  uint32_t h[2];
+  for (int q = 0; q < 2; ++q) {
+    uint64_t x = w[q];
+    int spins = 0;
+    while ((uint32_t)(x >> 32) != tag) {
+      if (failed || ++spins > RAS_SPIN_LIMIT) { failed = true; return false; }
+      __builtin_amdgcn_s_sleep(1);
+      x = __hip_atomic_load(const_cast<uint64_t *>(p + q), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    h[q] = (uint32_t)x;
+  }
+  v = __longlong_as_double((long long)(((uint64_t)h[0] << 32) | h[1]));
+  return true;
+}
+
 // store the outputs of level lam (own lines [j0, j1)) from an LDS ring
 // buffer [H+2][4] (slot of line j: j - j0 + 1) to out, in wavefront order
 // (WF) or natural order
-template <bool WF>
+template <bool WF, class T = float>
 __device__ __forceinline__ void ras_write_strip(int lam, int nx, int ny, int j0, int j1, int64_t cl,
-                                                const float *__restrict__ src, float *__restrict__ out, int w, int nw) {
+                                                const T *__restrict__ src, T *__restrict__ out, int w, int nw) {
   if (lam < 0 || lam > nx + ny - 2) return;
   const int jlo = max(j0, lam - nx + 1), jhi = min(j1 - 1, lam);
   const int64_t base = WF ? cl + wf_off(lam, nx, ny) - max(0, lam - nx + 1) : 0;
   for (int j = jlo + w; j <= jhi; j += nw) {
     const int64_t c = WF ? base + j : cl + (int64_t)j * nx + (lam - j);
-    *(float4 *)(out + 4 * c) = *(const float4 *)(src + 4 * (j - j0 + 1));
+    *(typename vec4t<T>::type *)(out + 4 * c) = *(const typename vec4t<T>::type *)(src + 4 * (j - j0 + 1));
   }
 }
 
@@ -819,7 +852,7 @@ __global__ __launch_bounds__(320) void k_ras_bwd1(int nx, int ny, int nz, int S,
   }
 }
 
-// ---- sweeps with a quad of lanes per cell on strips (FP32) ------------------
+// ---- sweeps with a quad of lanes per cell on strips (FP32 and FP64) ---------
 // The strips, tickets and boundary words of the sweeps above, with the
 // compute of the one-workgroup-per-layer sweeps: lane r of a cell's quad owns
 // block row r and keeps its rows of the next P levels in flight in registers
@@ -830,16 +863,17 @@ __global__ __launch_bounds__(320) void k_ras_bwd1(int nx, int ny, int nz, int S,
 // (outputs and published boundary words); a poller wave only loads the
 // neighbour strip's words, so no wait for a load ever waits for a store.
 // Strips of up to 224 lines (one pass).
-template <int P>
+template <class T, int P>
 __global__ __launch_bounds__(1024) void k_ras_fwd3(int nx, int ny, int nz, int S, int H, int64_t n, int LWq,
-                                                   const float *__restrict__ blk, const float *__restrict__ rh,
-                                                   float *__restrict__ y, int *__restrict__ ctl,
+                                                   const T *__restrict__ blk, const T *__restrict__ rh,
+                                                   T *__restrict__ y, int *__restrict__ ctl,
                                                    uint64_t *__restrict__ xw, uint32_t tag) {
   extern __shared__ __align__(16) unsigned char smem[];
-  float *ring = (float *)smem;                          // [2][H+2][4]
+  T *ring = (T *)smem;                                  // [2][H+2][4]
   __shared__ int s_t;
-  __shared__ float gh[32][4];                           // ghost line j0-1, by level mod 32
+  __shared__ T gh[32][4];                               // ghost line j0-1, by level mod 32
   const int tid = threadIdx.x, NC = 4 * LWq;
+  constexpr int W = ras_nw<T>::W;                       // boundary words per value
   if (tid == 0) s_t = atomicAdd(&ctl[0], 1);
   __syncthreads();
   const int s = s_t / nz, k = s_t - (s_t / nz) * nz;
@@ -850,20 +884,22 @@ __global__ __launch_bounds__(1024) void k_ras_fwd3(int nx, int ny, int nz, int S
     // poller wave
     const int w = tid - NC - 64;
     bool failed = false;
-    auto issue16 = [&](int m16, uint64_t &slot) {
+    auto wp = [&](int m, int r) { return xw + W * (ras_xword(k, s - 1, S, nx, m) + r); };
+    auto issue16 = [&](int m16, uint64_t (&slot)[W]) {
       const int m = m16 + (w >> 2), r = w & 3;
       if (s == 0 || m >= nx) return;
-      slot = __hip_atomic_load(xw + ras_xword(k, s - 1, S, nx, m) + r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+      for (int q = 0; q < W; ++q)
+        slot[q] = __hip_atomic_load(wp(m, r) + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     };
-    auto finish16 = [&](int m16, uint64_t slot) {
+    auto finish16 = [&](int m16, const uint64_t (&slot)[W]) {
       const int m = m16 + (w >> 2), r = w & 3;
       if (s == 0 || m >= nx) return;
-      float v;
-      if ((uint32_t)(slot >> 32) == tag) v = __uint_as_float((uint32_t)slot);
-      else if (!ras_get(xw + ras_xword(k, s - 1, S, nx, m) + r, tag, v, failed)) atomicOr(&ctl[2], 1);
+      T v = 0;
+      if (!ras_get_v(wp(m, r), slot, tag, v, failed)) atomicOr(&ctl[2], 1);
       gh[m & 31][r] = v;
     };
-    uint64_t pend = 0;
+    uint64_t pend[W] = {};
     issue16(0, pend);
     finish16(0, pend);
     __syncthreads();
@@ -881,24 +917,24 @@ __global__ __launch_bounds__(1024) void k_ras_fwd3(int nx, int ny, int nz, int S
       if (s == S - 1 || w >= 4 || m < 0) return;
       const int i = m + j0 - (j1 - 1);
       if (i < 0 || i >= nx) return;
-      ras_put(xw + ras_xword(k, s, S, nx, i) + w, ring[(m & 1) * RS * 4 + (j1 - j0) * 4 + w], tag);
+      ras_put_v(xw + W * (ras_xword(k, s, S, nx, i) + w), ring[(m & 1) * RS * 4 + (j1 - j0) * 4 + w], tag);
     };
     __syncthreads();
     for (int m = 0; m < Lpad; ++m) {
-      ras_write_strip<true>(j0 + m - 1, nx, ny, j0, j1, cl, ring + ((m + 1) & 1) * RS * 4, y, w, nw);
+      ras_write_strip<true, T>(j0 + m - 1, nx, ny, j0, j1, cl, ring + ((m + 1) & 1) * RS * 4, y, w, nw);
       publish(m - 1);
       __syncthreads();
     }
-    ras_write_strip<true>(j0 + Lpad - 1, nx, ny, j0, j1, cl, ring + ((Lpad + 1) & 1) * RS * 4, y, w, nw);
+    ras_write_strip<true, T>(j0 + Lpad - 1, nx, ny, j0, j1, cl, ring + ((Lpad + 1) & 1) * RS * 4, y, w, nw);
     publish(Lpad - 1);
     return;
   }
   __syncthreads();
   const int row = tid & 3, j = j0 + (tid >> 2);
   const int sl = min(j, j1 - 1) - j0 + 1;               // slot of line j in the ring
-  const float *By = blk, *Bx = blk + n * 16;
-  ras_fpre<float> R[P];
-  auto load = [&](int m, ras_fpre<float> &p, float tok) {
+  const T *By = blk, *Bx = blk + n * 16;
+  ras_fpre<T> R[P];
+  auto load = [&](int m, ras_fpre<T> &p, T tok) {
     int jj = j;
     order_after(jj, tok);
     const int64_t c = wf_clamped(cl, j0 + m, jj, nx, ny);
@@ -907,19 +943,19 @@ __global__ __launch_bounds__(1024) void k_ras_fwd3(int nx, int ny, int nz, int S
     ld4v(Bx + c * 16 + 4 * row, p.a2);
   };
 #pragma unroll
-  for (int d = 0; d < P; ++d) load(d, R[d], 0.f);
+  for (int d = 0; d < P; ++d) load(d, R[d], (T)0);
   for (int m0 = 0; m0 < Lpad; m0 += P) {
 #pragma unroll
     for (int d = 0; d < P; ++d) {
       const int m = m0 + d, i = j0 + m - j;
       const bool act = j < j1 && i >= 0 && i < nx;
-      float *cur = ring + (m & 1) * RS * 4;
-      const float *prv = ring + ((m + 1) & 1) * RS * 4;
-      float yy[4], yx[4];
+      T *cur = ring + (m & 1) * RS * 4;
+      const T *prv = ring + ((m + 1) & 1) * RS * 4;
+      T yy[4], yx[4];
       ld4v(sl == 1 ? &gh[m & 31][0] : prv + 4 * (sl - 1), yy);   // line j0-1: the ghost
       ld4v(prv + 4 * sl, yx);
-      const float ty = dot4(R[d].a1, yy), tx = dot4(R[d].a2, yx);
-      float v = R[d].r;
+      const T ty = dot4(R[d].a1, yy), tx = dot4(R[d].a2, yx);
+      T v = R[d].r;
       v = (act && j > 0) ? v - ty : v;
       v = (act && i > 0) ? v - tx : v;
       if (act) cur[4 * sl + row] = v;
@@ -929,43 +965,46 @@ __global__ __launch_bounds__(1024) void k_ras_fwd3(int nx, int ny, int nz, int S
   }
 }
 
-template <int P>
+template <class T, int P>
 __global__ __launch_bounds__(1024) void k_ras_bwd3(int nx, int ny, int nz, int S, int H, int64_t n, int LWq,
-                                                   const float *__restrict__ blk, const float *__restrict__ y,
-                                                   const float *__restrict__ xpw, float *__restrict__ out,
+                                                   const T *__restrict__ blk, const T *__restrict__ y,
+                                                   const T *__restrict__ xpw, T *__restrict__ out,
                                                    int *__restrict__ ctl, uint64_t *__restrict__ xw, uint32_t tag) {
   extern __shared__ __align__(16) unsigned char smem[];
-  float *ring = (float *)smem;                          // [2][H+2][4]: z
+  T *ring = (T *)smem;                                  // [2][H+2][4]: z
   __shared__ int s_t;
-  __shared__ float gh[32][4];                           // ghost line j1, by step mod 32
+  __shared__ T gh[32][4];                               // ghost line j1, by step mod 32
   const int tid = threadIdx.x, NC = 4 * LWq;
+  constexpr int W = ras_nw<T>::W;                       // boundary words per value
   if (tid == 0) s_t = atomicAdd(&ctl[1], 1);
   __syncthreads();
   const int st = s_t / nz, k = s_t - st * nz, s = S - 1 - st;   // last strip first
   const int j0 = s * H, j1 = min(ny, j0 + H), RS = H + 2, nl = j1 - j0;
-  float *oring = ring + 2 * RS * 4;                     // [2][H+2][4]: output
+  T *oring = ring + 2 * RS * 4;                         // [2][H+2][4]: output
   const int64_t nxy = (int64_t)nx * ny, cl = nxy * k;
   const int Lw = nx + nl - 1, Lpad = (Lw + P - 1) / P * P;
   const int ltop = j1 - 1 + nx - 1;                     // step m handles level ltop - m
   if (tid >= NC + 64) {
     const int w = tid - NC - 64;
     bool failed = false;
-    auto issue16 = [&](int m16, uint64_t &slot) {
+    auto wp = [&](int i, int r) { return xw + W * (ras_xword(k, s + 1, S, nx, i) + r); };
+    auto issue16 = [&](int m16, uint64_t (&slot)[W]) {
       const int m = m16 + (w >> 2), r = w & 3;
       const int i = ltop - m - (j1 - 1);
       if (s == S - 1 || i < 0 || i >= nx) return;
-      slot = __hip_atomic_load(xw + ras_xword(k, s + 1, S, nx, i) + r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+      for (int q = 0; q < W; ++q)
+        slot[q] = __hip_atomic_load(wp(i, r) + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     };
-    auto finish16 = [&](int m16, uint64_t slot) {
+    auto finish16 = [&](int m16, const uint64_t (&slot)[W]) {
       const int m = m16 + (w >> 2), r = w & 3;
       const int i = ltop - m - (j1 - 1);
       if (s == S - 1 || i < 0 || i >= nx) return;
-      float v;
-      if ((uint32_t)(slot >> 32) == tag) v = __uint_as_float((uint32_t)slot);
-      else if (!ras_get(xw + ras_xword(k, s + 1, S, nx, i) + r, tag, v, failed)) atomicOr(&ctl[2], 1);
+      T v = 0;
+      if (!ras_get_v(wp(i, r), slot, tag, v, failed)) atomicOr(&ctl[2], 1);
       gh[m & 31][r] = v;
     };
-    uint64_t pend = 0;
+    uint64_t pend[W] = {};
     issue16(0, pend);
     finish16(0, pend);
     __syncthreads();
@@ -982,24 +1021,24 @@ __global__ __launch_bounds__(1024) void k_ras_bwd3(int nx, int ny, int nz, int S
       if (s == 0 || w >= 4 || m < 0) return;
       const int i = ltop - m - j0;
       if (i < 0 || i >= nx) return;
-      ras_put(xw + ras_xword(k, s, S, nx, i) + w, ring[(m & 1) * RS * 4 + 4 + w], tag);
+      ras_put_v(xw + W * (ras_xword(k, s, S, nx, i) + w), ring[(m & 1) * RS * 4 + 4 + w], tag);
     };
     __syncthreads();
     for (int m = 0; m < Lpad; ++m) {
-      if (m >= 1) ras_write_strip<false>(ltop - m + 1, nx, ny, j0, j1, cl, oring + ((m + 1) & 1) * RS * 4, out, w, nw);
+      if (m >= 1) ras_write_strip<false, T>(ltop - m + 1, nx, ny, j0, j1, cl, oring + ((m + 1) & 1) * RS * 4, out, w, nw);
       publish(m - 1);
       __syncthreads();
     }
-    ras_write_strip<false>(ltop - Lpad + 1, nx, ny, j0, j1, cl, oring + ((Lpad + 1) & 1) * RS * 4, out, w, nw);
+    ras_write_strip<false, T>(ltop - Lpad + 1, nx, ny, j0, j1, cl, oring + ((Lpad + 1) & 1) * RS * 4, out, w, nw);
     publish(Lpad - 1);
     return;
   }
   __syncthreads();
   const int row = tid & 3, j = j0 + (tid >> 2);
   const int sl = min(j, j1 - 1) - j0 + 1;
-  const float *Bx = blk + 2 * n * 16, *By = blk + 3 * n * 16;
-  ras_bpre<float> R[P];
-  auto load = [&](int m, ras_bpre<float> &p, float tok) {
+  const T *Bx = blk + 2 * n * 16, *By = blk + 3 * n * 16;
+  ras_bpre<T> R[P];
+  auto load = [&](int m, ras_bpre<T> &p, T tok) {
     int jj = j;
     order_after(jj, tok);
     const int64_t c = wf_clamped(cl, ltop - m, jj, nx, ny);
@@ -1009,18 +1048,18 @@ __global__ __launch_bounds__(1024) void k_ras_bwd3(int nx, int ny, int nz, int S
     ld4v(By + c * 16 + 4 * row, p.a5);
   };
 #pragma unroll
-  for (int d = 0; d < P; ++d) load(d, R[d], 0.f);
+  for (int d = 0; d < P; ++d) load(d, R[d], (T)0);
   for (int m0 = 0; m0 < Lpad; m0 += P) {
 #pragma unroll
     for (int d = 0; d < P; ++d) {
       const int m = m0 + d, i = ltop - m - j;
       const bool act = j < j1 && i >= 0 && i < nx;
       const int cb = (m & 1) * RS * 4, pb = ((m + 1) & 1) * RS * 4;
-      float zx[4], zy[4];
+      T zx[4], zy[4];
       ld4v(ring + pb + 4 * sl, zx);
       ld4v(sl == nl ? &gh[m & 31][0] : ring + pb + 4 * (sl + 1), zy);   // line j1: the ghost
-      const float tx = dot4(R[d].a4, zx), ty = dot4(R[d].a5, zy);
-      float zc = R[d].yc;
+      const T tx = dot4(R[d].a4, zx), ty = dot4(R[d].a5, zy);
+      T zc = R[d].yc;
       zc = (act && i < nx - 1) ? zc - tx : zc;
       zc = (act && j < ny - 1) ? zc - ty : zc;
       if (act) {
@@ -1195,13 +1234,13 @@ rs_status rs_ras_setup_run(rs_cpr_s *M, int *flag, hipStream_t s) {
     RS_TRY(M->rz2.alloc(es * 4 * (size_t)g.n));
     RS_TRY(M->rzero.alloc(es * (size_t)g.n));
   }
-  if (M->prec == 32) {
+  {
     // strips per layer: enough workgroups for the CUs, at least 32 lines each
     int S = std::max(1, std::min(256 / std::max(g.nz, 1), (g.ny + 31) / 32));
     int H = (g.ny + S - 1) / S;
     S = (g.ny + H - 1) / H;                          // every strip non-empty
     M->rs_strips = S; M->rs_h = H;
-    const size_t words = (size_t)g.nz * S * g.nx * 4;
+    const size_t words = (size_t)g.nz * S * g.nx * 4 * (M->prec == 64 ? 2 : 1);
     RS_TRY(M->rxw.alloc(sizeof(uint64_t) * words));
     RS_TRY(M->rctl.alloc(sizeof(int) * 4));
     RS_HIP(hipMemsetAsync(M->rxw.p, 0, sizeof(uint64_t) * words, s));
@@ -1264,7 +1303,7 @@ rs_status rs_ras_apply_run(rs_cpr_s *M, const T *xp, T *out, hipStream_t s) {
     const int64_t tiles = (int64_t)g.nz * ((g.nx + RI - 1) / RI) * ((g.ny + RJ - 1) / RJ);
     // the tickets of the sweeps below are zeroed here (overlap 0); the
     // overlapping form sweeps several times and zeroes them before each
-    int *tk = (sizeof(T) == 4 && !ov1) ? M->rctl.as<int>() : nullptr;
+    int *tk = !ov1 ? M->rctl.as<int>() : nullptr;
     k_ras_in_tile<T><<<(unsigned)tiles, 4 * RI * RJ, 0, s>>>(g.nx, g.ny, g.n, M->rt.as<T>(), D->col0.as<T>(), xp,
                                                              P0, rh, xpw, tk);
   }
@@ -1277,48 +1316,46 @@ rs_status rs_ras_apply_run(rs_cpr_s *M, const T *xp, T *out, hipStream_t s) {
   std::function<void(const T *, const T *, T *)> fwd;
   // one backward sweep: result + x_p (x_p in wavefront order) in natural order
   std::function<void(const T *, const T *, const T *, T *)> bwd;
-  if constexpr (sizeof(T) == 4) {
-    // strips of H lines, one lane per line (at most 256 per pass), one
-    // writer wave per workgroup; the tickets restart at every launch
-    const int S = M->rs_strips, H = M->rs_h;
+  // strips of H lines (the tickets restart at every launch)
+  const int S = M->rs_strips, H = M->rs_h;
+  int *ctl = M->rctl.as<int>();
+  uint64_t *xw = M->rxw.as<uint64_t>();
+  const unsigned nwg = (unsigned)(g.nz * S);
+  if (H <= 224) {
+    // strips of at most 224 lines: a quad of lanes per cell (one pass)
+    const int lwq = (H + 15) / 16 * 16, ntq = 4 * lwq + 128;
+    const size_t rb3 = sizeof(T) * 8 * (size_t)(H + 2);
+    fwd = [=](const T *blk, const T *r, T *yo) {
+      if (ov1) k_ras_reset<<<1, 64, 0, s>>>(ctl);
+      const uint32_t tag = ++M->repoch;
+      k_ras_fwd3<T, 4><<<nwg, ntq, rb3, s>>>(g.nx, g.ny, g.nz, S, H, g.n, lwq, blk, r, yo, ctl, xw, tag);
+    };
+    bwd = [=](const T *blk, const T *yi, const T *xw_p, T *o) {
+      if (ov1) k_ras_reset<<<1, 64, 0, s>>>(ctl);
+      const uint32_t tag = ++M->repoch;
+      k_ras_bwd3<T, 4><<<nwg, ntq, 2 * rb3, s>>>(g.nx, g.ny, g.nz, S, H, g.n, lwq, blk, yi, xw_p, o, ctl, xw, tag);
+    };
+  } else if constexpr (sizeof(T) == 4) {
+    // taller strips (FP32): one lane per line (at most 256 per pass, U passes)
     const int u1 = H <= 256 ? 1 : (H <= 512 ? 2 : 4);
     const int lw1 = ((H + u1 - 1) / u1 + 63) / 64 * 64, nt1 = lw1 + 64;
     const size_t rb = sizeof(float) * 8 * (size_t)(H + 2);
-    int *ctl = M->rctl.as<int>();
-    uint64_t *xw = M->rxw.as<uint64_t>();
-    const unsigned nwg = (unsigned)(g.nz * S);
-    // strips of at most 224 lines: a quad of lanes per cell (one pass)
-    const int lwq = (H + 15) / 16 * 16, ntq = 4 * lwq + 128;
-    if (H <= 224) {
-      const size_t rb3 = sizeof(float) * 8 * (size_t)(H + 2);
-      fwd = [=](const T *blk, const T *r, T *yo) {
-        if (ov1) k_ras_reset<<<1, 64, 0, s>>>(ctl);
-        const uint32_t tag = ++M->repoch;
-        k_ras_fwd3<4><<<nwg, ntq, rb3, s>>>(g.nx, g.ny, g.nz, S, H, g.n, lwq, blk, r, yo, ctl, xw, tag);
-      };
-      bwd = [=](const T *blk, const T *yi, const T *xw_p, T *o) {
-        if (ov1) k_ras_reset<<<1, 64, 0, s>>>(ctl);
-        const uint32_t tag = ++M->repoch;
-        k_ras_bwd3<4><<<nwg, ntq, 2 * rb3, s>>>(g.nx, g.ny, g.nz, S, H, g.n, lwq, blk, yi, xw_p, o, ctl, xw, tag);
-      };
-    } else {
-      // taller strips: one lane per line, U passes
-      fwd = [=](const T *blk, const T *r, T *yo) {
-        if (ov1) k_ras_reset<<<1, 64, 0, s>>>(ctl);
-        const uint32_t tag = ++M->repoch;
-        if (u1 == 1) k_ras_fwd1<1, 5><<<nwg, nt1, rb, s>>>(g.nx, g.ny, g.nz, S, H, g.n, lw1, blk, r, yo, ctl, xw, tag);
-        else if (u1 == 2) k_ras_fwd1<2, 3><<<nwg, nt1, rb, s>>>(g.nx, g.ny, g.nz, S, H, g.n, lw1, blk, r, yo, ctl, xw, tag);
-        else k_ras_fwd1<4, 2><<<nwg, nt1, rb, s>>>(g.nx, g.ny, g.nz, S, H, g.n, lw1, blk, r, yo, ctl, xw, tag);
-      };
-      bwd = [=](const T *blk, const T *yi, const T *xw_p, T *o) {
-        if (ov1) k_ras_reset<<<1, 64, 0, s>>>(ctl);
-        const uint32_t tag = ++M->repoch;
-        if (u1 == 1) k_ras_bwd1<1, 5><<<nwg, nt1, 2 * rb, s>>>(g.nx, g.ny, g.nz, S, H, g.n, lw1, blk, yi, xw_p, o, ctl, xw, tag);
-        else if (u1 == 2) k_ras_bwd1<2, 3><<<nwg, nt1, 2 * rb, s>>>(g.nx, g.ny, g.nz, S, H, g.n, lw1, blk, yi, xw_p, o, ctl, xw, tag);
-        else k_ras_bwd1<4, 2><<<nwg, nt1, 2 * rb, s>>>(g.nx, g.ny, g.nz, S, H, g.n, lw1, blk, yi, xw_p, o, ctl, xw, tag);
-      };
-    }
+    fwd = [=](const T *blk, const T *r, T *yo) {
+      if (ov1) k_ras_reset<<<1, 64, 0, s>>>(ctl);
+      const uint32_t tag = ++M->repoch;
+      if (u1 == 1) k_ras_fwd1<1, 5><<<nwg, nt1, rb, s>>>(g.nx, g.ny, g.nz, S, H, g.n, lw1, blk, r, yo, ctl, xw, tag);
+      else if (u1 == 2) k_ras_fwd1<2, 3><<<nwg, nt1, rb, s>>>(g.nx, g.ny, g.nz, S, H, g.n, lw1, blk, r, yo, ctl, xw, tag);
+      else k_ras_fwd1<4, 2><<<nwg, nt1, rb, s>>>(g.nx, g.ny, g.nz, S, H, g.n, lw1, blk, r, yo, ctl, xw, tag);
+    };
+    bwd = [=](const T *blk, const T *yi, const T *xw_p, T *o) {
+      if (ov1) k_ras_reset<<<1, 64, 0, s>>>(ctl);
+      const uint32_t tag = ++M->repoch;
+      if (u1 == 1) k_ras_bwd1<1, 5><<<nwg, nt1, 2 * rb, s>>>(g.nx, g.ny, g.nz, S, H, g.n, lw1, blk, yi, xw_p, o, ctl, xw, tag);
+      else if (u1 == 2) k_ras_bwd1<2, 3><<<nwg, nt1, 2 * rb, s>>>(g.nx, g.ny, g.nz, S, H, g.n, lw1, blk, yi, xw_p, o, ctl, xw, tag);
+      else k_ras_bwd1<4, 2><<<nwg, nt1, 2 * rb, s>>>(g.nx, g.ny, g.nz, S, H, g.n, lw1, blk, yi, xw_p, o, ctl, xw, tag);
+    };
   } else {
+    // taller layers (FP64): one workgroup per layer, a quad of lanes per cell
     fwd = [=](const T *blk, const T *r, T *yo) {
       if (sh.u == 1) k_ras_fwd<T, 1, 4><<<g.nz, nt, ring_bytes, s>>>(g.nx, g.ny, g.n, sh.lw, blk, r, yo);
       else k_ras_fwd<T, 2, 2><<<g.nz, nt, ring_bytes, s>>>(g.nx, g.ny, g.n, sh.lw, blk, r, yo);

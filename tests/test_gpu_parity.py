@@ -208,25 +208,26 @@ def test_ras_wide_layers(dims, prec):
     assert_close(z.cpu().numpy(), Mo.apply(r), 1e-10 if prec == 64 else 1e-4)
 
 
+@pytest.mark.parametrize("prec", [32, 64])
 @pytest.mark.parametrize("dims", [(3, 448, 128), (3, 450, 128), (6, 256, 128), (5, 75, 100), (4, 40, 300),
                                   (7, 112, 64), (3, 16, 20)])
-def test_ras_fp32_strip_shapes(dims):
-    """The FP32 sweeps at the edges of their launch shapes: strips of 224
-    lines (the largest the quad-per-cell sweeps take), 225 (the one-lane-per-
-    line sweeps), 128, uneven strips (38 + 37 lines), more layers than CUs
-    (one strip each), four strips, one 16-line strip.  Both sweeps are
-    compared through the CPR apply, twice in a row (the tickets and tags of a
-    second launch)."""
+def test_ras_strip_shapes(dims, prec):
+    """The sweeps at the edges of their launch shapes: strips of 224 lines
+    (the largest the quad-per-cell strip sweeps take), 225 (one lane per line
+    in FP32, one workgroup per layer in FP64), 128, uneven strips (38 + 37
+    lines), more layers than CUs (one strip each), four strips, one 16-line
+    strip.  Both sweeps are compared through the CPR apply, twice in a row
+    (the tickets and tags of a second launch)."""
     p = _prob(dims, sigma=1.5)
     A = oracle.assemble(p)
     Mo = oracle.CPR(A, smoother=oracle.SM_RAS)
     B = upload(A)
-    Mg = rs.cpr_setup(B, rs.decouple(B, rs.ABF, 32), rs.cpr_opts(smoother=rs.SM_RAS))
+    Mg = rs.cpr_setup(B, rs.decouple(B, rs.ABF, prec), rs.cpr_opts(smoother=rs.SM_RAS))
     for seed in (9, 10):
         r = np.random.default_rng(seed).standard_normal(4 * A.n)
         z = torch.empty(4 * A.n, dtype=torch.float64, device="cuda")
         rs.cpr_apply(Mg, dev(r), z)
-        assert_close(z.cpu().numpy(), Mo.apply(r), 1e-4)
+        assert_close(z.cpu().numpy(), Mo.apply(r), 1e-4 if prec == 32 else 1e-10)
 
 
 def test_ras_layer_limit():

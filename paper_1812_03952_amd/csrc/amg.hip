@@ -347,7 +347,12 @@ __global__ void k_cand(int nc, const int32_t *__restrict__ mptr, const int32_t *
 // at most GAL_CAP distinct coarse columns; a row that needs more starts
 // again with the list in the global scratch (sized by the candidate count).
 // The additions happen in the same order either way.
-constexpr int GAL_BLOCK = 128, GAL_CAP = 32;
+constexpr int GAL_BLOCK = 128;
+// LDS list length per row source: piecewise-constant aggregation of a
+// 7-point (and the next coarser) pattern gives short coarse rows (at most 15
+// entries on the grids measured), and a shorter list leaves room for more
+// workgroups per CU; the smoothed product's rows are longer
+template <class R> struct gal_cap { static constexpr int CAP = 16; };
 
 // Row sources: each(i, agg, f) calls f(agg[col], a) for the entries of
 // fine row i in column order and stops when f returns false.
@@ -449,7 +454,7 @@ __device__ __forceinline__ bool gal_row(int I, const int32_t *__restrict__ mptr,
   return true;
 }
 
-template <class R>
+template <class R, int GAL_CAP = gal_cap<R>::CAP>
 __global__ __launch_bounds__(GAL_BLOCK) void k_galerkin(int nc, const int32_t *__restrict__ mptr,
                                                         const int32_t *__restrict__ mem, R rows,
                                                         const int32_t *__restrict__ agg,
@@ -1453,6 +1458,7 @@ struct rows_sa {
     return true;
   }
 };
+template <> struct gal_cap<rows_sa> { static constexpr int CAP = 32; };
 
 #pragma clang fp contract(fast)
 

@@ -102,8 +102,9 @@ def run_variant(rs, dp, A, prec, steps, warmup, tag, smoother, solver="gmres", m
         t1 = time.perf_counter()
         M = rs.cpr_setup(A, D, rs.cpr_opts(smoother=smoother, stages=stages, smooth=smooth))
         t2 = time.perf_counter()
-        x = torch.zeros_like(dp.b)
-        # x0 = 0: the solvers take r0 = b without a product with A
+        # x0 = 0 by zero_guess: the solvers take r0 = b without a product with
+        # A and never read x before writing it
+        x = torch.empty_like(dp.b)
         if solver == "gmres":
             info = rs.gmres_solve(A, M, dp.b, x, rs.gmres_opts(zero_guess=1))
         else:

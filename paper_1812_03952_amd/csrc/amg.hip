@@ -1819,6 +1819,7 @@ rs_status rs_amg_build(rs_cpr_s *M, hipStream_t s) {
     int h = 0;
     RS_TRY(rs_wait_read(&h, flag.p, sizeof(int), s));
     if (h) return RS_E_SINGULAR;
+    return RS_OK;                 // the read waited for the stream
   }
   RS_TRY(rs_wait(s));
   return RS_OK;

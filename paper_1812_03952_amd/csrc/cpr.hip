@@ -297,23 +297,24 @@ extern "C" rs_status rs_cpr_setup(rs_bsr A, rs_dcpl D, const rs_cpr_opts *o, voi
     }
   } while (0);
   if (split && launched) {
-    // join: the caller's stream waits for the side stream, and the side
-    // stream is drained before any buffer can go back to the pool
-    if (hipEventRecord(ev, ss) != hipSuccess || hipStreamWaitEvent(s, ev, 0) != hipSuccess ||
-        rs_wait(ss) != RS_OK) {
+    // join: the caller's stream waits for the side stream; the read of the
+    // error word below waits for the caller's stream, hence for all the side
+    // stream's work, before any buffer can go back to the pool
+    if (hipEventRecord(ev, ss) != hipSuccess || hipStreamWaitEvent(s, ev, 0) != hipSuccess) {
       if (st == RS_OK) st = RS_E_HIP;
     }
   }
-  if (ev) (void)hipEventDestroy(ev);
   if (st == RS_OK) {
     int h = 0;
     if (hipGetLastError() != hipSuccess || rs_wait_read(&h, flag.p, sizeof(int), s) != RS_OK) st = RS_E_HIP;
     else if (h & RSF_NONFINITE) st = RS_E_NONFINITE;
     else if (h & RSF_SINGULAR) st = RS_E_SINGULAR;
-    else st = rs_dilu_check(M, s);
+    else if (opts.smoother == RS_SM_DILU) st = rs_dilu_check(M, s);   // its set-up's bounded waits
   } else {
     (void)hipStreamSynchronize(s);
+    if (split && launched) (void)hipStreamSynchronize(ss);
   }
+  if (ev) (void)hipEventDestroy(ev);
   if (st != RS_OK) { delete M; return st; }
   *out = M;
   return RS_OK;

@@ -527,8 +527,7 @@ rs_status rs_dilu_apply_run(rs_cpr_s *M, const T *xp, T *out, hipStream_t s) {
   const rs_dcpl_s *D = M->D;
   uint64_t *xch = M->pxch.as<uint64_t>();
   uint32_t xbytes = (uint32_t)M->pxch.bytes;
-  int nw = 6;
-  if (const char *e = getenv("RSOLVE_DILU_WAVES")) { int v = atoi(e); if (v == 4 || v == 6 || v == 8) nw = v; }
+  const int nw = 6;                   // waves per brick workgroup
   pipe_reset(M, s);
   uint32_t tag = ++M->pepoch;
 #define RS_FWD(NW) k_fwd_pipe<T, NW><<<nb, 64 * NW, 0, s>>>(g.nx, g.ny, g.nz, M->pnj, M->pord.as<int>(), ctl, ctl + 1, \

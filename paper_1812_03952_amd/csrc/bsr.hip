@@ -12,6 +12,7 @@
 // the SpMV then finds each block from the closed-form row start of csr7.h,
 // with the same 32-byte row pieces and the same arithmetic.
 #include "rs_internal.h"
+#include <algorithm>
 #include <math.h>
 
 namespace {
@@ -119,6 +120,16 @@ template <> struct vec4_of<float> {
 // CSR: a7 is the caller's row-major blocks in CSR order (attached values);
 // an off-grid slot reads the row's diagonal block and zeroes it, so both
 // layouts give the same products in the same order.
+// Without dot products (ND = 0) the cells are handed out in row bands, one
+// per XCD: workgroup i runs on XCD i % 8 (round-robin dispatch) and takes the
+// (i / 8)-th run of 64 cells of band i % 8, the rows j in
+// [x ny / 8, (x + 1) ny / 8) of every plane.  A cell's +-x, +-y and +-z
+// neighbours are then mostly in the same band, so x is fetched into one L2
+// instead of several (the results do not depend on the mapping; the grid is
+// spmv_band_grid).  With dot products the natural order keeps each
+// workgroup's partial over the same cells as before.
+__host__ __device__ inline int64_t spmv_band_rows(int ny, int b) { return (int64_t)(b + 1) * ny / 8 - (int64_t)b * ny / 8; }
+
 template <class TX, bool RES, int ND, bool CSR>
 __global__ __launch_bounds__(256) void k_spmv7(int64_t n, int ny, int nz, int64_t nx, int64_t nxy,
                                                 const double *__restrict__ a7,
@@ -127,8 +138,20 @@ __global__ __launch_bounds__(256) void k_spmv7(int64_t n, int ny, int nz, int64_
                                                 double *__restrict__ y,
                                                 const double *__restrict__ u,
                                                 double *__restrict__ part) {
-  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool valid = t < 4 * n;
+  int64_t t;
+  bool valid;
+  if constexpr (ND == 0) {
+    const int xb = (int)(blockIdx.x & 7u);
+    const uint32_t m = (blockIdx.x >> 3) * 64u + (threadIdx.x >> 2);        // cell within the band
+    const uint32_t j0 = (uint32_t)((int64_t)xb * ny / 8);
+    const uint32_t band = (uint32_t)(spmv_band_rows(ny, xb) * nx);          // cells of the band per plane
+    valid = band > 0 && m < band * (uint32_t)nz;                              // n < 2^31
+    const uint32_t k = valid ? m / band : 0, in = valid ? m - k * band : 0;
+    t = 4 * ((int64_t)k * nxy + (int64_t)j0 * nx + in) + (threadIdx.x & 3);
+  } else {
+    t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    valid = t < 4 * n;
+  }
   double yv = 0.0;
   if (valid) {
     int64_t c = t >> 2;
@@ -332,6 +355,13 @@ rs_status rs_spmv_any(const rs_bsr_s *A, const void *x, int xprec, double *y, co
 
 unsigned rs_spmv_blocks(const rs_bsr_s *A) { return rs_grid(4 * A->g.n); }
 
+// grid of the banded SpMV (ND = 0): 8 x the workgroups of the largest band
+static unsigned spmv_band_grid(const grid3 &g) {
+  int64_t most = 0;
+  for (int b = 0; b < 8; ++b) most = std::max(most, spmv_band_rows(g.ny, b) * g.nx * g.nz);
+  return (unsigned)(8 * ((most + 63) / 64));
+}
+
 // LDS reserved by every SpMV launch, unused by the kernel: it caps the SpMV at
 // three workgroups (12 waves) per CU.  Fewer requests in flight at once
 // stream A faster on this part (measured 4 to 6 % at 0.5M to 32M cells
@@ -341,7 +371,7 @@ static constexpr size_t SPMV_LDS_CAP = 160 * 1024 / 3 - 1024;
 rs_status rs_spmv_dots(const rs_bsr_s *A, const void *x, int xprec, double *y, const double *b_minus,
                        int nd, const double *u, double *part, hipStream_t s) {
   int64_t n = A->g.n;
-  unsigned grid = rs_grid(4 * n);
+  const unsigned grid = nd == 0 ? spmv_band_grid(A->g) : rs_grid(4 * n);
   const double *a7 = A->ref ? A->ref : A->a7.as<double>();
   const int64_t nx = A->g.nx, nxy = A->g.nxy;
   const int ny = A->g.ny, nz = A->g.nz;

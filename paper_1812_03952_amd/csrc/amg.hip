@@ -33,6 +33,7 @@
 //              recompute it); on the fine level, which keeps the 7-point
 //              pattern and is stored by stencil slot, it is formed once.
 #include "rs_internal.h"
+#include <algorithm>
 #include <type_traits>
 #include <math.h>
 #include <mutex>
@@ -958,6 +959,28 @@ __device__ __forceinline__ int nbr7(int i, int s, int n, int nx, int nxy) {
   return (q < 0 || q >= n) ? i : q;             // off-grid slots hold zero values
 }
 
+// Fine-level V-cycle kernels hand out their cells in row bands, one per XCD
+// (as the SpMV): workgroup i runs on XCD i % 8 and takes the (i / 8)-th run of
+// blockDim.x cells of band i % 8, the rows [b ny / 8, (b + 1) ny / 8) of every
+// plane, so a cell's neighbours are mostly read through the same L2.  False
+// past the band's end.  Grid: band_grid.
+__device__ __forceinline__ bool band_cell(int n, int nx, int nxy, int &c) {
+  const int ny = nxy / nx, nz = n / nxy;
+  const int xb = (int)(blockIdx.x & 7u);
+  const uint32_t m = (blockIdx.x >> 3) * blockDim.x + threadIdx.x;
+  const uint32_t j0 = (uint32_t)((int64_t)xb * ny / 8), j1 = (uint32_t)((int64_t)(xb + 1) * ny / 8);
+  const uint32_t band = (j1 - j0) * (uint32_t)nx;
+  if (band == 0 || m >= band * (uint32_t)nz) return false;
+  const uint32_t k = m / band;
+  c = (int)(k * (uint32_t)nxy + j0 * (uint32_t)nx + (m - k * band));
+  return true;
+}
+static unsigned band_grid(int nx, int ny, int nz) {
+  int64_t most = 0;
+  for (int b = 0; b < 8; ++b) most = std::max(most, ((int64_t)(b + 1) * ny / 8 - (int64_t)b * ny / 8) * nx * nz);
+  return (unsigned)(8 * ((most + RS_BLOCK - 1) / RS_BLOCK));
+}
+
 // pre-smoothing from x = 0 and the residual: y = b ./ d (kept for the
 // post-smoothing), r = b - A y with each neighbour's y_q = b_q / d_q formed
 // where it is used (the same division, so the same value as a stored y)
@@ -965,8 +988,8 @@ template <class T>
 __global__ __launch_bounds__(256) void k_vc_pre7(int n, int nx, int nxy, const T *__restrict__ s7,
                                                   const T *__restrict__ d, const T *__restrict__ b,
                                                   T *__restrict__ y, T *__restrict__ r) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+  int i;
+  if (!band_cell(n, nx, nxy, i)) return;
   T s = 0;
 #pragma unroll
   for (int k = 0; k < 7; ++k) {
@@ -982,8 +1005,8 @@ __global__ __launch_bounds__(256) void k_vc_post7(int n, int nx, int nxy, const 
                                                    const T *__restrict__ d, const int32_t *__restrict__ agg,
                                                    const T *__restrict__ b, const T *__restrict__ y,
                                                    const T *__restrict__ xc, T *__restrict__ x) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+  int i;
+  if (!band_cell(n, nx, nxy, i)) return;
   // two batches of loads, each issued at once: the neighbours' y and
   // aggregates, then their coarse corrections (index 0 for no aggregate)
   T yq[7], xq[7];
@@ -1506,8 +1529,8 @@ template <class T>
 __global__ __launch_bounds__(256) void k_vc_post7z(int n, int nx, int nxy, const T *__restrict__ s7,
                                                     const T *__restrict__ d, const T *__restrict__ b,
                                                     const T *__restrict__ z, T *__restrict__ x) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+  int i;
+  if (!band_cell(n, nx, nxy, i)) return;
   T s = 0;
 #pragma unroll
   for (int k = 0; k < 7; ++k) s = fma(s7[(int64_t)k * n + i], z[nbr7(i, k, n, nx, nxy)], s);
@@ -1834,7 +1857,7 @@ static rs_status vcycle_t(rs_cpr_s *M, hipStream_t s) {
     const T *a = (M->prec == 64) ? (const T *)L->a.p : (const T *)L->ap.p;
     if (l == 0 && L->s7.p) {
       const grid3 &g = M->A->g;
-      k_vc_pre7<T><<<rs_grid(L->n), RS_BLOCK, 0, s>>>(L->n, g.nx, (int)g.nxy, L->s7.as<T>(), L->dl1.as<T>(),
+      k_vc_pre7<T><<<band_grid(g.nx, g.ny, g.nz), RS_BLOCK, 0, s>>>(L->n, g.nx, (int)g.nxy, L->s7.as<T>(), L->dl1.as<T>(),
                                                       L->b.as<T>(), L->y.as<T>(), L->r.as<T>());
     } else {
       k_vc_pre<T><<<rs_grid(L->n), RS_BLOCK, 0, s>>>(L->n, L->rp.as<int32_t>(), L->ci.as<int32_t>(), a,
@@ -1875,7 +1898,7 @@ static rs_status vcycle_t(rs_cpr_s *M, hipStream_t s) {
                                                          Cl->xp<T>(), L->z.as<T>());
       if (st) {
         const grid3 &g = M->A->g;
-        k_vc_post7z<T><<<rs_grid(L->n), RS_BLOCK, 0, s>>>(L->n, g.nx, (int)g.nxy, L->s7.as<T>(), L->dl1.as<T>(),
+        k_vc_post7z<T><<<band_grid(g.nx, g.ny, g.nz), RS_BLOCK, 0, s>>>(L->n, g.nx, (int)g.nxy, L->s7.as<T>(), L->dl1.as<T>(),
                                                           L->b.as<T>(), L->z.as<T>(), L->xp<T>());
       } else {
         k_vc_postz<T><<<rs_grid(L->n), RS_BLOCK, 0, s>>>(L->n, L->rp.as<int32_t>(), L->ci.as<int32_t>(), a,
@@ -1883,7 +1906,7 @@ static rs_status vcycle_t(rs_cpr_s *M, hipStream_t s) {
       }
     } else if (l == 0 && L->s7.p) {
       const grid3 &g = M->A->g;
-      k_vc_post7<T><<<rs_grid(L->n), RS_BLOCK, 0, s>>>(L->n, g.nx, (int)g.nxy, L->s7.as<T>(), L->dl1.as<T>(),
+      k_vc_post7<T><<<band_grid(g.nx, g.ny, g.nz), RS_BLOCK, 0, s>>>(L->n, g.nx, (int)g.nxy, L->s7.as<T>(), L->dl1.as<T>(),
                                                        L->agg.as<int32_t>(), L->b.as<T>(), L->y.as<T>(),
                                                        Cl->xp<T>(), L->xp<T>());
     } else {

@@ -216,13 +216,16 @@ def test_ras_strip_shapes(dims, prec):
     (the largest the quad-per-cell strip sweeps take), 225 (one lane per line
     in FP32, one workgroup per layer in FP64), 128, uneven strips (38 + 37
     lines), more layers than CUs (one strip each), four strips, one 16-line
-    strip.  Both sweeps are compared through the CPR apply, twice in a row
-    (the tickets and tags of a second launch)."""
+    strip.  The FP64 factors (one workgroup per layer) are compared bit for
+    bit.  Both sweeps are compared through the CPR apply, twice in a row (the
+    tickets and tags of a second launch)."""
     p = _prob(dims, sigma=1.5)
     A = oracle.assemble(p)
     Mo = oracle.CPR(A, smoother=oracle.SM_RAS)
     B = upload(A)
     Mg = rs.cpr_setup(B, rs.decouple(B, rs.ABF, prec), rs.cpr_opts(smoother=rs.SM_RAS))
+    if prec == 64:
+        assert np.array_equal(rs.cpr_smoother_get(Mg), Mo.dinv2())
     for seed in (9, 10):
         r = np.random.default_rng(seed).standard_normal(4 * A.n)
         z = torch.empty(4 * A.n, dtype=torch.float64, device="cuda")

@@ -56,7 +56,7 @@ __global__ void k_validate(int nx, int ny, int nz, int64_t nnzb, const int32_t *
   int err = 0;
   if (c == 0 && p != 0) err = 1;
   if (c == n - 1 && end != nnzb) err = 1;
-  if (end < p || end > nnzb) err = 1;
+  if (p < 0 || end < p || end > nnzb) err = 1;      // no column index is read outside [0, nnzb)
   for (int s = 0; s < 7; ++s) {
     int64_t q = -1;
     if (slot_in(s, i, j, k, nx, ny, nz)) {

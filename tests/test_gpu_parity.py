@@ -123,6 +123,13 @@ def test_decouple_errors():
     with pytest.raises(rs.RsError) as e:
         rs.bsr_create(2, 2, 1, rp, ci, dev(v.reshape(-1)))
     assert e.value.status == -5
+    # row starts out of range (negative, past nnzb, decreasing): refused
+    # before any column index is read through them
+    for r, val in ((1, -5), (2, -(1 << 30)), (1, 10 ** 6), (3, 1)):
+        badrp = rp.clone(); badrp[r] = val
+        with pytest.raises(rs.RsError) as e:
+            rs.bsr_create(2, 2, 1, badrp, ci, dev(A.v.reshape(-1)))
+        assert e.value.status == -1, (r, val)
 
 
 @pytest.mark.parametrize("dims,sigma", [((20, 20, 10), 1.0), ((33, 17, 9), 2.0), ((40, 40, 20), 2.0)])

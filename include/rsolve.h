@@ -24,6 +24,7 @@
  *   - `stream` is a hipStream_t passed as void* (0 = the null stream).  All
  *     device work is enqueued on it.  Calls that return scalars to the host
  *     (setup status, solve info) synchronise that stream before returning.
+ *   - Grids: nx, ny, nz >= 1 and nx*ny*nz < 2^30 cells (RS_E_ARG otherwise).
  *   - Cell c = i + nx*(j + ny*k), 0-based, i fastest.  Block rows follow the
  *     cell order; in a row the stored columns are ascending:
  *     c-nx*ny, c-nx, c-1, c, c+1, c+nx, c+nx*ny (those inside the grid).

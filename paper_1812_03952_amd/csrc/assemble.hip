@@ -163,7 +163,7 @@ extern "C" rs_status rs_assemble(int nx, int ny, int nz, const double *d_logk, d
                                  const double *d_Mf, const double *d_Mb, const double *d_B, double dt,
                                  int nw, const int32_t *d_wcell, const double *d_wu,
                                  const int32_t *d_row_ptr, double *d_vals, void *stream) {
-  if (nx < 1 || ny < 1 || nz < 1 || nw < 0 || !d_logk || !d_Mf || !d_Mb || !d_B || !d_row_ptr || !d_vals ||
+  if (!rs_grid_dims_ok(nx, ny, nz) || nw < 0 || !d_logk || !d_Mf || !d_Mb || !d_B || !d_row_ptr || !d_vals ||
       (nw > 0 && (!d_wcell || !d_wu)) || !(dt > 0.0))
     return RS_E_ARG;
   int64_t n = (int64_t)nx * ny * nz;
@@ -187,7 +187,7 @@ extern "C" rs_status rs_grad_logk(int nx, int ny, int nz, const double *d_logk, 
                                   const double *d_Mf, const double *d_Mb, int nw, const int32_t *d_wcell,
                                   const double *d_wu, const int32_t *d_row_ptr, const double *d_G,
                                   double *d_g, void *stream) {
-  if (nx < 1 || ny < 1 || nz < 1 || nw < 0 || !d_logk || !d_Mf || !d_Mb || !d_row_ptr || !d_G || !d_g ||
+  if (!rs_grid_dims_ok(nx, ny, nz) || nw < 0 || !d_logk || !d_Mf || !d_Mb || !d_row_ptr || !d_G || !d_g ||
       (nw > 0 && (!d_wcell || !d_wu)))
     return RS_E_ARG;
   int64_t n = (int64_t)nx * ny * nz;

@@ -299,9 +299,9 @@ extern "C" rs_status rs_bsr_create(int nx, int ny, int nz, int bs, int64_t nnzb,
                                    const double *d_vals, void *stream, rs_bsr *out) {
   if (!out) return RS_E_ARG;
   *out = nullptr;
-  if (bs != 4 || nx < 1 || ny < 1 || nz < 1 || !d_row_ptr || !d_col_idx || !d_vals) return RS_E_ARG;
+  if (bs != 4 || !rs_grid_dims_ok(nx, ny, nz) || !d_row_ptr || !d_col_idx || !d_vals) return RS_E_ARG;
   int64_t n = (int64_t)nx * ny * nz;
-  if (n > INT32_MAX / 2 || nnzb != grid_nnzb(nx, ny, nz) || nnzb > INT32_MAX) return RS_E_ARG;
+  if (nnzb != grid_nnzb(nx, ny, nz) || nnzb > INT32_MAX) return RS_E_ARG;
   hipStream_t s = rs_stream(stream);
   rs_bsr_s *A = new rs_bsr_s();
   A->g = {nx, ny, nz, n, (int64_t)nx * ny};
@@ -448,7 +448,7 @@ rs_status rs_from7_host(const rs_bsr_s *A, const void *a7, int prec, double *h_v
 
 extern "C" rs_status rs_pattern(int nx, int ny, int nz, int32_t *d_row_ptr, int32_t *d_col_idx,
                                 int64_t *h_nnzb, void *stream) {
-  if (nx < 1 || ny < 1 || nz < 1 || !d_row_ptr || !d_col_idx) return RS_E_ARG;
+  if (!rs_grid_dims_ok(nx, ny, nz) || !d_row_ptr || !d_col_idx) return RS_E_ARG;
   int64_t n = (int64_t)nx * ny * nz;
   if (grid_nnzb(nx, ny, nz) > INT32_MAX) return RS_E_ARG;
   k_pattern<<<rs_grid(n), RS_BLOCK, 0, rs_stream(stream)>>>(nx, ny, nz, d_row_ptr, d_col_idx);

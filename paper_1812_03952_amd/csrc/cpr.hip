@@ -249,7 +249,8 @@ extern "C" rs_status rs_cpr_setup(rs_bsr A, rs_dcpl D, const rs_cpr_opts *o, voi
       (ras && rs_ras_check_shape(A->g, D->prec) != RS_OK) || opts.coarse_n < 1 ||
       opts.max_levels < 1 || opts.lu_max < 1 || opts.lu_max > 8192 || opts.coarse_sweeps < 1 ||
       (opts.stages != 2 && opts.stages != 3) || (opts.smooth != 0 && opts.smooth != 1) ||
-      !(opts.trunc >= 0.0 && opts.trunc <= 1.0))
+      !(opts.trunc >= 0.0 && opts.trunc <= 1.0) || opts.theta != opts.theta ||
+      opts.max_row_sum != opts.max_row_sum)
     return RS_E_ARG;
   hipStream_t s = rs_stream(stream);
   hipStream_t ss = opts.smoother == RS_SM_DILU ? nullptr : side_stream();

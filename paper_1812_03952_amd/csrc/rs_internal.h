@@ -66,6 +66,15 @@ struct grid3 {
   int64_t n, nxy;
 };
 
+// grid extents the library takes: each at least 1 and at most 2^30 cells in
+// all (cell and block indices stay in int32), the product formed without
+// overflow
+static inline bool rs_grid_dims_ok(int nx, int ny, int nz) {
+  if (nx < 1 || ny < 1 || nz < 1) return false;
+  const int64_t nxy = (int64_t)nx * ny;
+  return nxy <= INT32_MAX / 2 && nxy * nz <= INT32_MAX / 2;
+}
+
 // ---- handles --------------------------------------------------------------
 struct rs_bsr_s {
   grid3 g;

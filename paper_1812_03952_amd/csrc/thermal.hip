@@ -322,7 +322,7 @@ extern "C" rs_status rs_thermal_assemble(int nx, int ny, int nz, const rs_therma
                                          const double *d_uold, int nw, const int32_t *d_wcell,
                                          const int32_t *d_wkind, const double *d_wval, double *d_vals,
                                          double *d_res, void *stream) {
-  if (nx < 1 || ny < 1 || nz < 1 || !q || !d_kx || !d_ky || !d_kz || !d_u || !d_uold || nw < 0 ||
+  if (!rs_grid_dims_ok(nx, ny, nz) || !q || !d_kx || !d_ky || !d_kz || !d_u || !d_uold || nw < 0 ||
       (nw > 0 && (!d_wcell || !d_wkind || !d_wval)) || (!d_vals && !d_res))
     return RS_E_ARG;
   const int64_t n = (int64_t)nx * ny * nz;

@@ -156,28 +156,33 @@ def _ptr(t: torch.Tensor, dtype, n=None):
     return C.c_void_p(t.data_ptr())
 
 
+def _set_fields(o, kw):
+    # a misspelt option would otherwise become a plain Python attribute that
+    # the library never sees
+    names = {f for f, _ in type(o)._fields_}
+    for k, v in kw.items():
+        if k not in names:
+            raise TypeError(f"{type(o).__name__} has no option {k!r} (options: {', '.join(sorted(names))})")
+        setattr(o, k, v)
+    return o
+
+
 def cpr_opts(**kw) -> CprOpts:
     o = CprOpts()
     lib().rs_cpr_opts_default(C.byref(o))
-    for k, v in kw.items():
-        setattr(o, k, v)
-    return o
+    return _set_fields(o, kw)
 
 
 def gmres_opts(**kw) -> GmresOpts:
     o = GmresOpts()
     lib().rs_gmres_opts_default(C.byref(o))
-    for k, v in kw.items():
-        setattr(o, k, v)
-    return o
+    return _set_fields(o, kw)
 
 
 def bicgstab_opts(**kw) -> BicgstabOpts:
     o = BicgstabOpts()
     lib().rs_bicgstab_opts_default(C.byref(o))
-    for k, v in kw.items():
-        setattr(o, k, v)
-    return o
+    return _set_fields(o, kw)
 
 
 # ---------------------------------------------------------------------------

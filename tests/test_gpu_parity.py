@@ -132,6 +132,33 @@ def test_decouple_errors():
         assert e.value.status == -1, (r, val)
 
 
+def test_options_rejected():
+    """Out-of-range options of the set-up and the solvers give RS_E_ARG."""
+    p = _prob((4, 4, 2))
+    A = oracle.assemble(p)
+    B = upload(A)
+    D = rs.decouple(B, rs.ABF, 64)
+    nan = float("nan")
+    for kw in (dict(smoother=7), dict(coarse_n=0), dict(max_levels=0), dict(lu_max=0), dict(lu_max=8193),
+               dict(coarse_sweeps=0), dict(stages=1), dict(stages=4), dict(theta=nan), dict(max_row_sum=nan)):
+        with pytest.raises(rs.RsError) as e:
+            rs.cpr_setup(B, D, rs.cpr_opts(**kw))
+        assert e.value.status == -1, kw
+    M = rs.cpr_setup(B, D, rs.cpr_opts(smoother=rs.SM_RAS))
+    b = dev(np.ones(4 * A.n))
+    x = torch.zeros(4 * A.n, dtype=torch.float64, device="cuda")
+    for kw in (dict(restart=0), dict(restart=33), dict(maxit=-1), dict(rtol=-1.0), dict(rtol=nan)):
+        with pytest.raises(rs.RsError) as e:
+            rs.gmres_solve(B, M, b, x, rs.gmres_opts(**kw))
+        assert e.value.status == -1, kw
+    for kw in (dict(maxit=-1), dict(rtol=nan)):
+        with pytest.raises(rs.RsError) as e:
+            rs.bicgstab_solve(B, M, b, x, rs.bicgstab_opts(**kw))
+        assert e.value.status == -1, kw
+    info = rs.gmres_solve(B, M, b, x, rs.gmres_opts(zero_guess=1))       # the handles still work
+    assert info["return"] == 0
+
+
 @pytest.mark.parametrize("dims,sigma", [((20, 20, 10), 1.0), ((33, 17, 9), 2.0), ((40, 40, 20), 2.0)])
 def test_amg_hierarchy_bitwise(dims, sigma):
     p = _prob(dims, sigma=sigma, shale=0.1 if sigma > 1.5 else 0.0)

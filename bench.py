@@ -170,7 +170,7 @@ def main():
                     help="run one 1 GiB copy kernel (for counter calibration under rocprofv3 --pmc)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py: measures one GPU; --gpus {args.gpus} is not supported "
               "(multi-GPU sharding is design only)", file=sys.stderr)
         sys.exit(2)
 

@@ -1,4 +1,4 @@
-/* asan_check.c -- memory-safety driver for the oracle (test infrastructure).
+/* asan_check.c -- memory-safety check program for the oracle (test infrastructure).
  *
  * Built by the CPU test suite together with the oracle's sources under
  * gcc -fsanitize=address,undefined, it reads one small seeded problem (raw

@@ -4,9 +4,9 @@
  *
  * TEST INFRASTRUCTURE ONLY.  This library exists to check the HIP library
  * against the paper's definitions.  It is called by the test suite, by the
- * graft smoke check and by the CPU-baseline leg of the benchmark, and by
- * nothing else.  It shares no code, header, table or constant generator with
- * the HIP library and must never be linked into it.
+ * smoke check in __graft_entry__.py and by the CPU-baseline leg of the
+ * benchmark, and by nothing else.  It shares no code, header, table or
+ * constant generator with the HIP library and must never be linked into it.
  *
  * Conventions
  *   - Grid cells are numbered c = i + nx*(j + ny*k), 0-based, i fastest

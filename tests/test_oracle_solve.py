@@ -241,7 +241,7 @@ def test_gmres_restart_cycles(restart):
     assert np.linalg.norm(x1 - Z @ y) <= 1e-8 * np.linalg.norm(Z @ y)
 
 
-def test_workload_reading_survey_recipe_stalls():
+def test_workload_without_unit_scaling_and_storage_stalls():
     """The synthetic recipe's two readings (field-unit Darcy constant on the
     transmissibilities, storage on the non-pressure diagonal) are what make
     the Jacobian a CPR target.  Without them (tscale 1, storage 0) random
